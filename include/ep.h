@@ -1,0 +1,240 @@
+/*
+ * ep.h - C ABI of the MI355X elastoplastic Newton hot path.
+ *
+ * Method: Cermak, Sysala, Valdman, "Efficient and flexible MATLAB
+ * implementation of 2D and 3D elastoplastic problems" (arXiv 1805.04155).
+ * One Newton iteration of its semismooth Newton method (Section 4,
+ * ALG-NEWTON) consists of
+ *   - the strain E = B u at every integration point (Section 6.2),
+ *   - the return map T_k and consistent tangent T_k^o (Sections 2.2, 2.3),
+ *   - the compaction of the plastic integration points,
+ *   - the tangent K = K_elast + B^T (D_tangent - D_elast) B (eq. K-split),
+ *   - the internal force F = B^T (WEIGHT .* S) (Section 7),
+ *   - a linear solve for the Newton correction (here Jacobi-PCG).
+ *
+ * Conventions
+ *   - Pointers are DEVICE pointers unless the comment says host.  Device
+ *     buffers passed in are owned by the caller; the library never frees
+ *     them and never keeps them past the call.  Host arrays are copied
+ *     during the call.
+ *   - Indices are 0-based.  dof = dim*node + component (Section 5).
+ *   - Integration point ip = e*n_q + q (element-major, Section 6.1).
+ *   - Per-point arrays are structure-of-arrays: [component][n_int].
+ *   - Voigt order 11,22,33,12,23,13.  Strain-type vectors carry doubled
+ *     shears (engineering strain), stress-type vectors do not (Section 5).
+ *     In plane strain (dim = 2) the strain has the 3 in-plane components
+ *     (11, 22, 12), the stress, plastic strain and back stress have the 4
+ *     components (11, 22, 33, 12), and the tangent is the in-plane 3x3 block.
+ *   - n_str = 6 (3D) or 3 (2D) strain components; n_sc = 6 or 4 stress /
+ *     state components.
+ *   - All device work of a context is enqueued on its stream (the
+ *     hip_stream given to ep_setup or ep_set_stream).  Calls return once the
+ *     work is enqueued, except where a host-visible result is documented.
+ *   - Errors are status codes; ep_last_error gives the context's message.
+ *     A context is not thread-safe.
+ */
+#ifndef EP_H
+#define EP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ep_ctx ep_ctx;
+
+typedef enum {
+  EP_OK = 0,
+  EP_EINVAL = -1,    /* invalid argument or mesh                           */
+  EP_ENOMEM = -2,    /* device or host allocation failed                   */
+  EP_EDEVICE = -3,   /* a HIP runtime call failed                          */
+  EP_ENOTCONV = -4,  /* PCG reached its iteration limit                    */
+  EP_ESTATE = -5     /* call out of order (e.g. assembly before constitutive) */
+} ep_status;
+
+/* Lagrange elements of the paper's Appendix.  EP_P1: 3-node triangle /
+ * 4-node tetrahedron, 1 point.  EP_P2: 10-node tetrahedron, 11-point rule
+ * (3D only).  EP_Q1: 4-node quadrilateral (2x2 Gauss) / 8-node hexahedron
+ * (2x2x2).  EP_Q2: 9-node quadrilateral (3x3) / 27-node hexahedron (3x3x3),
+ * tensor-product Lagrange with the paper's 20 hexahedron nodes first, then
+ * the face centres (-xi3,+xi3,-xi2,+xi1,+xi2,-xi1) and the centre; the
+ * 9-node quadrilateral lists vertices counter-clockwise, edge midpoints
+ * (bottom, right, top, left) and the centre. */
+typedef enum { EP_P1 = 1, EP_P2 = 2, EP_Q1 = 3, EP_Q2 = 4 } ep_elem;
+
+/* EP_VM: von Mises with linear kinematic hardening (Section 2.2; a = 0 is
+ *        perfect plasticity).  State: plastic strain, back stress.
+ * EP_DP: Drucker-Prager (Section 2.3) with yield function
+ *        |dev s|/sqrt(2) + eta*p - (c + a*kappa), p = tr(sigma)/3 and
+ *        associated flow; a = 0 is the paper's perfect plasticity, a > 0
+ *        linear hardening of the cohesion in the accumulated multiplier
+ *        kappa.  State: plastic strain, kappa. */
+typedef enum { EP_VM = 1, EP_DP = 2 } ep_model;
+
+typedef enum { EP_FP64 = 0, EP_FP32 = 1, EP_BF16 = 2 } ep_prec;
+
+typedef struct {
+  int32_t dim;               /* 2 (plane strain) or 3                        */
+  int32_t type;              /* ep_elem                                      */
+  int64_t n_nodes, n_elems;
+  const double *coord;       /* host [dim][n_nodes]                          */
+  const int32_t *elem;       /* host [n_elems][n_p], local order of ep_elem  */
+  const uint8_t *free_mask;  /* host [dim*n_nodes], 1 = free, 0 = Dirichlet  */
+} ep_mesh;
+
+/* Optional quadrature override: same number of points as the built-in rule
+ * of the element (the kernels are specialised on it). */
+typedef struct {
+  int32_t n_q;
+  const double *xi;          /* host [n_q][dim] reference coordinates        */
+  const double *w;           /* host [n_q] weights (sign kept, Section 6.3)  */
+} ep_quadrature;
+
+typedef struct {
+  int32_t model;             /* ep_model                                     */
+  double E, nu;              /* K = E/(3(1-2nu)), G = E/(2(1+nu)) (Sec. 8.1) */
+  double Y;                  /* VM yield level on |dev(sigma) - beta|        */
+  double a;                  /* hardening modulus (VM kinematic, DP cohesion) */
+  double eta, c;             /* DP friction and cohesion parameters          */
+} ep_material;
+
+typedef struct {
+  int32_t tangent_prec;      /* EP_FP64 or EP_FP32: storage of the K values  */
+  int32_t local_prec;        /* EP_FP64 (default) or EP_FP32: element-local
+                                B^T (D - D_e) B products                      */
+  int32_t pcg_max_it;        /* PCG iteration limit per Newton step          */
+  int32_t pcg_check_every;   /* PCG iterations between host checks           */
+  double newton_rtol;        /* |Q(f - F)| <= newton_rtol |Q f|              */
+  double pcg_forcing_max;    /* PCG stops at min(this, res_rel) relative     */
+} ep_options;
+
+typedef struct {
+  int32_t dim, n_p, n_q, n_str, n_sc, n_colours;
+  int64_t n_nodes, n_elems, n_int, n_dof;
+  int64_t nnz;               /* scalar CSR entries of K                      */
+  int64_t nnz_blocks;        /* dim x dim node blocks of K                   */
+} ep_sizes;
+
+typedef struct {
+  double res_rel;            /* |Q(f - F(u))| / |Q f| at the u passed in     */
+  double res_norm, f_norm;
+  double pcg_relres;         /* final relative PCG residual (if solved)      */
+  int32_t pcg_its;
+  int32_t converged;         /* 1: res_rel <= newton_rtol; u left unchanged  */
+  int64_t n_plastic_ip, n_plastic_elem;
+} ep_newton_info;
+
+/* Builds everything that depends only on the mesh (Sections 6.1-6.3):
+ * reference tables, the node-block CSR pattern of K, the element position
+ * map, an element colouring (no two elements of one colour share a node),
+ * the node-to-element map, the geometry check (det J > 0 at every point)
+ * and K_elast = B^T D_elast B.  The plastic state starts at zero.
+ * quadrature and options may be NULL (built-in rule, default options).
+ * On error *out is NULL and ep_last_error(NULL) holds the message.
+ * Synchronises the stream. */
+ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quadrature,
+                   const ep_material *material, const ep_options *options,
+                   void *hip_stream, ep_ctx **out);
+
+/* Releases every allocation of the context.  NULL is accepted. */
+void ep_destroy(ep_ctx *ctx);
+
+/* Message of the last failed call on ctx (ctx = NULL: of the last failed
+ * ep_setup of this thread).  Never NULL. */
+const char *ep_last_error(const ep_ctx *ctx);
+
+ep_status ep_set_stream(ep_ctx *ctx, void *hip_stream);
+ep_status ep_get_sizes(const ep_ctx *ctx, ep_sizes *out /* host */);
+
+/* State from the previous load step (eps^p_{k-1}, beta_{k-1}, kappa_{k-1}),
+ * [n_sc][n_int] and [n_int].  beta is used by EP_VM, kappa by EP_DP; a NULL
+ * pointer sets that array to zero.  ep_get_state copies the state out
+ * (NULL outputs are skipped). */
+ep_status ep_set_state(ep_ctx *ctx, const double *ep, const double *beta,
+                       const double *kappa);
+ep_status ep_get_state(ep_ctx *ctx, double *ep, double *beta, double *kappa);
+
+/* Gradients of the basis functions at every point, dphi[n_int][n_p][dim],
+ * and WEIGHT = |det J| * omega_q, w[n_int] (Section 6.1, eq.
+ * basis_derivative).  The hot kernels recompute these on the fly; this
+ * entry point exposes them for checking.  Either output may be NULL. */
+ep_status ep_geometry(ep_ctx *ctx, double *dphi, double *w);
+
+/* E = B u (Section 6.2): eps[n_str][n_int], engineering strain. */
+ep_status ep_strain(ep_ctx *ctx, const double *u, double *eps);
+
+/* Strain, return map and consistent tangent at every point for the
+ * displacement u[n_dof], against the stored state (eqs. T_kinematic,
+ * DT_kinematic; Section 2.3), followed by the element force vectors used by
+ * ep_internal_force and the plastic-element bitmask used by
+ * ep_assemble_tangent.  Optional outputs (NULL = skipped): sig[n_sc][n_int],
+ * D[n_str*n_str][n_int] (row-major Voigt tangent, strain-type to
+ * stress-type), flag[n_int] (0 elastic, 1 plastic / smooth cone, 2 apex). */
+ep_status ep_constitutive(ep_ctx *ctx, const double *u, double *sig, double *D,
+                          uint8_t *flag);
+
+/* K_tangent = K_elast + B^T (D_tangent - D_elast) B (eq. K-split) for the
+ * last ep_constitutive: compaction of the plastic elements (grouped by
+ * colour), restore of the blocks touched by the previous assembly, and the
+ * element-local products over plastic points scattered through the
+ * position map, one colour at a time (deterministic, no float atomics).
+ * Returns EP_ESTATE if ep_constitutive has not run since setup or commit. */
+ep_status ep_assemble_tangent(ep_ctx *ctx);
+
+/* F = B^T (WEIGHT .* S) (Section 7) for the last ep_constitutive,
+ * F[n_dof].  Deterministic node gather of the element vectors. */
+ep_status ep_internal_force(ep_ctx *ctx, double *F);
+
+/* One iteration of ALG-NEWTON for the load vector f[n_dof] on the
+ * displacement u[n_dof] (updated in place on free dofs; Dirichlet values of
+ * u are kept).  Computes the residual r = Q(f - F(u)); if |r| <= newton_rtol
+ * |Q f| it sets info->converged = 1 and leaves u unchanged; otherwise it
+ * assembles K_tangent, solves K du = r on the free dofs by Jacobi-PCG to
+ * the relative tolerance min(pcg_forcing_max, res_rel) and adds du to u.
+ * Writes info (host).  Synchronises the stream.  EP_ENOTCONV if PCG hits
+ * its limit (u is still updated with the last iterate). */
+ep_status ep_newton_step(ep_ctx *ctx, const double *f, double *u,
+                         ep_newton_info *info);
+
+/* Accepts the load step: recomputes the return map at u and stores the
+ * updated plastic strain, back stress and kappa (eq. T_other; Section 2.3)
+ * as the state of the next step. */
+ep_status ep_commit_step(ep_ctx *ctx, const double *u);
+
+/* Plastic points of the last ep_constitutive, ascending:
+ * ip[n_int] (capacity), elem[n_elems] (capacity); counts written to the
+ * host pointers.  Any output may be NULL.  Synchronises the stream. */
+ep_status ep_get_plastic(ep_ctx *ctx, int32_t *ip, int64_t *n_ip, int32_t *elem,
+                         int64_t *n_elem);
+
+/* Scalar CSR view of K (which = 0: K_elast, 1: K_tangent):
+ * row_ptr[n_dof+1], col_idx[nnz] (ascending in each row), val[nnz]
+ * (converted to double).  Any output may be NULL. */
+ep_status ep_get_csr(ep_ctx *ctx, int32_t which, int32_t *row_ptr, int32_t *col_idx,
+                     double *val);
+
+/* Scalar position map pos[n_elems][dim*n_p][dim*n_p]: index in col_idx of
+ * the entry (dof(e,a), dof(e,b)), local dof a = dim*p + i. */
+ep_status ep_get_position_map(ep_ctx *ctx, int32_t *pos);
+
+/* y = Q (K_tangent (Q x)) on free dofs, y = 0 on Dirichlet dofs. */
+ep_status ep_spmv(ep_ctx *ctx, const double *x, double *y);
+
+/* Solves Q K_tangent Q x = Q b by Jacobi-PCG from x = 0 to
+ * |r| <= rtol |Q b|.  its and relres are host outputs.  Synchronises. */
+ep_status ep_pcg(ep_ctx *ctx, const double *b, double *x, double rtol, int32_t max_it,
+                 int32_t *its, double *relres);
+
+/* Per-kernel timing with HIP events recorded on the context's stream
+ * around every launch of the named kernels.  ep_profile_read returns the
+ * summed duration (ms) and the launch count of kernel id k (0 constitutive,
+ * 1 compaction, 2 restore, 3 colour assembly, 4 force gather, 5 SpMV,
+ * 6 PCG vector update) and resets it.  Synchronises. */
+ep_status ep_profile(ep_ctx *ctx, int32_t enable);
+ep_status ep_profile_read(ep_ctx *ctx, int32_t k, double *ms, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EP_H */

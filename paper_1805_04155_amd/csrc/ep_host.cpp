@@ -1,0 +1,877 @@
+// Host part of the MI355X elastoplastic hot-path library: reference tables,
+// sparsity structures, element colouring, device memory, and the C ABI of
+// include/ep.h.
+//
+// Method: Cermak, Sysala, Valdman (arXiv 1805.04155).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <thread>
+#include <vector>
+
+#include "ep_internal.h"
+
+using namespace ep;
+
+namespace ep {
+hipError_t launch_pcg_beta_init(Ctx &c, double rtol);
+}
+
+namespace {
+
+thread_local std::string g_setup_err;
+
+#define HIPC(x)                                                               \
+  do {                                                                        \
+    hipError_t e__ = (x);                                                     \
+    if (e__ != hipSuccess) {                                                  \
+      c->err = std::string(#x) + " failed: " + hipGetErrorString(e__);       \
+      return EP_EDEVICE;                                                      \
+    }                                                                         \
+  } while (0)
+
+#define CHECK_CTX(c)                        \
+  do {                                      \
+    if (!(c)) return EP_EINVAL;             \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Reference elements (Appendix) and quadrature
+// ---------------------------------------------------------------------------
+struct ElemDef {
+  int id, dim, n_p, n_q;
+};
+
+bool elem_def(int dim, int type, ElemDef &d) {
+  if (dim == 2 && type == EP_P1) d = {ET_P1_2D, 2, 3, 1};
+  else if (dim == 2 && type == EP_Q1) d = {ET_Q1_2D, 2, 4, 4};
+  else if (dim == 2 && type == EP_Q2) d = {ET_Q2_2D, 2, 9, 9};
+  else if (dim == 3 && type == EP_P1) d = {ET_P1_3D, 3, 4, 1};
+  else if (dim == 3 && type == EP_P2) d = {ET_P2_3D, 3, 10, 11};
+  else if (dim == 3 && type == EP_Q1) d = {ET_Q1_3D, 3, 8, 8};
+  else if (dim == 3 && type == EP_Q2) d = {ET_Q2_3D, 3, 27, 27};
+  else return false;
+  return true;
+}
+
+// Local coordinates of tensor-product nodes: value in {-1, 0, 1} per axis.
+const int kQuad4[4][2] = {{-1, -1}, {1, -1}, {1, 1}, {-1, 1}};
+const int kQuad9[9][2] = {{-1, -1}, {1, -1}, {1, 1}, {-1, 1}, {0, -1},
+                          {1, 0},   {0, 1},  {-1, 0}, {0, 0}};
+const int kHex27[27][3] = {
+    {-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {1, 1, 1},
+    {-1, 1, 1},   {0, -1, -1}, {1, 0, -1}, {0, 1, -1},  {-1, 0, -1}, {0, -1, 1}, {1, 0, 1},
+    {0, 1, 1},    {-1, 0, 1},  {-1, -1, 0}, {1, -1, 0}, {1, 1, 0},   {-1, 1, 0}, {0, 0, -1},
+    {0, 0, 1},    {0, -1, 0},  {1, 0, 0},  {0, 1, 0},   {-1, 0, 0},  {0, 0, 0}};
+// P2 tetrahedron edges (paper's nodes 5..10)
+const int kTetEdge[6][2] = {{0, 1}, {1, 2}, {0, 2}, {1, 3}, {2, 3}, {0, 3}};
+
+// 1D Lagrange basis and derivative: linear on {-1, 1}, quadratic on {-1, 0, 1}.
+void lag1d(int order, int node, double t, double &v, double &dv) {
+  if (order == 1) {
+    v = 0.5 * (1.0 + node * t);
+    dv = 0.5 * node;
+    return;
+  }
+  switch (node) {
+    case -1: v = 0.5 * t * (t - 1.0); dv = t - 0.5; break;
+    case 0: v = (1.0 - t) * (1.0 + t); dv = -2.0 * t; break;
+    default: v = 0.5 * t * (t + 1.0); dv = t + 0.5; break;
+  }
+}
+
+// Reference gradients g[p*dim + i] = d phi_p / d xi_i at xi.
+void ref_gradients(int id, const double *xi, double *g) {
+  switch (id) {
+    case ET_P1_2D: {
+      const double G[6] = {-1, -1, 1, 0, 0, 1};
+      std::copy(G, G + 6, g);
+      return;
+    }
+    case ET_P1_3D: {
+      const double G[12] = {-1, -1, -1, 1, 0, 0, 0, 1, 0, 0, 0, 1};
+      std::copy(G, G + 12, g);
+      return;
+    }
+    case ET_P2_3D: {
+      const double lam[4] = {1.0 - xi[0] - xi[1] - xi[2], xi[0], xi[1], xi[2]};
+      const double dl[4][3] = {{-1, -1, -1}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+      for (int k = 0; k < 4; ++k)
+        for (int i = 0; i < 3; ++i) g[3 * k + i] = (4.0 * lam[k] - 1.0) * dl[k][i];
+      for (int k = 0; k < 6; ++k) {
+        const int a = kTetEdge[k][0], b = kTetEdge[k][1];
+        for (int i = 0; i < 3; ++i) g[3 * (4 + k) + i] = 4.0 * (dl[a][i] * lam[b] + lam[a] * dl[b][i]);
+      }
+      return;
+    }
+    default: break;
+  }
+  // tensor-product elements
+  int dim, n_p, order;
+  const int *nodes;
+  if (id == ET_Q1_2D) { dim = 2; n_p = 4; order = 1; nodes = &kQuad4[0][0]; }
+  else if (id == ET_Q2_2D) { dim = 2; n_p = 9; order = 2; nodes = &kQuad9[0][0]; }
+  else if (id == ET_Q1_3D) { dim = 3; n_p = 8; order = 1; nodes = &kHex27[0][0]; }
+  else { dim = 3; n_p = 27; order = 2; nodes = &kHex27[0][0]; }
+  for (int p = 0; p < n_p; ++p) {
+    double v[3], dv[3];
+    for (int a = 0; a < dim; ++a) lag1d(order, nodes[p * dim + a], xi[a], v[a], dv[a]);
+    for (int i = 0; i < dim; ++i) {
+      double s = 1.0;
+      for (int a = 0; a < dim; ++a) s *= (a == i) ? dv[a] : v[a];
+      g[p * dim + i] = s;
+    }
+  }
+}
+
+void builtin_rule(int id, int dim, std::vector<double> &xi, std::vector<double> &w) {
+  xi.clear();
+  w.clear();
+  if (id == ET_P1_2D) { xi = {1.0 / 3, 1.0 / 3}; w = {0.5}; return; }
+  if (id == ET_P1_3D) { xi = {0.25, 0.25, 0.25}; w = {1.0 / 6}; return; }
+  if (id == ET_P2_3D) {
+    // Keast's 11-point rule (degree 4) with the exact values of the table
+    const double a = 1.0 / 14, b = 11.0 / 14, s = std::sqrt(5.0 / 14);
+    const double c = 0.25 * (1 + s), d = 0.25 * (1 - s);
+    xi = {0.25, 0.25, 0.25, a, a, a, b, a, a, a, b, a, a, a, b,
+          c, d, d, d, c, d, d, d, c, c, c, d, c, d, c, d, c, c};
+    w = {-74.0 / 5625};
+    for (int k = 0; k < 4; ++k) w.push_back(343.0 / 45000);
+    for (int k = 0; k < 6; ++k) w.push_back(56.0 / 2250);
+    return;
+  }
+  const bool two = (id == ET_Q1_2D || id == ET_Q1_3D);
+  std::vector<double> x1, w1;
+  if (two) { x1 = {-1 / std::sqrt(3.0), 1 / std::sqrt(3.0)}; w1 = {1, 1}; }
+  else { x1 = {-std::sqrt(0.6), 0.0, std::sqrt(0.6)}; w1 = {5.0 / 9, 8.0 / 9, 5.0 / 9}; }
+  const int m = (int)x1.size();
+  const int nz = dim == 3 ? m : 1;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < m; ++i) {
+        xi.push_back(x1[i]);
+        xi.push_back(x1[j]);
+        if (dim == 3) xi.push_back(x1[k]);
+        w.push_back(w1[i] * w1[j] * (dim == 3 ? w1[k] : 1.0));
+      }
+}
+
+template <class F>
+void parallel_for(int64_t n, F f) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 4096) nt = 1;
+  std::vector<std::thread> th;
+  const int64_t chunk = (n + nt - 1) / nt;
+  for (unsigned t = 0; t < nt; ++t) {
+    const int64_t a = t * chunk, b = std::min(n, a + chunk);
+    if (a >= b) break;
+    th.emplace_back([=] { f(a, b); });
+  }
+  for (auto &x : th) x.join();
+}
+
+template <class T>
+hipError_t dalloc(T **p, int64_t n) {
+  *p = nullptr;
+  if (n <= 0) n = 1;
+  return hipMalloc((void **)p, sizeof(T) * (size_t)n);
+}
+
+template <class T>
+hipError_t upload(T *d, const std::vector<T> &h, hipStream_t s) {
+  if (h.empty()) return hipSuccess;
+  return hipMemcpyAsync(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, s);
+}
+
+void free_ctx(Ctx *c) {
+  if (!c) return;
+  void *ptrs[] = {c->coord, c->elem, c->freem, c->ref, c->bptr, c->bcol, c->bdiag, c->bpos,
+                  c->Ke, c->Ke32, c->Kt, c->epoch, c->n2e_ptr, c->n2e, c->ecol_perm,
+                  c->d_colour_first_block, c->ep_s, c->beta_s, c->kappa_s, c->flag, c->desc,
+                  c->Fe, c->emask, c->plist[0], c->plist[1], c->coff[0], c->coff[1], c->ptotals,
+                  c->cmp_counts, c->cmp_counts2, c->cmp_offsets, c->F, c->r, c->partials,
+                  c->norms, c->pz, c->pp[0], c->pp[1], c->pq, c->px, c->dinv, c->sc,
+                  c->iscratch};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->norms_h) (void)hipHostFree(c->norms_h);
+  if (c->sc_h) (void)hipHostFree(c->sc_h);
+  for (auto &pd : c->pending) {
+    (void)hipEventDestroy(pd.a);
+    (void)hipEventDestroy(pd.b);
+  }
+  for (auto ev : c->event_pool) (void)hipEventDestroy(ev);
+  delete c;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// profiling
+// ---------------------------------------------------------------------------
+int Ctx::prof_begin(int id) {
+  if (!prof) return -1;
+  hipEvent_t a, b;
+  if (event_pool.size() >= 2) {
+    a = event_pool.back();
+    event_pool.pop_back();
+    b = event_pool.back();
+    event_pool.pop_back();
+  } else {
+    if (hipEventCreate(&a) != hipSuccess) return -1;
+    if (hipEventCreate(&b) != hipSuccess) return -1;
+  }
+  (void)hipEventRecord(a, stream);
+  pending.push_back({id, a, b});
+  return (int)pending.size() - 1;
+}
+
+void Ctx::prof_end(int token) {
+  if (token < 0) return;
+  (void)hipEventRecord(pending[token].b, stream);
+}
+
+void Ctx::prof_collect() {
+  if (pending.empty()) return;
+  (void)hipStreamSynchronize(stream);
+  for (auto &pd : pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pd.a, pd.b) == hipSuccess) {
+      prof_ms[pd.id] += ms;
+      prof_n[pd.id] += 1;
+    }
+    event_pool.push_back(pd.a);
+    event_pool.push_back(pd.b);
+  }
+  pending.clear();
+}
+
+// ---------------------------------------------------------------------------
+// internal steps
+// ---------------------------------------------------------------------------
+namespace {
+
+ep_status do_constitutive(Ctx *c, const double *u, double *sig, double *D, uint8_t *flag) {
+  ConstArgs a{};
+  a.u = u;
+  a.return_map = true;
+  a.sig_out = sig;
+  a.D_out = D;
+  a.flag_out = flag;
+  a.commit = false;
+  a.force = true;
+  int tok = c->prof_begin(PROF_CONST);
+  HIPC(launch_constitutive(*c, a));
+  c->prof_end(tok);
+  // plastic elements grouped by colour, into the buffer not used by the last
+  // assembly
+  const int nb = c->asm_buf == 0 ? 1 : 0;
+  tok = c->prof_begin(PROF_COMPACT);
+  HIPC(launch_compact(*c, 1, c->emask, c->ecol_perm, c->n_perm, c->plist[nb],
+                      c->d_colour_first_block, c->n_col, c->coff[nb], c->ptotals, nullptr));
+  c->prof_end(tok);
+  c->cur = nb;
+  c->have_const = true;
+  return EP_OK;
+}
+
+ep_status do_assemble(Ctx *c) {
+  if (!c->have_const) {
+    c->err = "ep_assemble_tangent: no constitutive evaluation since setup or commit";
+    return EP_ESTATE;
+  }
+  if (c->have_prev) {
+    const int tok = c->prof_begin(PROF_RESTORE);
+    HIPC(launch_restore(*c));
+    c->prof_end(tok);
+  }
+  const int epoch = ++c->epoch_counter;
+  for (int col = 0; col < c->n_col; ++col) {
+    const int tok = c->prof_begin(PROF_ASSEMBLE);
+    HIPC(launch_colour_assembly(*c, col, epoch));
+    c->prof_end(tok);
+  }
+  c->have_prev = true;
+  c->asm_buf = c->cur;
+  return EP_OK;
+}
+
+// residual r = Q(f - F), norms -> c->norms[0] = |r|^2, [1] = |Qf|^2
+ep_status do_residual(Ctx *c, const double *f, double *F_out) {
+  const int nblk = (int)((c->n_n + 255) / 256);
+  const int tok = c->prof_begin(PROF_FORCE);
+  HIPC(launch_force_gather(*c, f, F_out, c->r, c->partials, nblk));
+  c->prof_end(tok);
+  HIPC(launch_reduce(*c, c->partials, nblk, 2, c->norms));
+  return EP_OK;
+}
+
+ep_status do_pcg(Ctx *c, const double *b, double *x, double rtol, int max_it, int *its,
+                 double *relres) {
+  HIPC(launch_diag_inv(*c));
+  HIPC(launch_pcg_init(*c, b, x));
+  HIPC(launch_pcg_beta_init(*c, rtol));
+  const int chunk = std::max(1, c->opt.pcg_check_every);
+  int done_its = 0;
+  bool done = false;
+  while (!done) {
+    const int n = std::min(chunk, max_it - done_its);
+    if (n <= 0) break;
+    for (int k = 0; k < n; ++k) HIPC(launch_pcg_iteration(*c, x));
+    done_its += n;
+    HIPC(hipMemcpyAsync(c->sc_h, c->sc, 16 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPC(hipStreamSynchronize(c->stream));
+    done = c->sc_h[4] != 0.0;
+  }
+  *its = (int)c->sc_h[5];
+  *relres = c->sc_h[8] > 0 ? std::sqrt(c->sc_h[2] / c->sc_h[8]) : 0.0;
+  if (!done) {
+    c->err = "PCG reached its iteration limit";
+    return EP_ENOTCONV;
+  }
+  return EP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *ep_last_error(const ep_ctx *ctx) {
+  if (!ctx) return g_setup_err.c_str();
+  return reinterpret_cast<const Ctx *>(ctx)->err.c_str();
+}
+
+void ep_destroy(ep_ctx *ctx) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (c && c->stream) (void)hipStreamSynchronize(c->stream);
+  free_ctx(c);
+}
+
+ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_material *mat,
+                   const ep_options *opt_in, void *hip_stream, ep_ctx **out) {
+  if (out) *out = nullptr;
+  auto fail = [](const std::string &m, ep_status s) {
+    g_setup_err = m;
+    return s;
+  };
+  if (!mesh || !mat || !out) return fail("ep_setup: NULL argument", EP_EINVAL);
+  ElemDef ed;
+  if (!elem_def(mesh->dim, mesh->type, ed)) return fail("ep_setup: unsupported element", EP_EINVAL);
+  if (mesh->n_nodes <= 0 || mesh->n_elems < 0 || !mesh->coord || !mesh->elem || !mesh->free_mask)
+    return fail("ep_setup: invalid mesh arrays", EP_EINVAL);
+  if ((int64_t)mesh->dim * mesh->n_nodes >= (int64_t)1 << 31 ||
+      mesh->n_elems * ed.n_p * ed.n_p >= (int64_t)1 << 31)
+    return fail("ep_setup: mesh too large for 32-bit indices", EP_EINVAL);
+  if (!(mat->E > 0) || !(mat->nu >= 0 && mat->nu < 0.5))
+    return fail("ep_setup: need E > 0 and 0 <= nu < 0.5", EP_EINVAL);
+  if (mat->model == EP_VM) {
+    if (!(mat->Y > 0) || !(mat->a >= 0)) return fail("ep_setup: von Mises needs Y > 0, a >= 0", EP_EINVAL);
+  } else if (mat->model == EP_DP) {
+    if (!(mat->eta > 0) || !(mat->c > 0) || !(mat->a >= 0))
+      return fail("ep_setup: Drucker-Prager needs eta > 0, c > 0, a >= 0", EP_EINVAL);
+  } else {
+    return fail("ep_setup: unknown model", EP_EINVAL);
+  }
+  const int64_t n_n = mesh->n_nodes, n_e = mesh->n_elems;
+  const int dim = ed.dim, n_p = ed.n_p, n_q = ed.n_q;
+  for (int64_t i = 0; i < n_e * n_p; ++i)
+    if (mesh->elem[i] < 0 || mesh->elem[i] >= n_n)
+      return fail("ep_setup: node id out of range in elem", EP_EINVAL);
+
+  ep_options opt{EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2};
+  if (opt_in) opt = *opt_in;
+  if (opt.tangent_prec != EP_FP64 && opt.tangent_prec != EP_FP32)
+    return fail("ep_setup: tangent_prec must be EP_FP64 or EP_FP32", EP_EINVAL);
+  if (opt.local_prec != EP_FP64)
+    return fail("ep_setup: local_prec other than EP_FP64 is not available", EP_EINVAL);
+  if (opt.pcg_max_it <= 0) opt.pcg_max_it = 20000;
+  if (opt.pcg_check_every <= 0) opt.pcg_check_every = 50;
+
+  // reference tables
+  std::vector<double> xi, wq;
+  if (quad) {
+    if (quad->n_q != n_q || !quad->xi || !quad->w)
+      return fail("ep_setup: quadrature must have the element's number of points", EP_EINVAL);
+    xi.assign(quad->xi, quad->xi + n_q * dim);
+    wq.assign(quad->w, quad->w + n_q);
+  } else {
+    builtin_rule(ed.id, dim, xi, wq);
+  }
+  std::vector<double> ref((size_t)n_q * n_p * dim + n_q);
+  for (int q = 0; q < n_q; ++q) ref_gradients(ed.id, &xi[q * dim], &ref[(size_t)q * n_p * dim]);
+  for (int q = 0; q < n_q; ++q) ref[(size_t)n_q * n_p * dim + q] = wq[q];
+
+  Ctx *c = new Ctx();
+  c->stream = (hipStream_t)hip_stream;
+  (void)hipGetDevice(&c->dev);
+  c->et = ed.id;
+  c->dim = dim;
+  c->n_p = n_p;
+  c->n_q = n_q;
+  c->n_str = dim == 3 ? 6 : 3;
+  c->n_sc = dim == 3 ? 6 : 4;
+  c->n_desc = dim == 3 ? 10 : 7;
+  c->n_n = n_n;
+  c->n_e = n_e;
+  c->n_int = n_e * n_q;
+  c->n_dof = dim * n_n;
+  c->opt = opt;
+  c->mat.model = mat->model;
+  c->mat.G = mat->E / (2.0 * (1.0 + mat->nu));
+  c->mat.K = mat->E / (3.0 * (1.0 - 2.0 * mat->nu));
+  c->mat.a = mat->a;
+  c->mat.Y = mat->Y;
+  c->mat.eta = mat->eta;
+  c->mat.c = mat->c;
+
+  auto bail = [&](ep_status s) {
+    g_setup_err = c->err;
+    free_ctx(c);
+    return s;
+  };
+#define SETUP_HIP(x)                                                         \
+  do {                                                                       \
+    hipError_t e__ = (x);                                                    \
+    if (e__ != hipSuccess) {                                                 \
+      c->err = std::string("ep_setup: ") + #x + ": " + hipGetErrorString(e__); \
+      return bail(e__ == hipErrorOutOfMemory ? EP_ENOMEM : EP_EDEVICE);      \
+    }                                                                        \
+  } while (0)
+
+  const int32_t *E = mesh->elem;
+  // node -> (element, local node), ascending element
+  std::vector<int32_t> n2e_ptr(n_n + 1, 0), n2e(n_e * n_p);
+  for (int64_t i = 0; i < n_e * n_p; ++i) n2e_ptr[E[i] + 1]++;
+  for (int64_t m = 0; m < n_n; ++m) n2e_ptr[m + 1] += n2e_ptr[m];
+  {
+    std::vector<int32_t> fill(n2e_ptr.begin(), n2e_ptr.end() - 1);
+    for (int64_t e = 0; e < n_e; ++e)
+      for (int p = 0; p < n_p; ++p) n2e[fill[E[e * n_p + p]]++] = (int32_t)(e * n_p + p);
+  }
+  // node adjacency -> node-block CSR
+  std::vector<int32_t> deg(n_n, 0);
+  auto neighbours = [&](int64_t m, std::vector<int32_t> &mark, std::vector<int32_t> &lst) {
+    lst.clear();
+    for (int k = n2e_ptr[m]; k < n2e_ptr[m + 1]; ++k) {
+      const int64_t e = n2e[k] / n_p;
+      for (int p = 0; p < n_p; ++p) {
+        const int32_t v = E[e * n_p + p];
+        if (mark[v] != (int32_t)m) {
+          mark[v] = (int32_t)m;
+          lst.push_back(v);
+        }
+      }
+    }
+    std::sort(lst.begin(), lst.end());
+  };
+  parallel_for(n_n, [&](int64_t a, int64_t b) {
+    std::vector<int32_t> mark(n_n, -1), lst;
+    for (int64_t m = a; m < b; ++m) {
+      neighbours(m, mark, lst);
+      deg[m] = (int32_t)lst.size();
+    }
+  });
+  std::vector<int32_t> bptr(n_n + 1, 0);
+  for (int64_t m = 0; m < n_n; ++m) bptr[m + 1] = bptr[m] + deg[m];
+  const int64_t nnzb = bptr[n_n];
+  if (nnzb * dim * dim >= (int64_t)1 << 31) {
+    c->err = "ep_setup: matrix too large for 32-bit indices";
+    return bail(EP_EINVAL);
+  }
+  c->nnzb = nnzb;
+  std::vector<int32_t> bcol(nnzb), bdiag(n_n);
+  parallel_for(n_n, [&](int64_t a, int64_t b) {
+    std::vector<int32_t> mark(n_n, -1), lst;
+    for (int64_t m = a; m < b; ++m) {
+      neighbours(m, mark, lst);
+      std::copy(lst.begin(), lst.end(), bcol.begin() + bptr[m]);
+      bdiag[m] = (int32_t)(bptr[m] + (std::lower_bound(lst.begin(), lst.end(), (int32_t)m) - lst.begin()));
+    }
+  });
+  // element position map of node pairs
+  std::vector<int32_t> bpos((size_t)n_e * n_p * n_p);
+  parallel_for(n_e, [&](int64_t a, int64_t b) {
+    for (int64_t e = a; e < b; ++e)
+      for (int p = 0; p < n_p; ++p) {
+        const int32_t m = E[e * n_p + p];
+        const int32_t *lo = bcol.data() + bptr[m], *hi = bcol.data() + bptr[m + 1];
+        for (int pp = 0; pp < n_p; ++pp) {
+          const int32_t *it = std::lower_bound(lo, hi, E[e * n_p + pp]);
+          bpos[(e * n_p + p) * n_p + pp] = (int32_t)(it - bcol.data());
+        }
+      }
+  });
+  // greedy colouring: elements of one colour share no node
+  std::vector<int32_t> colour(n_e, -1);
+  int n_col = 0;
+  {
+    std::vector<uint64_t> used(8);
+    for (int64_t e = 0; e < n_e; ++e) {
+      std::fill(used.begin(), used.end(), 0);
+      for (int p = 0; p < n_p; ++p) {
+        const int32_t m = E[e * n_p + p];
+        for (int k = n2e_ptr[m]; k < n2e_ptr[m + 1]; ++k) {
+          const int64_t e2 = n2e[k] / n_p;
+          if (e2 < e) {
+            const int cc = colour[e2];
+            used[cc >> 6] |= 1ull << (cc & 63);
+          }
+        }
+      }
+      int cc = 0;
+      while (cc < 512 && ((used[cc >> 6] >> (cc & 63)) & 1ull)) ++cc;
+      if (cc >= 512) {
+        c->err = "ep_setup: colouring needs more than 512 colours";
+        return bail(EP_EINVAL);
+      }
+      colour[e] = cc;
+      n_col = std::max(n_col, cc + 1);
+    }
+  }
+  c->n_col = n_col;
+  c->colour_size.assign(n_col, 0);
+  for (int64_t e = 0; e < n_e; ++e) c->colour_size[colour[e]]++;
+  c->colour_first_block.assign(n_col + 1, 0);
+  for (int col = 0; col < n_col; ++col)
+    c->colour_first_block[col + 1] =
+        c->colour_first_block[col] + (int32_t)((c->colour_size[col] + CMP_CHUNK - 1) / CMP_CHUNK);
+  c->n_perm = (int64_t)c->colour_first_block[n_col] * CMP_CHUNK;
+  std::vector<int32_t> perm(std::max<int64_t>(c->n_perm, 1), -1);
+  {
+    std::vector<int64_t> fill(n_col);
+    for (int col = 0; col < n_col; ++col) fill[col] = (int64_t)c->colour_first_block[col] * CMP_CHUNK;
+    for (int64_t e = 0; e < n_e; ++e) perm[fill[colour[e]]++] = (int32_t)e;
+  }
+
+  // device memory
+  hipStream_t s = c->stream;
+  const int64_t n_int = c->n_int, n_dof = c->n_dof;
+  SETUP_HIP(dalloc(&c->coord, dim * n_n));
+  SETUP_HIP(dalloc(&c->elem, n_e * n_p));
+  SETUP_HIP(dalloc(&c->freem, n_dof));
+  SETUP_HIP(dalloc(&c->ref, (int64_t)ref.size()));
+  SETUP_HIP(dalloc(&c->bptr, n_n + 1));
+  SETUP_HIP(dalloc(&c->bcol, nnzb));
+  SETUP_HIP(dalloc(&c->bdiag, n_n));
+  SETUP_HIP(dalloc(&c->bpos, n_e * n_p * n_p));
+  SETUP_HIP(dalloc(&c->Ke, nnzb * dim * dim));
+  if (opt.tangent_prec == EP_FP32) {
+    SETUP_HIP(dalloc(&c->Ke32, nnzb * dim * dim));
+    SETUP_HIP(hipMalloc(&c->Kt, sizeof(float) * std::max<int64_t>(1, nnzb * dim * dim)));
+  } else {
+    SETUP_HIP(hipMalloc(&c->Kt, sizeof(double) * std::max<int64_t>(1, nnzb * dim * dim)));
+  }
+  SETUP_HIP(dalloc(&c->epoch, nnzb));
+  SETUP_HIP(dalloc(&c->n2e_ptr, n_n + 1));
+  SETUP_HIP(dalloc(&c->n2e, n_e * n_p));
+  SETUP_HIP(dalloc(&c->ecol_perm, (int64_t)perm.size()));
+  SETUP_HIP(dalloc(&c->d_colour_first_block, n_col + 1));
+  SETUP_HIP(dalloc(&c->ep_s, c->n_sc * n_int));
+  if (mat->model == EP_VM) SETUP_HIP(dalloc(&c->beta_s, c->n_sc * n_int));
+  SETUP_HIP(dalloc(&c->kappa_s, n_int));
+  SETUP_HIP(dalloc(&c->flag, n_int));
+  SETUP_HIP(dalloc(&c->desc, c->n_desc * n_int));
+  SETUP_HIP(dalloc(&c->Fe, n_e * n_p * dim));
+  SETUP_HIP(dalloc(&c->emask, n_e));
+  for (int k = 0; k < 2; ++k) {
+    SETUP_HIP(dalloc(&c->plist[k], n_e));
+    SETUP_HIP(dalloc(&c->coff[k], n_col + 1));
+  }
+  SETUP_HIP(dalloc(&c->ptotals, 4));
+  SETUP_HIP(dalloc(&c->iscratch, std::max(n_int, n_e)));
+  c->cmp_cap = std::max<int64_t>((n_int + CMP_CHUNK - 1) / CMP_CHUNK, c->n_perm / CMP_CHUNK) + 2;
+  c->cmp_cap = std::max<int64_t>(c->cmp_cap, (n_e + CMP_CHUNK - 1) / CMP_CHUNK + 2);
+  SETUP_HIP(dalloc(&c->cmp_counts, c->cmp_cap));
+  SETUP_HIP(dalloc(&c->cmp_counts2, c->cmp_cap));
+  SETUP_HIP(dalloc(&c->cmp_offsets, c->cmp_cap + 1));
+  SETUP_HIP(dalloc(&c->F, n_dof));
+  SETUP_HIP(dalloc(&c->r, n_dof));
+  c->partials_cap = 2 * ((n_dof + 255) / 256) + 64;
+  SETUP_HIP(dalloc(&c->partials, c->partials_cap));
+  SETUP_HIP(dalloc(&c->norms, 16));
+  SETUP_HIP(hipHostMalloc((void **)&c->norms_h, 16 * sizeof(double), hipHostMallocDefault));
+  SETUP_HIP(dalloc(&c->pz, n_dof));
+  SETUP_HIP(dalloc(&c->pp[0], n_dof));
+  SETUP_HIP(dalloc(&c->pp[1], n_dof));
+  SETUP_HIP(dalloc(&c->pq, n_dof));
+  SETUP_HIP(dalloc(&c->px, n_dof));
+  SETUP_HIP(dalloc(&c->dinv, n_dof));
+  SETUP_HIP(dalloc(&c->sc, 16));
+  SETUP_HIP(hipHostMalloc((void **)&c->sc_h, 16 * sizeof(double), hipHostMallocDefault));
+
+  SETUP_HIP(hipMemcpyAsync(c->coord, mesh->coord, sizeof(double) * dim * n_n, hipMemcpyHostToDevice, s));
+  if (n_e > 0)
+    SETUP_HIP(hipMemcpyAsync(c->elem, E, sizeof(int32_t) * n_e * n_p, hipMemcpyHostToDevice, s));
+  SETUP_HIP(hipMemcpyAsync(c->freem, mesh->free_mask, n_dof, hipMemcpyHostToDevice, s));
+  SETUP_HIP(upload(c->ref, ref, s));
+  SETUP_HIP(upload(c->bptr, bptr, s));
+  SETUP_HIP(upload(c->bcol, bcol, s));
+  SETUP_HIP(upload(c->bdiag, bdiag, s));
+  SETUP_HIP(upload(c->bpos, bpos, s));
+  SETUP_HIP(upload(c->n2e_ptr, n2e_ptr, s));
+  SETUP_HIP(upload(c->n2e, n2e, s));
+  SETUP_HIP(upload(c->ecol_perm, perm, s));
+  SETUP_HIP(upload(c->d_colour_first_block, c->colour_first_block, s));
+  SETUP_HIP(hipMemsetAsync(c->ep_s, 0, sizeof(double) * c->n_sc * n_int, s));
+  if (c->beta_s) SETUP_HIP(hipMemsetAsync(c->beta_s, 0, sizeof(double) * c->n_sc * n_int, s));
+  SETUP_HIP(hipMemsetAsync(c->kappa_s, 0, sizeof(double) * n_int, s));
+  SETUP_HIP(hipMemsetAsync(c->emask, 0, sizeof(uint32_t) * std::max<int64_t>(n_e, 1), s));
+  SETUP_HIP(hipMemsetAsync(c->epoch, 0, sizeof(int32_t) * std::max<int64_t>(nnzb, 1), s));
+  SETUP_HIP(hipMemsetAsync(c->Ke, 0, sizeof(double) * std::max<int64_t>(1, nnzb * dim * dim), s));
+  SETUP_HIP(hipMemsetAsync(c->ptotals, 0, sizeof(int32_t) * 4, s));
+  for (int k = 0; k < 2; ++k) SETUP_HIP(hipMemsetAsync(c->coff[k], 0, sizeof(int32_t) * (n_col + 1), s));
+
+  // geometry check: det J > 0 at every point
+  int32_t *bad = reinterpret_cast<int32_t *>(c->ptotals) + 2;
+  SETUP_HIP(launch_geometry(*c, nullptr, nullptr, bad));
+  int32_t bad_h = 0;
+  SETUP_HIP(hipMemcpyAsync(&bad_h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SETUP_HIP(hipStreamSynchronize(s));
+  if (bad_h > 0) {
+    c->err = "ep_setup: " + std::to_string(bad_h) + " integration points with det J <= 0";
+    return bail(EP_EINVAL);
+  }
+  // K_elast = B^T D_elast B (eq. K_elast-split), colour rounds
+  SETUP_HIP(launch_elastic_assembly(*c));
+  if (opt.tangent_prec == EP_FP32) SETUP_HIP(launch_to_float(c->Ke, c->Ke32, nnzb * dim * dim, s));
+  SETUP_HIP(launch_copy_ke_to_kt(*c));
+  SETUP_HIP(hipStreamSynchronize(s));
+  c->epoch_counter = 0;
+  c->cur = 0;
+  c->have_prev = false;
+  c->have_const = false;
+  *out = reinterpret_cast<ep_ctx *>(c);
+  return EP_OK;
+#undef SETUP_HIP
+}
+
+ep_status ep_set_stream(ep_ctx *ctx, void *hip_stream) {
+  CHECK_CTX(ctx);
+  reinterpret_cast<Ctx *>(ctx)->stream = (hipStream_t)hip_stream;
+  return EP_OK;
+}
+
+ep_status ep_get_sizes(const ep_ctx *ctx, ep_sizes *o) {
+  CHECK_CTX(ctx);
+  if (!o) return EP_EINVAL;
+  const Ctx *c = reinterpret_cast<const Ctx *>(ctx);
+  o->dim = c->dim;
+  o->n_p = c->n_p;
+  o->n_q = c->n_q;
+  o->n_str = c->n_str;
+  o->n_sc = c->n_sc;
+  o->n_colours = c->n_col;
+  o->n_nodes = c->n_n;
+  o->n_elems = c->n_e;
+  o->n_int = c->n_int;
+  o->n_dof = c->n_dof;
+  o->nnz = c->nnzb * c->dim * c->dim;
+  o->nnz_blocks = c->nnzb;
+  return EP_OK;
+}
+
+ep_status ep_set_state(ep_ctx *ctx, const double *ep, const double *beta, const double *kappa) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  const size_t nb = sizeof(double) * c->n_sc * c->n_int;
+  if (ep) HIPC(hipMemcpyAsync(c->ep_s, ep, nb, hipMemcpyDeviceToDevice, c->stream));
+  else HIPC(hipMemsetAsync(c->ep_s, 0, nb, c->stream));
+  if (c->beta_s) {
+    if (beta) HIPC(hipMemcpyAsync(c->beta_s, beta, nb, hipMemcpyDeviceToDevice, c->stream));
+    else HIPC(hipMemsetAsync(c->beta_s, 0, nb, c->stream));
+  }
+  if (kappa) HIPC(hipMemcpyAsync(c->kappa_s, kappa, sizeof(double) * c->n_int, hipMemcpyDeviceToDevice, c->stream));
+  else HIPC(hipMemsetAsync(c->kappa_s, 0, sizeof(double) * c->n_int, c->stream));
+  c->have_const = false;
+  return EP_OK;
+}
+
+ep_status ep_get_state(ep_ctx *ctx, double *ep, double *beta, double *kappa) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  const size_t nb = sizeof(double) * c->n_sc * c->n_int;
+  if (ep) HIPC(hipMemcpyAsync(ep, c->ep_s, nb, hipMemcpyDeviceToDevice, c->stream));
+  if (beta) {
+    if (c->beta_s) HIPC(hipMemcpyAsync(beta, c->beta_s, nb, hipMemcpyDeviceToDevice, c->stream));
+    else HIPC(hipMemsetAsync(beta, 0, nb, c->stream));
+  }
+  if (kappa) HIPC(hipMemcpyAsync(kappa, c->kappa_s, sizeof(double) * c->n_int, hipMemcpyDeviceToDevice, c->stream));
+  return EP_OK;
+}
+
+ep_status ep_geometry(ep_ctx *ctx, double *dphi, double *w) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  int32_t *bad = reinterpret_cast<int32_t *>(c->ptotals) + 2;
+  HIPC(launch_geometry(*c, dphi, w, bad));
+  return EP_OK;
+}
+
+ep_status ep_strain(ep_ctx *ctx, const double *u, double *eps) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!eps) return EP_EINVAL;
+  ConstArgs a{};
+  a.u = u;
+  a.eps_out = eps;
+  a.return_map = false;
+  a.force = false;
+  HIPC(launch_constitutive(*c, a));
+  return EP_OK;
+}
+
+ep_status ep_constitutive(ep_ctx *ctx, const double *u, double *sig, double *D, uint8_t *flag) {
+  CHECK_CTX(ctx);
+  return do_constitutive(reinterpret_cast<Ctx *>(ctx), u, sig, D, flag);
+}
+
+ep_status ep_assemble_tangent(ep_ctx *ctx) {
+  CHECK_CTX(ctx);
+  return do_assemble(reinterpret_cast<Ctx *>(ctx));
+}
+
+ep_status ep_internal_force(ep_ctx *ctx, double *F) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c->have_const) {
+    c->err = "ep_internal_force: no constitutive evaluation since setup or commit";
+    return EP_ESTATE;
+  }
+  return do_residual(c, nullptr, F);
+}
+
+ep_status ep_newton_step(ep_ctx *ctx, const double *f, double *u, ep_newton_info *info) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!f || !u || !info) return EP_EINVAL;
+  std::memset(info, 0, sizeof(*info));
+  ep_status st = do_constitutive(c, u, nullptr, nullptr, nullptr);
+  if (st) return st;
+  st = do_residual(c, f, nullptr);
+  if (st) return st;
+  HIPC(hipMemcpyAsync(c->norms_h, c->norms, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  int32_t tot[2];
+  HIPC(hipMemcpyAsync(tot, c->ptotals, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPC(hipStreamSynchronize(c->stream));
+  info->res_norm = std::sqrt(c->norms_h[0]);
+  info->f_norm = std::sqrt(c->norms_h[1]);
+  info->res_rel = info->f_norm > 0 ? info->res_norm / info->f_norm : info->res_norm;
+  info->n_plastic_elem = tot[0];
+  info->n_plastic_ip = tot[1];
+  if (info->res_rel <= c->opt.newton_rtol) {
+    info->converged = 1;
+    return EP_OK;
+  }
+  st = do_assemble(c);
+  if (st) return st;
+  const double rtol = std::min(c->opt.pcg_forcing_max, info->res_rel);
+  int its = 0;
+  double rel = 0;
+  const ep_status ps = do_pcg(c, c->r, c->px, rtol, c->opt.pcg_max_it, &its, &rel);
+  if (ps != EP_OK && ps != EP_ENOTCONV) return ps;
+  info->pcg_its = its;
+  info->pcg_relres = rel;
+  HIPC(launch_axpy_free(*c, c->px, u));
+  return ps;
+}
+
+ep_status ep_commit_step(ep_ctx *ctx, const double *u) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  ConstArgs a{};
+  a.u = u;
+  a.return_map = true;
+  a.commit = true;
+  a.force = false;
+  HIPC(launch_constitutive(*c, a));
+  c->have_const = false;
+  return EP_OK;
+}
+
+ep_status ep_get_plastic(ep_ctx *ctx, int32_t *ip, int64_t *n_ip, int32_t *elem, int64_t *n_elem) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c->have_const) {
+    c->err = "ep_get_plastic: no constitutive evaluation";
+    return EP_ESTATE;
+  }
+  int32_t *tot = c->ptotals + 2;  // [2], [3]: scratch totals
+  int32_t th[2] = {0, 0};
+  // elements (ascending) with their plastic-point counts
+  HIPC(launch_compact(*c, 1, c->emask, nullptr, c->n_e, elem ? elem : c->iscratch, nullptr, 0,
+                      nullptr, tot, nullptr));
+  HIPC(hipMemcpyAsync(th, tot, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPC(hipStreamSynchronize(c->stream));
+  if (n_elem) *n_elem = th[0];
+  if (n_ip) *n_ip = th[1];
+  if (ip) {
+    HIPC(launch_compact(*c, 0, c->flag, nullptr, c->n_int, ip, nullptr, 0, nullptr, tot, nullptr));
+    HIPC(hipMemcpyAsync(th, tot, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPC(hipStreamSynchronize(c->stream));
+    if (n_ip) *n_ip = th[0];
+  }
+  return EP_OK;
+}
+
+ep_status ep_get_csr(ep_ctx *ctx, int32_t which, int32_t *row_ptr, int32_t *col_idx, double *val) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (which != 0 && which != 1) return EP_EINVAL;
+  HIPC(launch_csr_expand(*c, which, row_ptr, col_idx, val));
+  return EP_OK;
+}
+
+ep_status ep_get_position_map(ep_ctx *ctx, int32_t *pos) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!pos) return EP_EINVAL;
+  HIPC(launch_pos_expand(*c, pos));
+  return EP_OK;
+}
+
+ep_status ep_spmv(ep_ctx *ctx, const double *x, double *y) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!x || !y) return EP_EINVAL;
+  HIPC(launch_spmv(*c, x, y, false, c->partials));
+  return EP_OK;
+}
+
+ep_status ep_pcg(ep_ctx *ctx, const double *b, double *x, double rtol, int32_t max_it, int32_t *its,
+                 double *relres) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!b || !x || max_it <= 0) return EP_EINVAL;
+  int it = 0;
+  double rel = 0;
+  const ep_status st = do_pcg(c, b, x, rtol, max_it, &it, &rel);
+  if (its) *its = it;
+  if (relres) *relres = rel;
+  return st;
+}
+
+ep_status ep_profile(ep_ctx *ctx, int32_t enable) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  c->prof_collect();
+  c->prof = enable != 0;
+  return EP_OK;
+}
+
+ep_status ep_profile_read(ep_ctx *ctx, int32_t k, double *ms, int64_t *count) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (k < 0 || k >= PROF_COUNT) return EP_EINVAL;
+  c->prof_collect();
+  if (ms) *ms = c->prof_ms[k];
+  if (count) *count = c->prof_n[k];
+  c->prof_ms[k] = 0;
+  c->prof_n[k] = 0;
+  return EP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,165 @@
+// Internal declarations shared by the host part of the library and its
+// HIP kernels.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ep.h"
+
+namespace ep {
+
+// Element kinds the kernels are specialised on.
+enum EtId { ET_P1_2D = 0, ET_Q1_2D, ET_Q2_2D, ET_P1_3D, ET_P2_3D, ET_Q1_3D, ET_Q2_3D, ET_COUNT };
+
+template <int ID> struct Et;
+template <> struct Et<ET_P1_2D> { static constexpr int D = 2, NP = 3, NQ = 1; };
+template <> struct Et<ET_Q1_2D> { static constexpr int D = 2, NP = 4, NQ = 4; };
+template <> struct Et<ET_Q2_2D> { static constexpr int D = 2, NP = 9, NQ = 9; };
+template <> struct Et<ET_P1_3D> { static constexpr int D = 3, NP = 4, NQ = 1; };
+template <> struct Et<ET_P2_3D> { static constexpr int D = 3, NP = 10, NQ = 11; };
+template <> struct Et<ET_Q1_3D> { static constexpr int D = 3, NP = 8, NQ = 8; };
+template <> struct Et<ET_Q2_3D> { static constexpr int D = 3, NP = 27, NQ = 27; };
+
+// Material constants used on the device.
+struct MatC {
+  int model;       // EP_VM / EP_DP
+  double G, K, a, Y, eta, c;
+};
+
+// Items per block of the compaction kernels (256 threads x 8 items).
+constexpr int CMP_THREADS = 256;
+constexpr int CMP_ITEMS = 8;
+constexpr int CMP_CHUNK = CMP_THREADS * CMP_ITEMS;
+
+// Kernel ids for ep_profile.
+enum ProfId { PROF_CONST = 0, PROF_COMPACT, PROF_RESTORE, PROF_ASSEMBLE, PROF_FORCE, PROF_SPMV,
+              PROF_PCGVEC, PROF_COUNT };
+
+struct Ctx;
+
+// ---- launch wrappers (ep_kernels.hip) ----
+struct ConstArgs {
+  const double *u;       // [n_dof] or nullptr (= zero displacement)
+  double *eps_out;       // [n_str][n_int] or nullptr
+  bool return_map;       // false: strain only
+  double *sig_out;       // [n_sc][n_int] or nullptr
+  double *D_out;         // [n_str^2][n_int] or nullptr
+  uint8_t *flag_out;     // [n_int] or nullptr (internal flag always written)
+  bool commit;           // write the updated state
+  bool force;            // element force vectors + plastic mask
+};
+hipError_t launch_constitutive(Ctx &c, const ConstArgs &a);
+hipError_t launch_geometry(Ctx &c, double *dphi, double *w, int32_t *bad_count);
+hipError_t launch_force_gather(Ctx &c, const double *f, double *F_out, double *r_out,
+                               double *partials, int nblk);
+hipError_t launch_reduce(Ctx &c, const double *partials, int nblk, int width, double *out);
+hipError_t launch_compact(Ctx &c, int kind, const void *src, const int32_t *perm, int64_t n,
+                          int32_t *out, int32_t *colour_first_block, int n_col,
+                          int32_t *colour_off, int32_t *total, int32_t *total_bits);
+hipError_t launch_elastic_assembly(Ctx &c);
+hipError_t launch_restore(Ctx &c);
+hipError_t launch_colour_assembly(Ctx &c, int colour, int epoch);
+hipError_t launch_copy_ke_to_kt(Ctx &c);
+hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t s);
+hipError_t launch_csr_expand(Ctx &c, int which, int32_t *row_ptr, int32_t *col_idx, double *val);
+hipError_t launch_pos_expand(Ctx &c, int32_t *pos);
+hipError_t launch_diag_inv(Ctx &c);
+hipError_t launch_spmv(Ctx &c, const double *x, double *y, bool fused_p, double *partials);
+hipError_t launch_pcg_init(Ctx &c, const double *b, double *x);
+hipError_t launch_pcg_iteration(Ctx &c, double *x);
+hipError_t launch_axpy_free(Ctx &c, const double *du, double *u);
+
+// ---- context ----
+struct Ctx {
+  std::string err;
+  hipStream_t stream = nullptr;
+  int dev = 0;
+
+  // sizes
+  int et = 0;            // EtId
+  int dim = 0, n_p = 0, n_q = 0, n_str = 0, n_sc = 0, n_desc = 0;
+  int64_t n_n = 0, n_e = 0, n_int = 0, n_dof = 0, nnzb = 0;
+  int n_col = 0;
+  MatC mat{};
+  ep_options opt{};
+
+  // mesh (device)
+  double *coord = nullptr;     // [dim][n_n]
+  int32_t *elem = nullptr;     // [n_e][n_p]
+  uint8_t *freem = nullptr;    // [n_dof]
+  double *ref = nullptr;       // [n_q][n_p][dim] reference gradients, then [n_q] weights
+
+  // node-block CSR of K (device)
+  int32_t *bptr = nullptr;     // [n_n+1]
+  int32_t *bcol = nullptr;     // [nnzb]
+  int32_t *bdiag = nullptr;    // [n_n] block index of (m, m)
+  int32_t *bpos = nullptr;     // [n_e][n_p][n_p] block index of (node p, node p')
+  double *Ke = nullptr;        // [nnzb][dim][dim]
+  float *Ke32 = nullptr;
+  void *Kt = nullptr;          // double or float, [nnzb][dim][dim]
+  int32_t *epoch = nullptr;    // [nnzb]
+  int epoch_counter = 0;
+
+  // node -> (element, local node), ascending element
+  int32_t *n2e_ptr = nullptr;  // [n_n+1]
+  int32_t *n2e = nullptr;      // [n_e*n_p], entries e*n_p + p
+
+  // colouring
+  std::vector<int64_t> colour_size;        // host
+  std::vector<int32_t> colour_first_block; // host, per colour + end
+  int32_t *ecol_perm = nullptr;            // [n_perm] colour-major, padded with -1
+  int64_t n_perm = 0;
+  int32_t *d_colour_first_block = nullptr; // [n_col+1]
+
+  // state and per-iteration data (device)
+  double *ep_s = nullptr;      // [n_sc][n_int]
+  double *beta_s = nullptr;    // [n_sc][n_int]
+  double *kappa_s = nullptr;   // [n_int]
+  uint8_t *flag = nullptr;     // [n_int]
+  double *desc = nullptr;      // [n_desc][n_int]
+  double *Fe = nullptr;        // [n_e*n_p][dim]
+  uint32_t *emask = nullptr;   // [n_e]
+  bool have_const = false;
+
+  // plastic element lists (colour-major), double-buffered
+  int32_t *plist[2] = {nullptr, nullptr};
+  int32_t *coff[2] = {nullptr, nullptr};   // [n_col+1] each
+  int32_t *ptotals = nullptr;              // [4]: total elems, total plastic ips, ...
+  int cur = 0;          // list written by the last constitutive pass
+  int asm_buf = -1;     // list used by the last assembly (-1: none yet)
+  bool have_prev = false;
+  int32_t *iscratch = nullptr;  // [max(n_int, n_e)] ascending plastic lists
+
+  // compaction scratch
+  int32_t *cmp_counts = nullptr, *cmp_counts2 = nullptr, *cmp_offsets = nullptr;
+  int64_t cmp_cap = 0;  // blocks
+
+  // vectors
+  double *F = nullptr, *r = nullptr;
+  double *partials = nullptr;  // reduction scratch
+  int64_t partials_cap = 0;
+  double *norms = nullptr;     // [8] device
+  double *norms_h = nullptr;   // pinned host [8]
+
+  // PCG
+  double *pz = nullptr, *pp[2] = {nullptr, nullptr}, *pq = nullptr, *px = nullptr,
+         *dinv = nullptr, *sc = nullptr, *sc_h = nullptr;
+  int pcur = 0;
+
+  // profiling
+  bool prof = false;
+  struct Pending { int id; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  double prof_ms[PROF_COUNT] = {0};
+  int64_t prof_n[PROF_COUNT] = {0};
+  int prof_begin(int id);
+  void prof_end(int token);
+  void prof_collect();
+};
+
+}  // namespace ep

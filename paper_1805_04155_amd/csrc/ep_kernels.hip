@@ -1,0 +1,1383 @@
+// HIP kernels of the elastoplastic Newton hot path, written for CDNA4 (gfx950).
+//
+// Method: Cermak, Sysala, Valdman (arXiv 1805.04155).  Data layout: per-point
+// arrays are structure-of-arrays [component][n_int]; the stiffness matrix is
+// stored as node blocks (dim x dim values contiguous) in a CSR over nodes;
+// element contributions reach it through an element position map of node
+// pairs.  Geometry (Jacobian, inverse, gradients, weights) is recomputed from
+// the element's node coordinates staged in LDS instead of storing B: this
+// trades a few hundred FP64 operations per point for the bytes a stored B
+// would cost, which is the right trade for these HBM-bound kernels.
+//
+// Determinism: every reduction has a fixed order; the scatter of element
+// matrices uses colour rounds (elements of one colour share no node) and no
+// floating-point atomics.
+#include "ep_internal.h"
+
+namespace ep {
+
+#define RT(x)                                  \
+  do {                                         \
+    hipError_t e__ = (x);                      \
+    if (e__ != hipSuccess) return e__;         \
+  } while (0)
+
+static inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// ----------------------------------------------------------------------------
+// Geometry: J_ij = sum_p dphi_p/dxi_i x_{p,j} (eq. Jacobian); grad_x = J^{-1}
+// grad_xi (eq. Jacobian2).  Returns det J.
+// ----------------------------------------------------------------------------
+template <int D, int NP>
+__device__ inline double jac_inv(const double *xs, const double *dr, double Ji[D][D]) {
+  double J[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) J[i][j] = 0.0;
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) J[i][j] += dr[p * D + i] * xs[p * D + j];
+  double det;
+  if constexpr (D == 2) {
+    det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const double id = 1.0 / det;
+    Ji[0][0] = J[1][1] * id;
+    Ji[0][1] = -J[0][1] * id;
+    Ji[1][0] = -J[1][0] * id;
+    Ji[1][1] = J[0][0] * id;
+  } else {
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const double id = 1.0 / det;
+    Ji[0][0] = c00 * id;
+    Ji[1][0] = c01 * id;
+    Ji[2][0] = c02 * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+  }
+  return det;
+}
+
+template <int D>
+__device__ inline void grad(const double Ji[D][D], const double *drp, double g[D]) {
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) s += Ji[i][k] * drp[k];
+    g[i] = s;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Return maps on Voigt vectors.  eps, ep: strain-type (engineering shears);
+// sig, beta, n: stress-type.  desc receives the tangent increment
+//   D - C = alpha*DEV + b*n n^T + g*(n 1^T + 1 n^T) + d*1 1^T
+// as [n(6), alpha, b, g, d] with DEV the deviatoric projector mapping
+// strain-type to stress-type vectors and 1 = (1,1,1,0,0,0).
+// ----------------------------------------------------------------------------
+__device__ inline void trial(const MatC &m, const double eps[6], const double ep[6], double dv[6],
+                             double &tr) {
+  double e[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) e[i] = eps[i] - ep[i];
+  tr = e[0] + e[1] + e[2];
+  const double t3 = tr / 3.0;
+  dv[0] = e[0] - t3;
+  dv[1] = e[1] - t3;
+  dv[2] = e[2] - t3;
+  dv[3] = 0.5 * e[3];
+  dv[4] = 0.5 * e[4];
+  dv[5] = 0.5 * e[5];
+}
+
+// von Mises, linear kinematic hardening (eqs. T_kinematic, DT_kinematic, T_other)
+__device__ inline int rm_vm(const MatC &m, const double eps[6], double ep[6], double beta[6],
+                           double sig[6], double desc[10], bool commit) {
+#pragma clang fp contract(off)
+  double dv[6], tr;
+  trial(m, eps, ep, dv, tr);
+  const double G2 = 2.0 * m.G;
+  double s[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    sig[i] = G2 * dv[i] + (i < 3 ? m.K * tr : 0.0);
+    s[i] = G2 * dv[i] - beta[i];
+  }
+  const double ns = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2] +
+                         2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
+  const double crit = ns - m.Y;
+  if (!(crit > 0.0)) return 0;
+  const double h = G2 + m.a;
+  const double dl = crit / h;
+  const double c1 = G2 * G2 / h;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const double n = s[i] / ns;
+    desc[i] = n;
+    sig[i] -= G2 * dl * n;
+    if (commit) {
+      ep[i] += (i < 3 ? 1.0 : 2.0) * dl * n;
+      beta[i] += m.a * dl * n;
+    }
+  }
+  desc[6] = c1 * (m.Y / ns - 1.0);
+  desc[7] = -c1 * m.Y / ns;
+  desc[8] = 0.0;
+  desc[9] = 0.0;
+  return 1;
+}
+
+// Drucker-Prager with yield function |s|/sqrt2 + eta p - (c + a kappa)
+// (Section 2.3; a = 0 perfect plasticity).  1 = smooth cone, 2 = apex.
+__device__ inline int rm_dp(const MatC &m, const double eps[6], double ep[6], double &kappa,
+                           double sig[6], double desc[10], bool commit) {
+#pragma clang fp contract(off)
+  const double r2 = 1.4142135623730951;
+  double dv[6], tr;
+  trial(m, eps, ep, dv, tr);
+  const double G2 = 2.0 * m.G;
+  const double p = m.K * tr;
+  const double dd = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2] +
+                    2.0 * (dv[3] * dv[3] + dv[4] * dv[4] + dv[5] * dv[5]);
+  const double rho = G2 * sqrt(dd);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) sig[i] = G2 * dv[i] + (i < 3 ? p : 0.0);
+  const double ck = m.c + m.a * kappa;
+  const double Ke2 = m.K * m.eta * m.eta;
+  const double crit1 = rho / r2 + m.eta * p - ck;
+  const double crit2 = m.eta * p - ck - (Ke2 + m.a) * rho / (r2 * m.G);
+  if (!(crit1 > 0.0)) return 0;
+  if (crit2 <= 0.0) {
+    const double h = m.G + Ke2 + m.a;
+    const double dl = crit1 / h;
+    const double c2 = 2.0 * r2 * m.G * m.G * dl / rho;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      const double n = G2 * dv[i] / rho;
+      desc[i] = n;
+      sig[i] -= dl * (r2 * m.G * n + (i < 3 ? m.K * m.eta : 0.0));
+      if (commit) ep[i] += i < 3 ? dl * (n / r2 + m.eta / 3.0) : 2.0 * dl * n / r2;
+    }
+    desc[6] = -c2;
+    desc[7] = c2 - 2.0 * m.G * m.G / h;
+    desc[8] = -r2 * m.G * m.K * m.eta / h;
+    desc[9] = -Ke2 * m.K / h;
+    if (commit) kappa += dl;
+    return 1;
+  }
+  const double dl = (m.eta * p - ck) / (Ke2 + m.a);
+  const double pk = p - m.K * m.eta * dl;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    sig[i] = i < 3 ? pk : 0.0;
+    desc[i] = 0.0;
+    if (commit) ep[i] = i < 3 ? eps[i] - pk / (3.0 * m.K) : eps[i];
+  }
+  desc[6] = -G2;
+  desc[7] = 0.0;
+  desc[8] = 0.0;
+  desc[9] = -Ke2 * m.K / (Ke2 + m.a);
+  if (commit) kappa += dl;
+  return 2;
+}
+
+// Full Voigt tangent entry (I, J) = C + (D - C) from the descriptor.
+__device__ inline double tangent_entry(const MatC &m, const double *desc, bool plastic, int I,
+                                       int J) {
+  const double one_I = I < 3 ? 1.0 : 0.0, one_J = J < 3 ? 1.0 : 0.0;
+  const double dev = (I == J ? (I < 3 ? 1.0 : 0.5) : 0.0) - one_I * one_J / 3.0;
+  double v = 2.0 * m.G * dev + m.K * one_I * one_J;
+  if (plastic) {
+    const double nI = desc[I], nJ = desc[J];
+    v += desc[6] * dev + desc[7] * nI * nJ + desc[8] * (nI * one_J + one_I * nJ) +
+         desc[9] * one_I * one_J;
+  }
+  return v;
+}
+
+// ----------------------------------------------------------------------------
+// Fused constitutive pass: strain, return map, tangent descriptor, element
+// force vectors and plastic bitmask.  One thread per integration point; the
+// EPB elements of a block stage their node coordinates and displacements in
+// LDS.  Element e, point q -> ip = e*NQ + q.
+// ----------------------------------------------------------------------------
+struct KC {
+  const double *coord;
+  const int32_t *elem;
+  const double *ref;
+  int64_t n_n, n_e, n_int;
+  const double *u;
+  MatC m;
+  double *ep, *beta, *kappa;
+  uint8_t *flag;
+  double *desc;
+  double *Fe;
+  uint32_t *emask;
+  double *eps_out, *sig_out, *D_out;
+  uint8_t *flag_out;
+  int rm, commit, force;
+};
+
+constexpr int CT = 256;  // threads of the constitutive kernel
+
+template <int ETID, int MODEL>
+__global__ __launch_bounds__(CT) void k_constitutive(KC a) {
+  using T = Et<ETID>;
+  constexpr int D = T::D, NP = T::NP, NQ = T::NQ;
+  constexpr int EPB = CT / NQ;
+  constexpr int NS = D == 3 ? 6 : 3;  // stress components entering B^T sigma
+  constexpr int NF = NS + D * D;      // per point: w*sigma, J^{-1}
+  constexpr int NSC = D == 3 ? 6 : 4; // stored state components
+  constexpr int NSTR = D == 3 ? 6 : 3;
+  __shared__ double s_ref[NQ * NP * D];
+  __shared__ double s_wq[NQ];
+  __shared__ double s_x[EPB * NP * D];
+  __shared__ double s_u[EPB * NP * D];
+  __shared__ double s_f[EPB * NQ * NF];
+  __shared__ uint32_t s_mask[EPB];
+
+  const int tid = threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * EPB;
+  for (int t = tid; t < NQ * NP * D; t += CT) s_ref[t] = a.ref[t];
+  for (int t = tid; t < NQ; t += CT) s_wq[t] = a.ref[NQ * NP * D + t];
+  for (int t = tid; t < EPB; t += CT) s_mask[t] = 0u;
+  for (int t = tid; t < EPB * NP; t += CT) {
+    const int64_t e = e0 + t / NP;
+    if (e < a.n_e) {
+      const int64_t node = a.elem[e * NP + t % NP];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        s_x[t * D + d] = a.coord[d * a.n_n + node];
+        s_u[t * D + d] = a.u ? a.u[D * node + d] : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+
+  const int el = tid / NQ, q = tid - (tid / NQ) * NQ;
+  const int64_t e = e0 + el;
+  if (tid < EPB * NQ && e < a.n_e) {
+    const int64_t ip = e * NQ + q;
+    const int64_t N = a.n_int;
+    const double *xs = s_x + el * NP * D, *us = s_u + el * NP * D, *dr = s_ref + q * NP * D;
+    double Ji[D][D];
+    const double det = jac_inv<D, NP>(xs, dr, Ji);
+    const double w = fabs(det) * s_wq[q];
+    // strain E = B u (eq. local_strain-displ), engineering Voigt
+    double eps[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      double g[D];
+      grad<D>(Ji, dr + p * D, g);
+      const double *up = us + p * D;
+      if constexpr (D == 3) {
+        eps[0] += g[0] * up[0];
+        eps[1] += g[1] * up[1];
+        eps[2] += g[2] * up[2];
+        eps[3] += g[1] * up[0] + g[0] * up[1];
+        eps[4] += g[2] * up[1] + g[1] * up[2];
+        eps[5] += g[2] * up[0] + g[0] * up[2];
+      } else {
+        eps[0] += g[0] * up[0];
+        eps[1] += g[1] * up[1];
+        eps[3] += g[1] * up[0] + g[0] * up[1];
+      }
+    }
+    if (a.eps_out) {
+      if constexpr (D == 3) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) a.eps_out[i * N + ip] = eps[i];
+      } else {
+        a.eps_out[0 * N + ip] = eps[0];
+        a.eps_out[1 * N + ip] = eps[1];
+        a.eps_out[2 * N + ip] = eps[3];
+      }
+    }
+    double sig[6] = {0, 0, 0, 0, 0, 0};
+    if (a.rm) {
+      double ep[6] = {0, 0, 0, 0, 0, 0}, bt[6] = {0, 0, 0, 0, 0, 0}, kap = 0.0;
+#pragma unroll
+      for (int c = 0; c < NSC; ++c) ep[c] = a.ep[c * N + ip];
+      if (MODEL == EP_VM) {
+#pragma unroll
+        for (int c = 0; c < NSC; ++c) bt[c] = a.beta[c * N + ip];
+      } else {
+        kap = a.kappa[ip];
+      }
+      double desc[10];
+      const bool commit = a.commit != 0;
+      const int f = MODEL == EP_VM ? rm_vm(a.m, eps, ep, bt, sig, desc, commit)
+                                   : rm_dp(a.m, eps, ep, kap, sig, desc, commit);
+      a.flag[ip] = (uint8_t)f;
+      if (a.flag_out) a.flag_out[ip] = (uint8_t)f;
+      if (f) {
+        if constexpr (D == 3) {
+#pragma unroll
+          for (int i = 0; i < 10; ++i) a.desc[i * N + ip] = desc[i];
+        } else {
+          a.desc[0 * N + ip] = desc[0];
+          a.desc[1 * N + ip] = desc[1];
+          a.desc[2 * N + ip] = desc[3];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) a.desc[(3 + i) * N + ip] = desc[6 + i];
+        }
+        atomicOr(&s_mask[el], 1u << q);
+      }
+      if (a.sig_out) {
+#pragma unroll
+        for (int c = 0; c < NSC; ++c) a.sig_out[c * N + ip] = sig[c];
+      }
+      if (a.D_out) {
+        constexpr int idx3[3] = {0, 1, 3};
+#pragma unroll
+        for (int I = 0; I < NSTR; ++I)
+#pragma unroll
+          for (int J = 0; J < NSTR; ++J) {
+            const int vI = D == 3 ? I : idx3[I], vJ = D == 3 ? J : idx3[J];
+            a.D_out[(I * NSTR + J) * N + ip] = tangent_entry(a.m, desc, f != 0, vI, vJ);
+          }
+      }
+      if (a.commit && f) {
+#pragma unroll
+        for (int c = 0; c < NSC; ++c) a.ep[c * N + ip] = ep[c];
+        if (MODEL == EP_VM) {
+#pragma unroll
+          for (int c = 0; c < NSC; ++c) a.beta[c * N + ip] = bt[c];
+        } else {
+          a.kappa[ip] = kap;
+        }
+      }
+    }
+    if (a.force) {
+      double *sf = s_f + tid * NF;
+      if constexpr (D == 3) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) sf[i] = w * sig[i];
+      } else {
+        sf[0] = w * sig[0];
+        sf[1] = w * sig[1];
+        sf[2] = w * sig[3];
+      }
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) sf[NS + i * D + j] = Ji[i][j];
+    }
+  }
+  __syncthreads();
+  if (!a.force) return;
+  // F_e[p] = sum_q w_q sigma_q grad phi_p(q)  (B^T (WEIGHT .* S), Section 7)
+  for (int t = tid; t < EPB * NP; t += CT) {
+    const int elx = t / NP, p = t - (t / NP) * NP;
+    const int64_t ee = e0 + elx;
+    if (ee >= a.n_e) continue;
+    double f[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) f[i] = 0.0;
+    for (int qq = 0; qq < NQ; ++qq) {
+      const double *sf = s_f + (elx * NQ + qq) * NF;
+      double Ji[D][D];
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) Ji[i][j] = sf[NS + i * D + j];
+      double g[D];
+      grad<D>(Ji, s_ref + (qq * NP + p) * D, g);
+      if constexpr (D == 3) {
+        f[0] += sf[0] * g[0] + sf[3] * g[1] + sf[5] * g[2];
+        f[1] += sf[3] * g[0] + sf[1] * g[1] + sf[4] * g[2];
+        f[2] += sf[5] * g[0] + sf[4] * g[1] + sf[2] * g[2];
+      } else {
+        f[0] += sf[0] * g[0] + sf[2] * g[1];
+        f[1] += sf[2] * g[0] + sf[1] * g[1];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) a.Fe[(ee * NP + p) * D + i] = f[i];
+  }
+  for (int t = tid; t < EPB; t += CT)
+    if (e0 + t < a.n_e) a.emask[e0 + t] = s_mask[t];
+}
+
+// ----------------------------------------------------------------------------
+// Geometry view (dphi, w) and the det J > 0 check.
+// ----------------------------------------------------------------------------
+template <int ETID>
+__global__ void k_geometry(const double *coord, const int32_t *elem, const double *ref,
+                           int64_t n_n, int64_t n_e, double *dphi, double *wout, int32_t *bad) {
+  using T = Et<ETID>;
+  constexpr int D = T::D, NP = T::NP, NQ = T::NQ;
+  const int64_t ip = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ip >= n_e * NQ) return;
+  const int64_t e = ip / NQ;
+  const int q = (int)(ip - e * NQ);
+  double xs[NP * D];
+  for (int p = 0; p < NP; ++p) {
+    const int64_t node = elem[e * NP + p];
+    for (int d = 0; d < D; ++d) xs[p * D + d] = coord[d * n_n + node];
+  }
+  const double *dr = ref + q * NP * D;
+  double Ji[D][D];
+  const double det = jac_inv<D, NP>(xs, dr, Ji);
+  if (!(det > 0.0)) atomicAdd(bad, 1);
+  if (wout) wout[ip] = fabs(det) * ref[NQ * NP * D + q];
+  if (dphi)
+    for (int p = 0; p < NP; ++p) {
+      double g[D];
+      grad<D>(Ji, dr + p * D, g);
+      for (int d = 0; d < D; ++d) dphi[(ip * NP + p) * D + d] = g[d];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Element-local tangent products scattered through the position map.
+//   elastic = 1: K_elast, C at every point, accumulated into Ke (setup).
+//   elastic = 0: Delta K_e = sum_{plastic q} w_q B_q^T (D_q - C) B_q added to
+//                the base value (K_elast if the block was not touched yet in
+//                this assembly, else K_tangent), blocks stamped with the
+//                assembly epoch.
+// One workgroup per element of the colour segment; one thread per node pair
+// (p, p'), which owns the dim x dim block.
+// ----------------------------------------------------------------------------
+struct KA {
+  const double *coord;
+  const int32_t *elem;
+  const double *ref;
+  int64_t n_n, n_int;
+  const double *desc;
+  const uint32_t *emask;
+  const int32_t *list;
+  const int32_t *off;  // device segment bounds (plastic lists) or nullptr
+  int colour;
+  int64_t k0, k1;      // host segment bounds when off == nullptr
+  const int32_t *bpos;
+  const double *Ke;
+  const float *Ke32;
+  void *Kt;
+  int32_t *epoch;
+  int cur;
+  int elastic;
+  double G, K;
+};
+
+template <int ETID>
+struct AsmCfg {
+  using T = Et<ETID>;
+  static constexpr int a = T::NP * T::NP > T::NQ * T::NP ? T::NP * T::NP : T::NQ * T::NP;
+  static constexpr int BS = a <= 64 ? 64 : ((a + 63) / 64) * 64;
+};
+
+template <int ETID, typename VT>
+__global__ __launch_bounds__(AsmCfg<ETID>::BS) void k_assemble(KA a) {
+  using T = Et<ETID>;
+  constexpr int D = T::D, NP = T::NP, NQ = T::NQ, BS = AsmCfg<ETID>::BS;
+  constexpr int NDESC = D == 3 ? 10 : 7;
+  constexpr int NN = D == 3 ? 6 : 3;  // stored n components
+  __shared__ double s_ref[NQ * NP * D];
+  __shared__ double s_x[NP * D];
+  __shared__ double s_w[NQ];
+  __shared__ double s_d[NQ * NDESC];
+  __shared__ double s_Ji[NQ * D * D];
+  __shared__ double s_g[NQ * NP * D];
+  __shared__ double s_ng[NQ * NP * D];
+  const int tid = threadIdx.x;
+  for (int t = tid; t < NQ * NP * D; t += BS) s_ref[t] = a.ref[t];
+  int64_t k0 = a.k0, k1 = a.k1;
+  if (a.off) {
+    k0 = a.off[a.colour];
+    k1 = a.off[a.colour + 1];
+  }
+  VT *Kt = (VT *)a.Kt;
+  for (int64_t k = k0 + blockIdx.x; k < k1; k += gridDim.x) {
+    const int e = a.list[k];
+    if (e < 0) continue;  // padding of the colour-major order (uniform)
+    const uint32_t mask = a.elastic ? 0xffffffffu : a.emask[e];
+    __syncthreads();
+    for (int t = tid; t < NP * D; t += BS) {
+      const int64_t node = a.elem[(int64_t)e * NP + t / D];
+      s_x[t] = a.coord[(t % D) * a.n_n + node];
+    }
+    __syncthreads();
+    if (tid < NQ && ((mask >> tid) & 1u)) {
+      double Ji[D][D];
+      const double det = jac_inv<D, NP>(s_x, s_ref + tid * NP * D, Ji);
+      s_w[tid] = fabs(det) * a.ref[NQ * NP * D + tid];
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) s_Ji[tid * D * D + i * D + j] = Ji[i][j];
+      if (a.elastic) {
+        for (int c = 0; c < NDESC; ++c) s_d[tid * NDESC + c] = 0.0;
+        s_d[tid * NDESC + NN + 0] = 2.0 * a.G;
+        s_d[tid * NDESC + NN + 3] = a.K;
+      } else {
+        const int64_t ip = (int64_t)e * NQ + tid;
+        for (int c = 0; c < NDESC; ++c) s_d[tid * NDESC + c] = a.desc[c * a.n_int + ip];
+      }
+    }
+    __syncthreads();
+    if (tid < NQ * NP) {
+      const int q = tid / NP, p = tid - (tid / NP) * NP;
+      if ((mask >> q) & 1u) {
+        double Ji[D][D];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int j = 0; j < D; ++j) Ji[i][j] = s_Ji[q * D * D + i * D + j];
+        double g[D];
+        grad<D>(Ji, s_ref + (q * NP + p) * D, g);
+        const double *n = s_d + q * NDESC;
+        double ng[D];
+        if constexpr (D == 3) {
+          // tensor n (stress-type Voigt 11,22,33,12,23,13) times g
+          ng[0] = n[0] * g[0] + n[3] * g[1] + n[5] * g[2];
+          ng[1] = n[3] * g[0] + n[1] * g[1] + n[4] * g[2];
+          ng[2] = n[5] * g[0] + n[4] * g[1] + n[2] * g[2];
+        } else {
+          ng[0] = n[0] * g[0] + n[2] * g[1];
+          ng[1] = n[2] * g[0] + n[1] * g[1];
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          s_g[(q * NP + p) * D + i] = g[i];
+          s_ng[(q * NP + p) * D + i] = ng[i];
+        }
+      }
+    }
+    __syncthreads();
+    for (int t = tid; t < NP * NP; t += BS) {
+      const int p = t / NP, pp = t - (t / NP) * NP;
+      double acc[D][D];
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) acc[i][j] = 0.0;
+      uint32_t m = mask & ((NQ == 32) ? 0xffffffffu : ((1u << NQ) - 1u));
+      while (m) {
+        const int q = __builtin_ctz(m);
+        m &= m - 1u;
+        const double *dq = s_d + q * NDESC + NN;
+        const double w = s_w[q];
+        const double al = w * dq[0], be = w * dq[1], ga = w * dq[2], de = w * dq[3];
+        const double *g = s_g + (q * NP + p) * D, *h = s_g + (q * NP + pp) * D;
+        const double *ng = s_ng + (q * NP + p) * D, *nh = s_ng + (q * NP + pp) * D;
+        double gh = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) gh += g[i] * h[i];
+        // block(i,j) of B_p^T (D - C) B_p': DEV gives 1/2 (g.h) d_ij
+        // + 1/2 h_i g_j - 1/3 g_i h_j
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int j = 0; j < D; ++j)
+            acc[i][j] += al * ((i == j ? 0.5 * gh : 0.0) + 0.5 * h[i] * g[j] - g[i] * h[j] / 3.0) +
+                         be * ng[i] * nh[j] + ga * (ng[i] * h[j] + g[i] * nh[j]) +
+                         de * g[i] * h[j];
+      }
+      const int64_t idx = a.bpos[(int64_t)e * NP * NP + t];
+      VT *dst = Kt + idx * D * D;
+      if (a.elastic) {
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int j = 0; j < D; ++j) dst[i * D + j] += (VT)acc[i][j];
+      } else {
+        const bool fresh = a.epoch[idx] != a.cur;
+        if (fresh) {
+          if constexpr (sizeof(VT) == 8) {
+            const double *src = a.Ke + idx * D * D;
+#pragma unroll
+            for (int i = 0; i < D * D; ++i) dst[i] = (VT)(src[i] + acc[i / D][i % D]);
+          } else {
+            const float *src = a.Ke32 + idx * D * D;
+#pragma unroll
+            for (int i = 0; i < D * D; ++i) dst[i] = (VT)((double)src[i] + acc[i / D][i % D]);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < D * D; ++i) dst[i] = (VT)((double)dst[i] + acc[i / D][i % D]);
+        }
+        a.epoch[idx] = a.cur;
+      }
+    }
+  }
+}
+
+// Blocks of the elements of the previous plastic list that are elastic now
+// go back to K_elast.  Elements still plastic are rewritten by the colour
+// rounds (their blocks carry an old epoch).
+template <int ETID, typename VT>
+__global__ void k_restore(const int32_t *prev, const int32_t *prev_total, const uint32_t *emask,
+                          const int32_t *bpos, const VT *Ke, VT *Kt) {
+  using T = Et<ETID>;
+  constexpr int D = T::D, NP = T::NP;
+  const int64_t total = *prev_total;
+  for (int64_t k = blockIdx.x; k < total; k += gridDim.x) {
+    const int e = prev[k];
+    if (emask[e]) continue;
+    for (int t = threadIdx.x; t < NP * NP; t += blockDim.x) {
+      const int64_t idx = bpos[(int64_t)e * NP * NP + t];
+#pragma unroll
+      for (int i = 0; i < D * D; ++i) Kt[idx * D * D + i] = Ke[idx * D * D + i];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Deterministic node gather of the element force vectors, residual and
+// partial norms.
+// ----------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_force_gather(int64_t n_n, const int32_t *n2e_ptr,
+                                                      const int32_t *n2e, const double *Fe,
+                                                      const double *f, const uint8_t *freem,
+                                                      double *F_out, double *r_out,
+                                                      double *partials) {
+  __shared__ double s_a[256], s_b[256];
+  const int tid = threadIdx.x;
+  const int64_t m = (int64_t)blockIdx.x * 256 + tid;
+  double rr = 0.0, ff = 0.0;
+  if (m < n_n) {
+    double s[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) s[i] = 0.0;
+    const int k1 = n2e_ptr[m + 1];
+    for (int k = n2e_ptr[m]; k < k1; ++k) {
+      const int64_t ent = n2e[k];
+#pragma unroll
+      for (int i = 0; i < D; ++i) s[i] += Fe[ent * D + i];
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const int64_t dof = D * m + i;
+      if (F_out) F_out[dof] = s[i];
+      const bool fr = freem[dof] != 0;
+      const double fv = (f && fr) ? f[dof] : 0.0;
+      const double r = fr ? fv - s[i] : 0.0;
+      if (r_out) r_out[dof] = r;
+      rr += r * r;
+      ff += fv * fv;
+    }
+  }
+  s_a[tid] = rr;
+  s_b[tid] = ff;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      s_a[tid] += s_a[tid + s];
+      s_b[tid] += s_b[tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    partials[2 * blockIdx.x] = s_a[0];
+    partials[2 * blockIdx.x + 1] = s_b[0];
+  }
+}
+
+// Sum of nblk partial vectors of `width` doubles, fixed order.
+__global__ __launch_bounds__(256) void k_reduce(const double *partials, int nblk, int width,
+                                                double *out) {
+  __shared__ double s[256];
+  const int tid = threadIdx.x;
+  for (int c = 0; c < width; ++c) {
+    double v = 0.0;
+    for (int b = tid; b < nblk; b += 256) v += partials[(int64_t)b * width + c];
+    s[tid] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (tid < h) s[tid] += s[tid + h];
+      __syncthreads();
+    }
+    if (tid == 0) out[c] = s[0];
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Stable compaction (wavefront ballot + block scan).  Items i < n (optionally
+// through a permutation, -1 = padding) with predicate src[item] != 0; kind 0:
+// uint8 source, kind 1: uint32 source (also counts set bits).
+// ----------------------------------------------------------------------------
+__device__ inline uint32_t cmp_value(const void *src, int kind, int64_t item) {
+  if (item < 0) return 0u;
+  return kind == 0 ? (uint32_t)((const uint8_t *)src)[item] : ((const uint32_t *)src)[item];
+}
+
+__global__ __launch_bounds__(CMP_THREADS) void k_compact_count(const void *src, int kind,
+                                                               const int32_t *perm, int64_t n,
+                                                               int32_t *counts,
+                                                               int32_t *counts2) {
+  __shared__ int32_t s_c[CMP_THREADS / 64], s_b[CMP_THREADS / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t base = (int64_t)blockIdx.x * CMP_CHUNK;
+  int32_t cnt = 0, bits = 0;
+  for (int k = 0; k < CMP_ITEMS; ++k) {
+    const int64_t i = base + (int64_t)k * CMP_THREADS + tid;
+    uint32_t v = 0u;
+    if (i < n) v = cmp_value(src, kind, perm ? (int64_t)perm[i] : i);
+    const uint64_t b = __ballot(v != 0u);
+    cnt += __popcll(b);
+    bits += __popc(v);
+  }
+  // wave-level sum of set bits
+  for (int o = 32; o > 0; o >>= 1) bits += __shfl_down(bits, o, 64);
+  if (lane == 0) {
+    s_c[wv] = cnt;
+    s_b[wv] = bits;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int32_t c = 0, bb = 0;
+    for (int w = 0; w < CMP_THREADS / 64; ++w) {
+      c += s_c[w];
+      bb += s_b[w];
+    }
+    counts[blockIdx.x] = c;
+    if (counts2) counts2[blockIdx.x] = bb;
+  }
+}
+
+// Exclusive scan of the block counts (single workgroup), colour offsets and
+// totals.  totals[0] = items, totals[1] = set bits.
+__global__ __launch_bounds__(1024) void k_compact_scan(const int32_t *counts,
+                                                       const int32_t *counts2, int nblk,
+                                                       int32_t *offsets,
+                                                       const int32_t *colour_first_block,
+                                                       int n_col, int32_t *colour_off,
+                                                       int32_t *totals) {
+  __shared__ int32_t s[1024];
+  __shared__ int32_t s2[1024];
+  const int tid = threadIdx.x;
+  const int per = (nblk + 1023) / 1024;
+  const int b0 = tid * per;
+  int32_t sum = 0, sum2 = 0;
+  for (int b = b0; b < b0 + per && b < nblk; ++b) {
+    sum += counts[b];
+    if (counts2) sum2 += counts2[b];
+  }
+  s[tid] = sum;
+  s2[tid] = sum2;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int32_t v = tid >= o ? s[tid - o] : 0;
+    const int32_t v2 = tid >= o ? s2[tid - o] : 0;
+    __syncthreads();
+    s[tid] += v;
+    s2[tid] += v2;
+    __syncthreads();
+  }
+  int32_t run = s[tid] - sum;  // exclusive prefix of this thread's range
+  for (int b = b0; b < b0 + per && b < nblk; ++b) {
+    offsets[b] = run;
+    run += counts[b];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    totals[0] = s[1023];
+    totals[1] = s2[1023];
+    offsets[nblk] = s[1023];
+  }
+  __syncthreads();
+  if (colour_off)
+    for (int c = tid; c <= n_col; c += 1024) {
+      const int fb = colour_first_block[c];
+      colour_off[c] = fb >= nblk ? s[1023] : offsets[fb];
+    }
+}
+
+__global__ __launch_bounds__(CMP_THREADS) void k_compact_scatter(const void *src, int kind,
+                                                                 const int32_t *perm, int64_t n,
+                                                                 const int32_t *offsets,
+                                                                 int32_t *out) {
+  __shared__ int32_t s_w[CMP_THREADS / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t base = (int64_t)blockIdx.x * CMP_CHUNK;
+  int32_t run = offsets[blockIdx.x];
+  for (int k = 0; k < CMP_ITEMS; ++k) {
+    const int64_t i = base + (int64_t)k * CMP_THREADS + tid;
+    int64_t item = -1;
+    uint32_t v = 0u;
+    if (i < n) {
+      item = perm ? (int64_t)perm[i] : i;
+      v = cmp_value(src, kind, item);
+    }
+    const uint64_t b = __ballot(v != 0u);
+    const int rank = __popcll(b & ((1ull << lane) - 1ull));
+    if (lane == 0) s_w[wv] = __popcll(b);
+    __syncthreads();
+    int32_t before = 0, tot = 0;
+    for (int w = 0; w < CMP_THREADS / 64; ++w) {
+      if (w < wv) before += s_w[w];
+      tot += s_w[w];
+    }
+    if (v != 0u) out[run + before + rank] = (int32_t)item;
+    run += tot;
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Sparse matrix views, SpMV and PCG vectors
+// ----------------------------------------------------------------------------
+template <int D, typename VT>
+__global__ void k_csr_expand(int64_t n_n, int64_t nnzb, const int32_t *bptr,
+                             const int32_t *bcol, const VT *val, int32_t *row_ptr,
+                             int32_t *col_idx, double *vout) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > D * n_n) return;
+  if (r == D * n_n) {
+    if (row_ptr) row_ptr[r] = (int32_t)(D * D * nnzb);
+    return;
+  }
+  const int64_t m = r / D;
+  const int i = (int)(r - m * D);
+  const int64_t b0 = bptr[m], deg = bptr[m + 1] - b0;
+  const int64_t rp = D * D * b0 + i * D * deg;
+  if (row_ptr) row_ptr[r] = (int32_t)rp;
+  for (int64_t t = 0; t < deg; ++t)
+    for (int j = 0; j < D; ++j) {
+      if (col_idx) col_idx[rp + D * t + j] = (int32_t)(D * bcol[b0 + t] + j);
+      if (vout) vout[rp + D * t + j] = (double)val[((b0 + t) * D + i) * D + j];
+    }
+}
+
+template <int ETID>
+__global__ void k_pos_expand(int64_t n_e, const int32_t *elem, const int32_t *bptr,
+                             const int32_t *bpos, int32_t *pos) {
+  using T = Et<ETID>;
+  constexpr int D = T::D, NP = T::NP;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_e * NP * NP) return;
+  const int64_t e = t / (NP * NP);
+  const int p = (int)((t / NP) % NP), pp = (int)(t % NP);
+  const int64_t m = elem[e * NP + p];
+  const int64_t b0 = bptr[m], deg = bptr[m + 1] - b0;
+  const int64_t tt = bpos[t] - b0;
+  constexpr int NL = D * NP;
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j)
+      pos[(e * NL + D * p + i) * NL + D * pp + j] =
+          (int32_t)(D * D * b0 + i * D * deg + D * tt + j);
+}
+
+template <int D, typename VT>
+__global__ void k_diag_inv(int64_t n_n, const int32_t *bdiag, const VT *Kt, const uint8_t *freem,
+                           double *dinv) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D * n_n) return;
+  const int64_t m = r / D;
+  const int i = (int)(r - m * D);
+  const double d = (double)Kt[((int64_t)bdiag[m] * D + i) * D + i];
+  dinv[r] = freem[r] ? 1.0 / d : 0.0;
+}
+
+// PCG scalars on the device
+enum { SC_RZ = 0, SC_PQ, SC_RR, SC_TOL, SC_DONE, SC_ITS, SC_ALPHA, SC_BETA, SC_RR0, SC_N };
+
+// y = Q K x (row per thread, node blocks), optional fused direction update
+// x = z + beta*p_old (written to p_new for the own row), partial x.y
+template <int D, typename VT>
+__global__ __launch_bounds__(256) void k_spmv(int64_t n_n, const int32_t *bptr,
+                                              const int32_t *bcol, const VT *val,
+                                              const double *x, const uint8_t *freem, double *y,
+                                              double *partials, const double *z,
+                                              const double *pold, double *pnew, const double *sc) {
+  __shared__ double s[256];
+  if (sc && sc[SC_DONE] != 0.0) return;
+  const int tid = threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * 256 + tid;
+  const double beta = sc ? sc[SC_BETA] : 0.0;
+  double dot = 0.0;
+  if (r < D * n_n) {
+    const int64_t m = r / D;
+    const int i = (int)(r - m * D);
+    double acc = 0.0;
+    const int b1 = bptr[m + 1];
+    for (int b = bptr[m]; b < b1; ++b) {
+      const int64_t c = bcol[b];
+      const VT *v = val + ((int64_t)b * D + i) * D;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const double xv = z ? z[D * c + j] + beta * pold[D * c + j] : x[D * c + j];
+        acc += (double)v[j] * xv;
+      }
+    }
+    const double yv = freem[r] ? acc : 0.0;
+    y[r] = yv;
+    double xr;
+    if (z) {
+      xr = z[r] + beta * pold[r];
+      pnew[r] = xr;
+    } else {
+      xr = x[r];
+    }
+    dot = xr * yv;
+  }
+  s[tid] = dot;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) s[tid] += s[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) partials[blockIdx.x] = s[0];
+}
+
+// alpha = rz / pq
+__global__ __launch_bounds__(256) void k_pcg_alpha(const double *partials, int nblk, double *sc) {
+  __shared__ double s[256];
+  if (sc[SC_DONE] != 0.0) return;
+  const int tid = threadIdx.x;
+  double v = 0.0;
+  for (int b = tid; b < nblk; b += 256) v += partials[b];
+  s[tid] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) s[tid] += s[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    sc[SC_PQ] = s[0];
+    sc[SC_ALPHA] = sc[SC_RZ] / s[0];
+  }
+}
+
+// x += alpha p, r -= alpha q, z = dinv r, partial (r.z, r.r)
+__global__ __launch_bounds__(256) void k_pcg_update(int64_t n, double *x, const double *p,
+                                                    double *r, const double *q, double *z,
+                                                    const double *dinv, const double *sc,
+                                                    double *partials) {
+  __shared__ double sa[256], sb[256];
+  if (sc[SC_DONE] != 0.0) return;
+  const int tid = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+  double rz = 0.0, rr = 0.0;
+  if (i < n) {
+    const double al = sc[SC_ALPHA];
+    x[i] += al * p[i];
+    const double rv = r[i] - al * q[i];
+    r[i] = rv;
+    const double zv = dinv[i] * rv;
+    z[i] = zv;
+    rz = rv * zv;
+    rr = rv * rv;
+  }
+  sa[tid] = rz;
+  sb[tid] = rr;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      sa[tid] += sa[tid + h];
+      sb[tid] += sb[tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    partials[2 * blockIdx.x] = sa[0];
+    partials[2 * blockIdx.x + 1] = sb[0];
+  }
+}
+
+// beta = rz_new / rz, convergence flag
+__global__ __launch_bounds__(256) void k_pcg_beta(const double *partials, int nblk, double *sc,
+                                                  int init, double rtol) {
+  __shared__ double sa[256], sb[256];
+  if (!init && sc[SC_DONE] != 0.0) return;
+  const int tid = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int k = tid; k < nblk; k += 256) {
+    a += partials[2 * k];
+    b += partials[2 * k + 1];
+  }
+  sa[tid] = a;
+  sb[tid] = b;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      sa[tid] += sa[tid + h];
+      sb[tid] += sb[tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (init) {
+      sc[SC_RZ] = sa[0];
+      sc[SC_RR] = sb[0];
+      sc[SC_RR0] = sb[0];
+      sc[SC_TOL] = rtol * rtol * sb[0];
+      sc[SC_ITS] = 0.0;
+      sc[SC_BETA] = 0.0;
+      sc[SC_DONE] = (sb[0] <= sc[SC_TOL]) ? 1.0 : 0.0;
+    } else {
+      sc[SC_BETA] = sa[0] / sc[SC_RZ];
+      sc[SC_RZ] = sa[0];
+      sc[SC_RR] = sb[0];
+      sc[SC_ITS] += 1.0;
+      if (sb[0] <= sc[SC_TOL]) sc[SC_DONE] = 1.0;
+    }
+  }
+}
+
+// r = Q b, x = 0, z = dinv r, p_old = 0, partial (r.z, r.r)
+__global__ __launch_bounds__(256) void k_pcg_init(int64_t n, const double *b, const uint8_t *freem,
+                                                  double *x, double *r, double *z, double *pold,
+                                                  const double *dinv, double *partials) {
+  __shared__ double sa[256], sb[256];
+  const int tid = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+  double rz = 0.0, rr = 0.0;
+  if (i < n) {
+    const double rv = freem[i] ? b[i] : 0.0;
+    x[i] = 0.0;
+    r[i] = rv;
+    const double zv = dinv[i] * rv;
+    z[i] = zv;
+    pold[i] = 0.0;
+    rz = rv * zv;
+    rr = rv * rv;
+  }
+  sa[tid] = rz;
+  sb[tid] = rr;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      sa[tid] += sa[tid + h];
+      sb[tid] += sb[tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    partials[2 * blockIdx.x] = sa[0];
+    partials[2 * blockIdx.x + 1] = sb[0];
+  }
+}
+
+__global__ void k_axpy_free(int64_t n, const double *du, const uint8_t *freem, double *u) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && freem[i]) u[i] += du[i];
+}
+
+__global__ void k_to_float(const double *src, float *dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)src[i];
+}
+
+// ----------------------------------------------------------------------------
+// Launch wrappers
+// ----------------------------------------------------------------------------
+template <int ETID>
+static hipError_t constitutive_et(Ctx &c, const ConstArgs &ca) {
+  using T = Et<ETID>;
+  constexpr int EPB = CT / T::NQ;
+  KC a;
+  a.coord = c.coord;
+  a.elem = c.elem;
+  a.ref = c.ref;
+  a.n_n = c.n_n;
+  a.n_e = c.n_e;
+  a.n_int = c.n_int;
+  a.u = ca.u;
+  a.m = c.mat;
+  a.ep = c.ep_s;
+  a.beta = c.beta_s;
+  a.kappa = c.kappa_s;
+  a.flag = c.flag;
+  a.desc = c.desc;
+  a.Fe = c.Fe;
+  a.emask = c.emask;
+  a.eps_out = ca.eps_out;
+  a.sig_out = ca.sig_out;
+  a.D_out = ca.D_out;
+  a.flag_out = ca.flag_out;
+  a.rm = ca.return_map;
+  a.commit = ca.commit;
+  a.force = ca.force;
+  const int grid = ceil_div(c.n_e, EPB);
+  if (grid == 0) return hipSuccess;
+  if (c.mat.model == EP_VM)
+    hipLaunchKernelGGL((k_constitutive<ETID, EP_VM>), dim3(grid), dim3(CT), 0, c.stream, a);
+  else
+    hipLaunchKernelGGL((k_constitutive<ETID, EP_DP>), dim3(grid), dim3(CT), 0, c.stream, a);
+  return hipGetLastError();
+}
+
+#define DISPATCH_ET(FN, ...)                                   \
+  switch (c.et) {                                              \
+    case ET_P1_2D: return FN<ET_P1_2D>(__VA_ARGS__);           \
+    case ET_Q1_2D: return FN<ET_Q1_2D>(__VA_ARGS__);           \
+    case ET_Q2_2D: return FN<ET_Q2_2D>(__VA_ARGS__);           \
+    case ET_P1_3D: return FN<ET_P1_3D>(__VA_ARGS__);           \
+    case ET_P2_3D: return FN<ET_P2_3D>(__VA_ARGS__);           \
+    case ET_Q1_3D: return FN<ET_Q1_3D>(__VA_ARGS__);           \
+    case ET_Q2_3D: return FN<ET_Q2_3D>(__VA_ARGS__);           \
+  }                                                            \
+  return hipErrorInvalidValue;
+
+hipError_t launch_constitutive(Ctx &c, const ConstArgs &a) { DISPATCH_ET(constitutive_et, c, a) }
+
+template <int ETID>
+static hipError_t geometry_et(Ctx &c, double *dphi, double *w, int32_t *bad) {
+  const int64_t n = c.n_int;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_geometry<ETID>), dim3(ceil_div(n, 128)), dim3(128), 0, c.stream, c.coord,
+                     c.elem, c.ref, c.n_n, c.n_e, dphi, w, bad);
+  return hipGetLastError();
+}
+hipError_t launch_geometry(Ctx &c, double *dphi, double *w, int32_t *bad) {
+  DISPATCH_ET(geometry_et, c, dphi, w, bad)
+}
+
+hipError_t launch_force_gather(Ctx &c, const double *f, double *F_out, double *r_out,
+                               double *partials, int nblk) {
+  if (nblk == 0) return hipSuccess;
+  if (c.dim == 2)
+    hipLaunchKernelGGL((k_force_gather<2>), dim3(nblk), dim3(256), 0, c.stream, c.n_n,
+                       c.n2e_ptr, c.n2e, c.Fe, f, c.freem, F_out, r_out, partials);
+  else
+    hipLaunchKernelGGL((k_force_gather<3>), dim3(nblk), dim3(256), 0, c.stream, c.n_n,
+                       c.n2e_ptr, c.n2e, c.Fe, f, c.freem, F_out, r_out, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(Ctx &c, const double *partials, int nblk, int width, double *out) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, c.stream, partials, nblk, width, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(Ctx &c, int kind, const void *src, const int32_t *perm, int64_t n,
+                          int32_t *out, int32_t *colour_first_block, int n_col,
+                          int32_t *colour_off, int32_t *totals, int32_t *) {
+  const int nblk = ceil_div(n, CMP_CHUNK);
+  if (nblk > c.cmp_cap) return hipErrorInvalidValue;
+  if (nblk > 0)
+    hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(CMP_THREADS), 0, c.stream, src, kind,
+                       perm, n, c.cmp_counts, c.cmp_counts2);
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, c.stream, c.cmp_counts,
+                     kind == 1 ? c.cmp_counts2 : (const int32_t *)nullptr, nblk, c.cmp_offsets,
+                     colour_first_block, n_col, colour_off, totals);
+  if (nblk > 0)
+    hipLaunchKernelGGL(k_compact_scatter, dim3(nblk), dim3(CMP_THREADS), 0, c.stream, src, kind,
+                       perm, n, c.cmp_offsets, out);
+  return hipGetLastError();
+}
+
+template <int ETID>
+static hipError_t elastic_et(Ctx &c) {
+  using Cfg = AsmCfg<ETID>;
+  for (int col = 0; col < c.n_col; ++col) {
+    KA a{};
+    a.coord = c.coord;
+    a.elem = c.elem;
+    a.ref = c.ref;
+    a.n_n = c.n_n;
+    a.n_int = c.n_int;
+    a.list = c.ecol_perm;
+    a.off = nullptr;
+    a.k0 = (int64_t)c.colour_first_block[col] * CMP_CHUNK;
+    a.k1 = a.k0 + c.colour_size[col];
+    a.bpos = c.bpos;
+    a.Kt = c.Ke;
+    a.elastic = 1;
+    a.G = c.mat.G;
+    a.K = c.mat.K;
+    const int64_t cnt = a.k1 - a.k0;
+    if (cnt == 0) continue;
+    const int grid = (int)(cnt < 8192 ? cnt : 8192);
+    hipLaunchKernelGGL((k_assemble<ETID, double>), dim3(grid), dim3(Cfg::BS), 0, c.stream, a);
+    RT(hipGetLastError());
+  }
+  return hipSuccess;
+}
+hipError_t launch_elastic_assembly(Ctx &c) { DISPATCH_ET(elastic_et, c) }
+
+template <int ETID>
+static hipError_t restore_et(Ctx &c) {
+  const int prev = c.asm_buf;
+  if (prev < 0) return hipSuccess;
+  const int grid = 2048;
+  if (c.opt.tangent_prec == EP_FP32)
+    hipLaunchKernelGGL((k_restore<ETID, float>), dim3(grid), dim3(64), 0, c.stream, c.plist[prev],
+                       c.coff[prev] + c.n_col, c.emask, c.bpos, c.Ke32, (float *)c.Kt);
+  else
+    hipLaunchKernelGGL((k_restore<ETID, double>), dim3(grid), dim3(64), 0, c.stream,
+                       c.plist[prev], c.coff[prev] + c.n_col, c.emask, c.bpos, c.Ke,
+                       (double *)c.Kt);
+  return hipGetLastError();
+}
+hipError_t launch_restore(Ctx &c) { DISPATCH_ET(restore_et, c) }
+
+template <int ETID>
+static hipError_t colour_et(Ctx &c, int colour, int epoch) {
+  using Cfg = AsmCfg<ETID>;
+  KA a{};
+  a.coord = c.coord;
+  a.elem = c.elem;
+  a.ref = c.ref;
+  a.n_n = c.n_n;
+  a.n_int = c.n_int;
+  a.desc = c.desc;
+  a.emask = c.emask;
+  a.list = c.plist[c.cur];
+  a.off = c.coff[c.cur];
+  a.colour = colour;
+  a.bpos = c.bpos;
+  a.Ke = c.Ke;
+  a.Ke32 = c.Ke32;
+  a.Kt = c.Kt;
+  a.epoch = c.epoch;
+  a.cur = epoch;
+  a.elastic = 0;
+  a.G = c.mat.G;
+  a.K = c.mat.K;
+  const int64_t cnt = c.colour_size[colour];
+  if (cnt == 0) return hipSuccess;
+  const int grid = (int)(cnt < 4096 ? cnt : 4096);
+  if (c.opt.tangent_prec == EP_FP32)
+    hipLaunchKernelGGL((k_assemble<ETID, float>), dim3(grid), dim3(Cfg::BS), 0, c.stream, a);
+  else
+    hipLaunchKernelGGL((k_assemble<ETID, double>), dim3(grid), dim3(Cfg::BS), 0, c.stream, a);
+  return hipGetLastError();
+}
+hipError_t launch_colour_assembly(Ctx &c, int colour, int epoch) {
+  DISPATCH_ET(colour_et, c, colour, epoch)
+}
+
+hipError_t launch_copy_ke_to_kt(Ctx &c) {
+  const int64_t n = c.nnzb * c.dim * c.dim;
+  if (c.opt.tangent_prec == EP_FP32)
+    return hipMemcpyAsync(c.Kt, c.Ke32, n * sizeof(float), hipMemcpyDeviceToDevice, c.stream);
+  return hipMemcpyAsync(c.Kt, c.Ke, n * sizeof(double), hipMemcpyDeviceToDevice, c.stream);
+}
+
+hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_float, dim3(ceil_div(n, 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_expand(Ctx &c, int which, int32_t *row_ptr, int32_t *col_idx,
+                             double *val) {
+  const int64_t n = c.n_dof + 1;
+  const int grid = ceil_div(n, 256);
+  const bool f32 = which == 1 && c.opt.tangent_prec == EP_FP32;
+  const void *v = which == 1 ? c.Kt : (const void *)c.Ke;
+#define CSRX(D, VT)                                                                          \
+  hipLaunchKernelGGL((k_csr_expand<D, VT>), dim3(grid), dim3(256), 0, c.stream, c.n_n, c.nnzb, \
+                     c.bptr, c.bcol, (const VT *)v, row_ptr, col_idx, val)
+  if (c.dim == 2) {
+    if (f32) CSRX(2, float); else CSRX(2, double);
+  } else {
+    if (f32) CSRX(3, float); else CSRX(3, double);
+  }
+#undef CSRX
+  return hipGetLastError();
+}
+
+template <int ETID>
+static hipError_t pos_et(Ctx &c, int32_t *pos) {
+  using T = Et<ETID>;
+  const int64_t n = c.n_e * T::NP * T::NP;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_pos_expand<ETID>), dim3(ceil_div(n, 256)), dim3(256), 0, c.stream, c.n_e,
+                     c.elem, c.bptr, c.bpos, pos);
+  return hipGetLastError();
+}
+hipError_t launch_pos_expand(Ctx &c, int32_t *pos) { DISPATCH_ET(pos_et, c, pos) }
+
+hipError_t launch_diag_inv(Ctx &c) {
+  const int grid = ceil_div(c.n_dof, 256);
+  const bool f32 = c.opt.tangent_prec == EP_FP32;
+#define DG(D, VT)                                                                               \
+  hipLaunchKernelGGL((k_diag_inv<D, VT>), dim3(grid), dim3(256), 0, c.stream, c.n_n, c.bdiag, \
+                     (const VT *)c.Kt, c.freem, c.dinv)
+  if (c.dim == 2) {
+    if (f32) DG(2, float); else DG(2, double);
+  } else {
+    if (f32) DG(3, float); else DG(3, double);
+  }
+#undef DG
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv(Ctx &c, const double *x, double *y, bool, double *partials) {
+  const int grid = ceil_div(c.n_dof, 256);
+  const bool f32 = c.opt.tangent_prec == EP_FP32;
+#define SPMV(D, VT)                                                                           \
+  hipLaunchKernelGGL((k_spmv<D, VT>), dim3(grid), dim3(256), 0, c.stream, c.n_n, c.bptr,      \
+                     c.bcol, (const VT *)c.Kt, x, c.freem, y, partials, (const double *)nullptr, \
+                     (const double *)nullptr, (double *)nullptr, (const double *)nullptr)
+  if (c.dim == 2) {
+    if (f32) SPMV(2, float); else SPMV(2, double);
+  } else {
+    if (f32) SPMV(3, float); else SPMV(3, double);
+  }
+#undef SPMV
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_init(Ctx &c, const double *b, double *x) {
+  const int grid = ceil_div(c.n_dof, 256);
+  c.pcur = 0;
+  hipLaunchKernelGGL(k_pcg_init, dim3(grid), dim3(256), 0, c.stream, c.n_dof, b, c.freem, x, c.r,
+                     c.pz, c.pp[0], c.dinv, c.partials);
+  RT(hipGetLastError());
+  return hipSuccess;
+}
+
+hipError_t launch_pcg_beta_init(Ctx &c, double rtol);
+
+hipError_t launch_pcg_iteration(Ctx &c, double *x) {
+  const int grid = ceil_div(c.n_dof, 256);
+  const bool f32 = c.opt.tangent_prec == EP_FP32;
+  double *pold = c.pp[c.pcur], *pnew = c.pp[1 - c.pcur];
+  int tok = c.prof_begin(PROF_SPMV);
+#define SPMVF(D, VT)                                                                          \
+  hipLaunchKernelGGL((k_spmv<D, VT>), dim3(grid), dim3(256), 0, c.stream, c.n_n, c.bptr,      \
+                     c.bcol, (const VT *)c.Kt, (const double *)nullptr, c.freem, c.pq,          \
+                     c.partials, c.pz, pold, pnew, c.sc)
+  if (c.dim == 2) {
+    if (f32) SPMVF(2, float); else SPMVF(2, double);
+  } else {
+    if (f32) SPMVF(3, float); else SPMVF(3, double);
+  }
+#undef SPMVF
+  c.prof_end(tok);
+  RT(hipGetLastError());
+  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(256), 0, c.stream, c.partials, grid, c.sc);
+  RT(hipGetLastError());
+  tok = c.prof_begin(PROF_PCGVEC);
+  hipLaunchKernelGGL(k_pcg_update, dim3(grid), dim3(256), 0, c.stream, c.n_dof, x, pnew, c.r,
+                     c.pq, c.pz, c.dinv, c.sc, c.partials);
+  c.prof_end(tok);
+  RT(hipGetLastError());
+  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(256), 0, c.stream, c.partials, grid, c.sc, 0, 0.0);
+  RT(hipGetLastError());
+  c.pcur = 1 - c.pcur;
+  return hipSuccess;
+}
+
+hipError_t launch_pcg_beta_init(Ctx &c, double rtol) {
+  const int grid = ceil_div(c.n_dof, 256);
+  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(256), 0, c.stream, c.partials, grid, c.sc, 1, rtol);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_free(Ctx &c, const double *du, double *u) {
+  if (c.n_dof == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpy_free, dim3(ceil_div(c.n_dof, 256)), dim3(256), 0, c.stream, c.n_dof,
+                     du, c.freem, u);
+  return hipGetLastError();
+}
+
+}  // namespace ep

@@ -1,0 +1,193 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle on the
+same seeded inputs.  Integer outputs (CSR pattern, position map, plastic
+sets, flags) must match bit for bit; FP64 outputs within 1e-12 relative to
+the field's scale (tolerances derived in each test)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from gpu_cases import CASES, make_case  # noqa: E402
+from paper_1805_04155_amd import _ep  # noqa: E402
+
+RTOL = 1e-12
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def close(a, b, tol=RTOL, scale=None):
+    a, b = np.asarray(a), np.asarray(b)
+    s = np.abs(b).max() if scale is None else scale
+    err = np.abs(a - b).max() if a.size else 0.0
+    assert err <= tol * s, f"max abs err {err:.3e} > {tol:.1e} * scale {s:.3e}"
+
+
+class Case:
+    def __init__(self, name):
+        self.name = name
+        self.mesh, self.free, self.mat, self.u, (self.ep, self.beta, self.kappa) = make_case(name)
+        self.dim = self.mesh.dim
+        self.ctx = _ep.Context(self.mesh, self.free, self.mat)
+        self.ctx.set_state(self.ep, self.beta if self.mat.model == "VM" else None,
+                           self.kappa if self.mat.model == "DP" else None)
+        self.dphi, self.w = O.geometry(self.mesh)
+        self.pattern = O.pattern(self.mesh)
+
+    def oracle_const(self, u):
+        eps = O.strain(self.mesh, self.dphi, u)
+        return O.constitutive(self.mat, eps, O.state_to_ip6(self.ep, self.dim),
+                              O.state_to_ip6(self.beta, self.dim),
+                              self.kappa if self.mat.model == "DP" else np.zeros(self.mesh.n_int))
+
+    def du(self):
+        return self.ctx.tensor(self.u)
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    c = Case(request.param)
+    yield c
+    c.ctx.close()
+
+
+def _voigt_from_soa(arr, dim):
+    """GPU SoA (n_comp, n_int) -> oracle-style (n_int, 6)."""
+    a = np.asarray(arr)
+    out = np.zeros((a.shape[1], 6))
+    if dim == 3:
+        out[:] = a.T
+    elif a.shape[0] == 3:       # in-plane strain 11, 22, 12
+        out[:, [0, 1, 3]] = a.T
+    else:                       # stress / state 11, 22, 33, 12
+        out[:, :4] = a.T
+    return out
+
+
+def test_pattern_and_position_map_bit_exact(case):
+    rp, ci, _ = case.ctx.csr(0)
+    orp, oci = case.pattern
+    assert np.array_equal(_np(rp), orp)
+    assert np.array_equal(_np(ci), oci)
+    pos = _np(case.ctx.position_map())
+    assert np.array_equal(pos, O.position_map(case.mesh, orp, oci))
+
+
+def test_geometry(case):
+    dphi, w = case.ctx.geometry()
+    close(_np(w), case.w)
+    close(_np(dphi), case.dphi)
+
+
+def test_strain(case):
+    eps = _voigt_from_soa(_np(case.ctx.strain(case.du())), case.dim)
+    ref = O.strain(case.mesh, case.dphi, case.u)
+    close(eps, ref)
+
+
+def test_return_map_and_tangent(case):
+    sig, D, flag = case.ctx.constitutive(case.du())
+    ref = case.oracle_const(case.u)
+    assert np.array_equal(_np(flag), ref["flag"])
+    close(_voigt_from_soa(_np(sig), case.dim), ref["sig"])
+    n = case.mesh.n_int
+    Dg = _np(D).T.reshape(n, case.ctx.sizes["n_str"], case.ctx.sizes["n_str"])
+    Dref = ref["D"] if case.dim == 3 else ref["D"][:, [0, 1, 3]][:, :, [0, 1, 3]]
+    close(Dg, Dref, scale=case.mat.E)
+
+
+def _row_scaled_close(a_val, b_val, row_ptr, scale_val, tol=RTOL):
+    rows = np.repeat(np.arange(len(row_ptr) - 1), np.diff(row_ptr))
+    rmax = np.zeros(len(row_ptr) - 1)
+    np.maximum.at(rmax, rows, np.abs(scale_val))
+    err = np.abs(a_val - b_val) / rmax[rows]
+    assert err.max() <= tol, f"row-relative error {err.max():.3e}"
+
+
+def test_elastic_stiffness(case):
+    rp, ci, val = case.ctx.csr(0)
+    n = case.mesh.n_int
+    D0 = O.constitutive(case.mat, np.zeros((n, 6)), np.zeros((n, 6)))["D"]
+    _, _, ref = O.assemble(case.mesh, case.dphi, case.w, D0, *case.pattern)
+    _row_scaled_close(_np(val), ref, case.pattern[0], ref)
+
+
+def test_incremental_tangent_over_iterations(case):
+    """K_elast + B^T (D_t - D_e) B through several constitutive/assembly
+    rounds with changing plastic sets (exercises restore and epochs) equals
+    the oracle's plain sum w B^T D_t B each time.  The split cancels up to
+    |K_elast|, so rows are scaled by max(|K_t|, |K_elast|) of the row."""
+    _, _, Ke = case.ctx.csr(0)
+    Ke = _np(Ke)
+    for k, s in enumerate([1.0, 0.3, 1.6, 0.0, 1.0]):
+        u = case.u * s
+        case.ctx.constitutive(case.ctx.tensor(u), sig=False, D=False, flag=False)
+        case.ctx.assemble_tangent()
+        _, _, val = case.ctx.csr(1)
+        ref = case.oracle_const(u)
+        _, _, Kt = O.assemble(case.mesh, case.dphi, case.w, ref["D"], *case.pattern)
+        _row_scaled_close(_np(val), Kt, case.pattern[0], np.maximum(np.abs(Kt), np.abs(Ke)))
+
+
+def test_internal_force(case):
+    case.ctx.constitutive(case.du(), sig=False, D=False, flag=False)
+    F = _np(case.ctx.internal_force())
+    ref = case.oracle_const(case.u)
+    Fo = O.internal_force(case.mesh, case.dphi, case.w, ref["sig"])
+    close(F, Fo)
+
+
+def test_plastic_sets_bit_exact(case):
+    case.ctx.constitutive(case.du(), sig=False, D=False, flag=False)
+    ip, el = case.ctx.plastic()
+    ref = case.oracle_const(case.u)
+    pl = np.nonzero(ref["flag"])[0]
+    assert np.array_equal(_np(ip), pl)
+    assert np.array_equal(_np(el), np.unique(pl // case.mesh.n_q))
+
+
+def test_commit_state(case):
+    ctx = _ep.Context(case.mesh, case.free, case.mat)
+    try:
+        ctx.set_state(case.ep, case.beta if case.mat.model == "VM" else None,
+                      case.kappa if case.mat.model == "DP" else None)
+        ctx.commit_step(case.du())
+        ep, beta, kappa = (_np(t) for t in ctx.get_state())
+        ref = case.oracle_const(case.u)
+        scale = np.abs(ref["ep"]).max()
+        close(_voigt_from_soa(ep, case.dim), ref["ep"], scale=scale)
+        if case.mat.model == "VM":
+            close(_voigt_from_soa(beta, case.dim), ref["beta"])
+        else:
+            close(kappa, ref["kappa"])
+    finally:
+        ctx.close()
+
+
+def test_spmv_matches_csr_product(case):
+    case.ctx.constitutive(case.du(), sig=False, D=False, flag=False)
+    case.ctx.assemble_tangent()
+    rp, ci, val = (_np(t) for t in case.ctx.csr(1))
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(case.mesh.n_dof)
+    y = _np(case.ctx.spmv(case.ctx.tensor(x)))
+    K = O.csr_to_scipy(rp, ci, val, case.mesh.n_dof)
+    ref = (K @ x) * case.free
+    close(y, ref)
+
+
+def test_determinism(case):
+    outs = []
+    for _ in range(2):
+        case.ctx.constitutive(case.du(), sig=False, D=False, flag=False)
+        case.ctx.assemble_tangent()
+        _, _, val = case.ctx.csr(1)
+        F = case.ctx.internal_force()
+        outs.append((_np(val), _np(F)))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
