@@ -4,7 +4,7 @@
 A step is one pass of the hot path over the whole workload: strain and return
 map at every integration point with the fused constitutive kernel, plastic-
 element compaction, the incremental tangent K_elast + B^T (D - D_elast) B
-(restore + colour rounds) and the internal force / residual.  The metric is
+(colour rounds over the plastic work list) and the internal force / residual.  The metric is
 millions of integration points per second.  Inputs are resident in HBM when
 the timed region starts.
 
@@ -49,7 +49,7 @@ def kernel_bytes(mesh, mat, counts, tangent_bytes):
     n_dof = D * n_n
     nsc = 6 if D == 3 else 4
     ndesc = 10 if D == 3 else 7
-    pe, pi, restored = counts["plastic_elems"], counts["plastic_ips"], counts["restored"]
+    pe, pi, listed = counts["plastic_elems"], counts["plastic_ips"], counts["listed"]
     state = (2 * nsc if mat.model == "VM" else nsc + 1) * 8
     s = tangent_bytes
     blk = NP * NP
@@ -58,11 +58,13 @@ def kernel_bytes(mesh, mat, counts, tangent_bytes):
         # flag, descriptor of plastic points, element force vectors, mask
         "constitutive": 2 * 8 * n_dof + 4 * NP * n_e + state * n_int + n_int
         + 8 * ndesc * pi + 8 * D * NP * n_e + 4 * n_e,
-        # position map, epoch read + write, base value read, tangent write,
-        # descriptors, connectivity and coordinates of each plastic element
-        "assembly": pe * (blk * (4 + 8 + 2 * D * D * s) + NP * (4 + 8 * D) + 4)
+        # per listed element: position map, epoch read + write, base value
+        # read, tangent write, mask; per plastic element its connectivity and
+        # coordinates; per plastic point its tangent descriptor
+        "assembly": listed * (blk * (4 + 8 + 2 * D * D * s) + 4) + pe * NP * (4 + 8 * D)
         + 8 * ndesc * pi,
-        "restore": restored * blk * (4 + 2 * D * D * s),
+        # colour-major order and two masks read, list written
+        "compaction": counts["n_perm"] * 4 + 8 * n_e + 4 * listed,
         "force": 4 * (n_n + 1) + 4 * NP * n_e + 8 * D * NP * n_e + n_dof * (8 + 1 + 8),
     }
 
@@ -162,11 +164,12 @@ def main():
     ms = 1e3 * t / args.steps
     value = mesh.n_int / (ms / 1e3) / 1e6
 
-    counts = {"plastic_elems": n_el, "plastic_ips": n_ip, "restored": 0}
+    counts = {"plastic_elems": n_el, "plastic_ips": n_ip, "listed": n_el,
+              "n_perm": mesh.n_elems}
     kb = kernel_bytes(mesh, mat, counts, tb)
     per_kernel = {}
-    for name, key in (("constitutive", "constitutive"), ("assembly", "assembly"),
-                      ("restore", "restore"), ("force", "force")):
+    for name, key in (("constitutive", "constitutive"), ("compaction", "compaction"),
+                      ("assembly", "assembly"), ("force", "force")):
         tms, n = prof[key]
         if n == 0:
             continue

@@ -175,10 +175,13 @@ ep_status ep_constitutive(ep_ctx *ctx, const double *u, double *sig, double *D,
                           uint8_t *flag);
 
 /* K_tangent = K_elast + B^T (D_tangent - D_elast) B (eq. K-split) for the
- * last ep_constitutive: compaction of the plastic elements (grouped by
- * colour), restore of the blocks touched by the previous assembly, and the
- * element-local products over plastic points scattered through the
- * position map, one colour at a time (deterministic, no float atomics).
+ * last ep_constitutive.  The work list (built by ep_constitutive) holds the
+ * elements plastic now or at the previous assembly, grouped by colour; for
+ * each, the element-local products over its plastic points are added to
+ * K_elast (blocks not yet written in this assembly) or to K_tangent through
+ * the position map, one colour at a time (deterministic, no float atomics);
+ * elements that left the plastic set restore K_elast on their blocks.  Cost
+ * is proportional to that list, not to the mesh.
  * Returns EP_ESTATE if ep_constitutive has not run since setup or commit. */
 ep_status ep_assemble_tangent(ep_ctx *ctx);
 
@@ -229,7 +232,7 @@ ep_status ep_pcg(ep_ctx *ctx, const double *b, double *x, double rtol, int32_t m
 /* Per-kernel timing with HIP events recorded on the context's stream
  * around every launch of the named kernels.  ep_profile_read returns the
  * summed duration (ms) and the launch count of kernel id k (0 constitutive,
- * 1 compaction, 2 restore, 3 colour assembly, 4 force gather, 5 SpMV,
+ * 1 compaction, 2 unused, 3 colour assembly, 4 force gather, 5 SpMV,
  * 6 PCG vector update) and resets it.  Synchronises. */
 ep_status ep_profile(ep_ctx *ctx, int32_t enable);
 ep_status ep_profile_read(ep_ctx *ctx, int32_t k, double *ms, int64_t *count);

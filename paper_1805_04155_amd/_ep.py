@@ -16,7 +16,7 @@ EP_OK, EP_EINVAL, EP_ENOMEM, EP_EDEVICE, EP_ENOTCONV, EP_ESTATE = 0, -1, -2, -3,
 EP_P1, EP_P2, EP_Q1, EP_Q2 = 1, 2, 3, 4
 EP_VM, EP_DP = 1, 2
 EP_FP64, EP_FP32, EP_BF16 = 0, 1, 2
-PROF = dict(constitutive=0, compaction=1, restore=2, assembly=3, force=4, spmv=5, pcg_vec=6)
+PROF = dict(constitutive=0, compaction=1, assembly=3, force=4, spmv=5, pcg_vec=6)
 
 ETYPE = {"P1_2D": (2, EP_P1), "Q1_2D": (2, EP_Q1), "Q2_2D": (2, EP_Q2), "P1_3D": (3, EP_P1),
          "P2_3D": (3, EP_P2), "Q1_3D": (3, EP_Q1), "Q2_3D": (3, EP_Q2)}

@@ -189,8 +189,8 @@ void free_ctx(Ctx *c) {
   void *ptrs[] = {c->coord, c->elem, c->freem, c->ref, c->bptr, c->bcol, c->bdiag, c->bpos,
                   c->Ke, c->Ke32, c->Kt, c->epoch, c->n2e_ptr, c->n2e, c->ecol_perm,
                   c->d_colour_first_block, c->ep_s, c->beta_s, c->kappa_s, c->flag, c->desc,
-                  c->Fe, c->emask, c->plist[0], c->plist[1], c->coff[0], c->coff[1], c->ptotals,
-                  c->cmp_counts, c->cmp_counts2, c->cmp_offsets, c->F, c->r, c->partials,
+                  c->Fe, c->em[0], c->em[1], c->plist, c->coff, c->ptotals, c->cmp_counts,
+                  c->cmp_counts2, c->cmp_counts3, c->cmp_offsets, c->F, c->r, c->partials,
                   c->norms, c->pz, c->pp[0], c->pp[1], c->pq, c->px, c->dinv, c->sc,
                   c->iscratch};
   for (void *p : ptrs)
@@ -261,17 +261,18 @@ ep_status do_constitutive(Ctx *c, const double *u, double *sig, double *D, uint8
   a.flag_out = flag;
   a.commit = false;
   a.force = true;
+  // the plastic masks go to the buffer the last assembly did not use
+  c->em_cur = c->em_asm == 0 ? 1 : 0;
   int tok = c->prof_begin(PROF_CONST);
   HIPC(launch_constitutive(*c, a));
   c->prof_end(tok);
-  // plastic elements grouped by colour, into the buffer not used by the last
-  // assembly
-  const int nb = c->asm_buf == 0 ? 1 : 0;
+  // assembly work list, grouped by colour: elements plastic now or at the
+  // last assembly
   tok = c->prof_begin(PROF_COMPACT);
-  HIPC(launch_compact(*c, 1, c->emask, c->ecol_perm, c->n_perm, c->plist[nb],
-                      c->d_colour_first_block, c->n_col, c->coff[nb], c->ptotals, nullptr));
+  HIPC(launch_compact(*c, 1, c->em[c->em_cur], c->em_asm >= 0 ? c->em[c->em_asm] : nullptr,
+                      c->ecol_perm, c->n_perm, c->plist, c->d_colour_first_block, c->n_col,
+                      c->coff, c->ptotals));
   c->prof_end(tok);
-  c->cur = nb;
   c->have_const = true;
   return EP_OK;
 }
@@ -281,19 +282,13 @@ ep_status do_assemble(Ctx *c) {
     c->err = "ep_assemble_tangent: no constitutive evaluation since setup or commit";
     return EP_ESTATE;
   }
-  if (c->have_prev) {
-    const int tok = c->prof_begin(PROF_RESTORE);
-    HIPC(launch_restore(*c));
-    c->prof_end(tok);
-  }
   const int epoch = ++c->epoch_counter;
   for (int col = 0; col < c->n_col; ++col) {
     const int tok = c->prof_begin(PROF_ASSEMBLE);
     HIPC(launch_colour_assembly(*c, col, epoch));
     c->prof_end(tok);
   }
-  c->have_prev = true;
-  c->asm_buf = c->cur;
+  c->em_asm = c->em_cur;
   return EP_OK;
 }
 
@@ -576,17 +571,17 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   SETUP_HIP(dalloc(&c->flag, n_int));
   SETUP_HIP(dalloc(&c->desc, c->n_desc * n_int));
   SETUP_HIP(dalloc(&c->Fe, n_e * n_p * dim));
-  SETUP_HIP(dalloc(&c->emask, n_e));
-  for (int k = 0; k < 2; ++k) {
-    SETUP_HIP(dalloc(&c->plist[k], n_e));
-    SETUP_HIP(dalloc(&c->coff[k], n_col + 1));
-  }
-  SETUP_HIP(dalloc(&c->ptotals, 4));
+  SETUP_HIP(dalloc(&c->em[0], n_e));
+  SETUP_HIP(dalloc(&c->em[1], n_e));
+  SETUP_HIP(dalloc(&c->plist, n_e));
+  SETUP_HIP(dalloc(&c->coff, n_col + 1));
+  SETUP_HIP(dalloc(&c->ptotals, 8));
   SETUP_HIP(dalloc(&c->iscratch, std::max(n_int, n_e)));
   c->cmp_cap = std::max<int64_t>((n_int + CMP_CHUNK - 1) / CMP_CHUNK, c->n_perm / CMP_CHUNK) + 2;
   c->cmp_cap = std::max<int64_t>(c->cmp_cap, (n_e + CMP_CHUNK - 1) / CMP_CHUNK + 2);
   SETUP_HIP(dalloc(&c->cmp_counts, c->cmp_cap));
   SETUP_HIP(dalloc(&c->cmp_counts2, c->cmp_cap));
+  SETUP_HIP(dalloc(&c->cmp_counts3, c->cmp_cap));
   SETUP_HIP(dalloc(&c->cmp_offsets, c->cmp_cap + 1));
   SETUP_HIP(dalloc(&c->F, n_dof));
   SETUP_HIP(dalloc(&c->r, n_dof));
@@ -619,14 +614,15 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   SETUP_HIP(hipMemsetAsync(c->ep_s, 0, sizeof(double) * c->n_sc * n_int, s));
   if (c->beta_s) SETUP_HIP(hipMemsetAsync(c->beta_s, 0, sizeof(double) * c->n_sc * n_int, s));
   SETUP_HIP(hipMemsetAsync(c->kappa_s, 0, sizeof(double) * n_int, s));
-  SETUP_HIP(hipMemsetAsync(c->emask, 0, sizeof(uint32_t) * std::max<int64_t>(n_e, 1), s));
+  for (int k = 0; k < 2; ++k)
+    SETUP_HIP(hipMemsetAsync(c->em[k], 0, sizeof(uint32_t) * std::max<int64_t>(n_e, 1), s));
   SETUP_HIP(hipMemsetAsync(c->epoch, 0, sizeof(int32_t) * std::max<int64_t>(nnzb, 1), s));
   SETUP_HIP(hipMemsetAsync(c->Ke, 0, sizeof(double) * std::max<int64_t>(1, nnzb * dim * dim), s));
-  SETUP_HIP(hipMemsetAsync(c->ptotals, 0, sizeof(int32_t) * 4, s));
-  for (int k = 0; k < 2; ++k) SETUP_HIP(hipMemsetAsync(c->coff[k], 0, sizeof(int32_t) * (n_col + 1), s));
+  SETUP_HIP(hipMemsetAsync(c->ptotals, 0, sizeof(int32_t) * 8, s));
+  SETUP_HIP(hipMemsetAsync(c->coff, 0, sizeof(int32_t) * (n_col + 1), s));
 
   // geometry check: det J > 0 at every point
-  int32_t *bad = reinterpret_cast<int32_t *>(c->ptotals) + 2;
+  int32_t *bad = c->ptotals + 7;
   SETUP_HIP(launch_geometry(*c, nullptr, nullptr, bad));
   int32_t bad_h = 0;
   SETUP_HIP(hipMemcpyAsync(&bad_h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -641,8 +637,8 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   SETUP_HIP(launch_copy_ke_to_kt(*c));
   SETUP_HIP(hipStreamSynchronize(s));
   c->epoch_counter = 0;
-  c->cur = 0;
-  c->have_prev = false;
+  c->em_cur = 0;
+  c->em_asm = -1;
   c->have_const = false;
   *out = reinterpret_cast<ep_ctx *>(c);
   return EP_OK;
@@ -706,7 +702,7 @@ ep_status ep_get_state(ep_ctx *ctx, double *ep, double *beta, double *kappa) {
 ep_status ep_geometry(ep_ctx *ctx, double *dphi, double *w) {
   CHECK_CTX(ctx);
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
-  int32_t *bad = reinterpret_cast<int32_t *>(c->ptotals) + 2;
+  int32_t *bad = c->ptotals + 7;
   HIPC(launch_geometry(*c, dphi, w, bad));
   return EP_OK;
 }
@@ -754,13 +750,13 @@ ep_status ep_newton_step(ep_ctx *ctx, const double *f, double *u, ep_newton_info
   st = do_residual(c, f, nullptr);
   if (st) return st;
   HIPC(hipMemcpyAsync(c->norms_h, c->norms, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  int32_t tot[2];
-  HIPC(hipMemcpyAsync(tot, c->ptotals, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  int32_t tot[3];
+  HIPC(hipMemcpyAsync(tot, c->ptotals, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIPC(hipStreamSynchronize(c->stream));
   info->res_norm = std::sqrt(c->norms_h[0]);
   info->f_norm = std::sqrt(c->norms_h[1]);
   info->res_rel = info->f_norm > 0 ? info->res_norm / info->f_norm : info->res_norm;
-  info->n_plastic_elem = tot[0];
+  info->n_plastic_elem = tot[2];
   info->n_plastic_ip = tot[1];
   if (info->res_rel <= c->opt.newton_rtol) {
     info->converged = 1;
@@ -799,17 +795,17 @@ ep_status ep_get_plastic(ep_ctx *ctx, int32_t *ip, int64_t *n_ip, int32_t *elem,
     c->err = "ep_get_plastic: no constitutive evaluation";
     return EP_ESTATE;
   }
-  int32_t *tot = c->ptotals + 2;  // [2], [3]: scratch totals
-  int32_t th[2] = {0, 0};
-  // elements (ascending) with their plastic-point counts
-  HIPC(launch_compact(*c, 1, c->emask, nullptr, c->n_e, elem ? elem : c->iscratch, nullptr, 0,
-                      nullptr, tot, nullptr));
-  HIPC(hipMemcpyAsync(th, tot, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  int32_t *tot = c->ptotals + 4;  // scratch totals
+  int32_t th[3] = {0, 0, 0};
+  // plastic elements (ascending) and the plastic-point count
+  HIPC(launch_compact(*c, 1, c->em[c->em_cur], nullptr, nullptr, c->n_e, elem ? elem : c->iscratch,
+                      nullptr, 0, nullptr, tot));
+  HIPC(hipMemcpyAsync(th, tot, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIPC(hipStreamSynchronize(c->stream));
   if (n_elem) *n_elem = th[0];
   if (n_ip) *n_ip = th[1];
   if (ip) {
-    HIPC(launch_compact(*c, 0, c->flag, nullptr, c->n_int, ip, nullptr, 0, nullptr, tot, nullptr));
+    HIPC(launch_compact(*c, 0, c->flag, nullptr, nullptr, c->n_int, ip, nullptr, 0, nullptr, tot));
     HIPC(hipMemcpyAsync(th, tot, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     HIPC(hipStreamSynchronize(c->stream));
     if (n_ip) *n_ip = th[0];

@@ -36,7 +36,7 @@ constexpr int CMP_ITEMS = 8;
 constexpr int CMP_CHUNK = CMP_THREADS * CMP_ITEMS;
 
 // Kernel ids for ep_profile.
-enum ProfId { PROF_CONST = 0, PROF_COMPACT, PROF_RESTORE, PROF_ASSEMBLE, PROF_FORCE, PROF_SPMV,
+enum ProfId { PROF_CONST = 0, PROF_COMPACT, PROF_UNUSED2, PROF_ASSEMBLE, PROF_FORCE, PROF_SPMV,
               PROF_PCGVEC, PROF_COUNT };
 
 struct Ctx;
@@ -57,11 +57,15 @@ hipError_t launch_geometry(Ctx &c, double *dphi, double *w, int32_t *bad_count);
 hipError_t launch_force_gather(Ctx &c, const double *f, double *F_out, double *r_out,
                                double *partials, int nblk);
 hipError_t launch_reduce(Ctx &c, const double *partials, int nblk, int width, double *out);
-hipError_t launch_compact(Ctx &c, int kind, const void *src, const int32_t *perm, int64_t n,
-                          int32_t *out, int32_t *colour_first_block, int n_col,
-                          int32_t *colour_off, int32_t *total, int32_t *total_bits);
+// Stable compaction of items i < n (through perm when given, -1 = padding)
+// with predicate (src[item] | src2[item]) != 0; kind 0: uint8 src, kind 1:
+// uint32 src (src2 optional, uint32).  totals[0] = selected items,
+// totals[1] = set bits of src, totals[2] = items with src != 0.
+hipError_t launch_compact(Ctx &c, int kind, const void *src, const uint32_t *src2,
+                          const int32_t *perm, int64_t n, int32_t *out,
+                          int32_t *colour_first_block, int n_col, int32_t *colour_off,
+                          int32_t *totals);
 hipError_t launch_elastic_assembly(Ctx &c);
-hipError_t launch_restore(Ctx &c);
 hipError_t launch_colour_assembly(Ctx &c, int colour, int epoch);
 hipError_t launch_copy_ke_to_kt(Ctx &c);
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t s);
@@ -122,20 +126,24 @@ struct Ctx {
   uint8_t *flag = nullptr;     // [n_int]
   double *desc = nullptr;      // [n_desc][n_int]
   double *Fe = nullptr;        // [n_e*n_p][dim]
-  uint32_t *emask = nullptr;   // [n_e]
+  // plastic-point bitmask per element, two buffers: the one written by the
+  // last constitutive pass and the one the last assembly used
+  uint32_t *em[2] = {nullptr, nullptr};   // [n_e] each
+  int em_cur = 0;
+  int em_asm = -1;                        // -1: no assembly yet
   bool have_const = false;
 
-  // plastic element lists (colour-major), double-buffered
-  int32_t *plist[2] = {nullptr, nullptr};
-  int32_t *coff[2] = {nullptr, nullptr};   // [n_col+1] each
-  int32_t *ptotals = nullptr;              // [4]: total elems, total plastic ips, ...
-  int cur = 0;          // list written by the last constitutive pass
-  int asm_buf = -1;     // list used by the last assembly (-1: none yet)
-  bool have_prev = false;
+  // work list of the assembly (colour-major): elements plastic now or at
+  // the last assembly; coff[c] .. coff[c+1] is colour c's segment
+  int32_t *plist = nullptr;
+  int32_t *coff = nullptr;                 // [n_col+1]
+  int32_t *ptotals = nullptr;              // [8]: list length, plastic points,
+                                           // plastic elements, scratch
   int32_t *iscratch = nullptr;  // [max(n_int, n_e)] ascending plastic lists
 
   // compaction scratch
-  int32_t *cmp_counts = nullptr, *cmp_counts2 = nullptr, *cmp_offsets = nullptr;
+  int32_t *cmp_counts = nullptr, *cmp_counts2 = nullptr, *cmp_counts3 = nullptr,
+          *cmp_offsets = nullptr;
   int64_t cmp_cap = 0;  // blocks
 
   // vectors

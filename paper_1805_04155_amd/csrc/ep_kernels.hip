@@ -443,12 +443,22 @@ __global__ void k_geometry(const double *coord, const int32_t *elem, const doubl
 // ----------------------------------------------------------------------------
 // Element-local tangent products scattered through the position map.
 //   elastic = 1: K_elast, C at every point, accumulated into Ke (setup).
-//   elastic = 0: Delta K_e = sum_{plastic q} w_q B_q^T (D_q - C) B_q added to
-//                the base value (K_elast if the block was not touched yet in
-//                this assembly, else K_tangent), blocks stamped with the
-//                assembly epoch.
-// One workgroup per element of the colour segment; one thread per node pair
-// (p, p'), which owns the dim x dim block.
+//   elastic = 0: for every element of the colour's work list (plastic now,
+//                or plastic at the last assembly), Delta K_e = sum over its
+//                plastic points of w_q B_q^T (D_q - C) B_q is added to the
+//                base value of each node block: K_elast if the block was not
+//                written yet in this assembly (epoch != cur), else K_tangent.
+//                An element that left the plastic set contributes zero and
+//                thereby restores K_elast on its untouched blocks.
+// Per plastic point q the Voigt matrix M_q = w_q (D_q - C) (or w_q C) is
+// formed from the tangent descriptor, then H_q = M_q B_q column by column
+// (three non-zeros per column of B in 3D, two in 2D), and each node block is
+// B_p^T H_p' summed over q.  The element matrix is symmetric (associative
+// models), so one thread owns a node pair p <= p' and writes the block and
+// its transpose.  One workgroup per element; the position-map and epoch
+// loads are issued with the coordinate gather and the base values before
+// the products, so their latency overlaps.  Points are processed in chunks
+// of QC so that the per-point tables fit in LDS.
 // ----------------------------------------------------------------------------
 struct KA {
   const double *coord;
@@ -458,7 +468,7 @@ struct KA {
   const double *desc;
   const uint32_t *emask;
   const int32_t *list;
-  const int32_t *off;  // device segment bounds (plastic lists) or nullptr
+  const int32_t *off;  // device segment bounds (work lists) or nullptr
   int colour;
   int64_t k0, k1;      // host segment bounds when off == nullptr
   const int32_t *bpos;
@@ -474,162 +484,234 @@ struct KA {
 template <int ETID>
 struct AsmCfg {
   using T = Et<ETID>;
-  static constexpr int a = T::NP * T::NP > T::NQ * T::NP ? T::NP * T::NP : T::NQ * T::NP;
-  static constexpr int BS = a <= 64 ? 64 : ((a + 63) / 64) * 64;
+  static constexpr int NPAIR = T::NP * (T::NP + 1) / 2;
+  static constexpr int BS = NPAIR <= 64 ? 64 : (NPAIR <= 128 ? 128 : 256);
+  static constexpr int NBT = (NPAIR + BS - 1) / BS;
+  static constexpr int QC = T::NQ <= 11 ? T::NQ : 9;  // points per LDS chunk
+  static constexpr int WPE = T::D == 2 ? 6 : 4;       // occupancy target (waves/SIMD)
 };
 
+// Voigt M = C + (alpha DEV + b n n^T + g (n 1^T + 1 n^T) + d 1 1^T) scaled by
+// w, in the stored components (3D: 6, plane strain: 11, 22, 12).
+template <int D>
+__device__ inline void tangent_matrix(const double *desc, bool elastic, double G, double K,
+                                      double w, double *M) {
+  constexpr int NS = D == 3 ? 6 : 3;
+  constexpr int NN = NS;
+  double n[NS], al, be, ga, de;
+  if (elastic) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) n[i] = 0.0;
+    al = 2.0 * G;
+    be = 0.0;
+    ga = 0.0;
+    de = K;
+  } else {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) n[i] = desc[i];
+    al = desc[NN];
+    be = desc[NN + 1];
+    ga = desc[NN + 2];
+    de = desc[NN + 3];
+  }
+#pragma unroll
+  for (int I = 0; I < NS; ++I)
+#pragma unroll
+    for (int J = 0; J < NS; ++J) {
+      const bool nI = D == 3 ? I < 3 : I < 2, nJ = D == 3 ? J < 3 : J < 2;  // normal rows
+      const double oI = nI ? 1.0 : 0.0, oJ = nJ ? 1.0 : 0.0;
+      const double dev = (I == J ? (nI ? 1.0 : 0.5) : 0.0) - oI * oJ / 3.0;
+      M[I * NS + J] = w * (al * dev + be * n[I] * n[J] + ga * (n[I] * oJ + oI * n[J]) + de * oI * oJ);
+    }
+}
+
 template <int ETID, typename VT>
-__global__ __launch_bounds__(AsmCfg<ETID>::BS) void k_assemble(KA a) {
+__global__ __launch_bounds__(AsmCfg<ETID>::BS)
+__attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a) {
   using T = Et<ETID>;
-  constexpr int D = T::D, NP = T::NP, NQ = T::NQ, BS = AsmCfg<ETID>::BS;
+  using Cfg = AsmCfg<ETID>;
+  constexpr int D = T::D, NP = T::NP, NQ = T::NQ, BS = Cfg::BS, NBT = Cfg::NBT;
+  constexpr int NPAIR = Cfg::NPAIR, QC = Cfg::QC, NB2 = NP * NP;
+  constexpr int NS = D == 3 ? 6 : 3;
   constexpr int NDESC = D == 3 ? 10 : 7;
-  constexpr int NN = D == 3 ? 6 : 3;  // stored n components
-  __shared__ double s_ref[NQ * NP * D];
+  static_assert(NP * D <= BS && NQ <= BS, "one thread per coordinate and per point");
   __shared__ double s_x[NP * D];
-  __shared__ double s_w[NQ];
-  __shared__ double s_d[NQ * NDESC];
+  __shared__ double s_M[NQ * NS * NS];     // w (D_q - C), all points of the element
   __shared__ double s_Ji[NQ * D * D];
-  __shared__ double s_g[NQ * NP * D];
-  __shared__ double s_ng[NQ * NP * D];
+  __shared__ double s_g[QC * D * NP];      // [q][d][p]
+  __shared__ double s_H[QC * D * NS * NP]; // [q][j][k][p]
+  __shared__ int s_q[NQ];                  // plastic points in order
   const int tid = threadIdx.x;
-  for (int t = tid; t < NQ * NP * D; t += BS) s_ref[t] = a.ref[t];
   int64_t k0 = a.k0, k1 = a.k1;
   if (a.off) {
     k0 = a.off[a.colour];
     k1 = a.off[a.colour + 1];
   }
   VT *Kt = (VT *)a.Kt;
+  const uint32_t qmask = NQ == 32 ? 0xffffffffu : ((1u << NQ) - 1u);
+  // node pairs of this thread
+  int pp_[NBT], pq_[NBT];
+#pragma unroll
+  for (int j = 0; j < NBT; ++j) {
+    int t = tid + j * BS, p = 0;
+    if (t >= NPAIR) t = 0;
+    while (t >= NP - p) {
+      t -= NP - p;
+      ++p;
+    }
+    pp_[j] = p;
+    pq_[j] = p + t;
+  }
   for (int64_t k = k0 + blockIdx.x; k < k1; k += gridDim.x) {
     const int e = a.list[k];
     if (e < 0) continue;  // padding of the colour-major order (uniform)
-    const uint32_t mask = a.elastic ? 0xffffffffu : a.emask[e];
-    __syncthreads();
-    for (int t = tid; t < NP * D; t += BS) {
-      const int64_t node = a.elem[(int64_t)e * NP + t / D];
-      s_x[t] = a.coord[(t % D) * a.n_n + node];
+    const uint32_t mask = (a.elastic ? 0xffffffffu : a.emask[e]) & qmask;
+    const int nq = __popc(mask);
+    // block indices (p,p') and (p',p), freshness of this assembly
+    int64_t i1[NBT], i2[NBT];
+    bool f1[NBT], f2[NBT];
+#pragma unroll
+    for (int j = 0; j < NBT; ++j) {
+      const bool on = tid + j * BS < NPAIR;
+      i1[j] = on ? (int64_t)a.bpos[(int64_t)e * NB2 + pp_[j] * NP + pq_[j]] : 0;
+      i2[j] = on ? (int64_t)a.bpos[(int64_t)e * NB2 + pq_[j] * NP + pp_[j]] : 0;
     }
-    __syncthreads();
-    if (tid < NQ && ((mask >> tid) & 1u)) {
-      double Ji[D][D];
-      const double det = jac_inv<D, NP>(s_x, s_ref + tid * NP * D, Ji);
-      s_w[tid] = fabs(det) * a.ref[NQ * NP * D + tid];
 #pragma unroll
-      for (int i = 0; i < D; ++i)
+    for (int j = 0; j < NBT; ++j) {
+      const bool on = tid + j * BS < NPAIR;
+      f1[j] = (!a.elastic && on) ? (a.epoch[i1[j]] != a.cur) : false;
+      f2[j] = (!a.elastic && on) ? (a.epoch[i2[j]] != a.cur) : false;
+    }
+    double acc[NBT][D * D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) s_Ji[tid * D * D + i * D + j] = Ji[i][j];
-      if (a.elastic) {
-        for (int c = 0; c < NDESC; ++c) s_d[tid * NDESC + c] = 0.0;
-        s_d[tid * NDESC + NN + 0] = 2.0 * a.G;
-        s_d[tid * NDESC + NN + 3] = a.K;
-      } else {
-        const int64_t ip = (int64_t)e * NQ + tid;
-        for (int c = 0; c < NDESC; ++c) s_d[tid * NDESC + c] = a.desc[c * a.n_int + ip];
+    for (int j = 0; j < NBT; ++j)
+#pragma unroll
+      for (int i = 0; i < D * D; ++i) acc[j][i] = 0.0;
+    if (mask) {
+      __syncthreads();  // LDS of the previous element is no longer read
+      if (tid < NP * D) {
+        const int64_t node = a.elem[(int64_t)e * NP + tid / D];
+        s_x[tid] = a.coord[(tid % D) * a.n_n + node];
       }
-    }
-    __syncthreads();
-    if (tid < NQ * NP) {
-      const int q = tid / NP, p = tid - (tid / NP) * NP;
-      if ((mask >> q) & 1u) {
+      if (tid < NQ) {
+        const uint32_t below = mask & ((1u << tid) - 1u);
+        if ((mask >> tid) & 1u) s_q[__popc(below)] = tid;
+      }
+      __syncthreads();
+      if (tid < nq) {
+        const int q = s_q[tid];
         double Ji[D][D];
+        const double det = jac_inv<D, NP>(s_x, a.ref + q * NP * D, Ji);
+        const double w = fabs(det) * a.ref[NQ * NP * D + q];
 #pragma unroll
         for (int i = 0; i < D; ++i)
 #pragma unroll
-          for (int j = 0; j < D; ++j) Ji[i][j] = s_Ji[q * D * D + i * D + j];
-        double g[D];
-        grad<D>(Ji, s_ref + (q * NP + p) * D, g);
-        const double *n = s_d + q * NDESC;
-        double ng[D];
-        if constexpr (D == 3) {
-          // tensor n (stress-type Voigt 11,22,33,12,23,13) times g
-          ng[0] = n[0] * g[0] + n[3] * g[1] + n[5] * g[2];
-          ng[1] = n[3] * g[0] + n[1] * g[1] + n[4] * g[2];
-          ng[2] = n[5] * g[0] + n[4] * g[1] + n[2] * g[2];
-        } else {
-          ng[0] = n[0] * g[0] + n[2] * g[1];
-          ng[1] = n[2] * g[0] + n[1] * g[1];
+          for (int jj = 0; jj < D; ++jj) s_Ji[tid * D * D + i * D + jj] = Ji[i][jj];
+        double dsc[NDESC];
+        if (!a.elastic) {
+          const int64_t ip = (int64_t)e * NQ + q;
+#pragma unroll
+          for (int c = 0; c < NDESC; ++c) dsc[c] = a.desc[c * a.n_int + ip];
         }
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-          s_g[(q * NP + p) * D + i] = g[i];
-          s_ng[(q * NP + p) * D + i] = ng[i];
-        }
+        tangent_matrix<D>(dsc, a.elastic != 0, a.G, a.K, w, s_M + tid * NS * NS);
       }
-    }
-    __syncthreads();
-    for (int t = tid; t < NP * NP; t += BS) {
-      const int p = t / NP, pp = t - (t / NP) * NP;
-      double acc[D][D];
+      for (int q0 = 0; q0 < nq; q0 += QC) {
+        const int nc = nq - q0 < QC ? nq - q0 : QC;
+        __syncthreads();
+        // gradients and H = M B, one (point, node) per thread
+        for (int t = tid; t < nc * NP; t += BS) {
+          const int ql = t / NP, p = t - (t / NP) * NP;
+          const int qi = q0 + ql;
+          double Ji[D][D];
 #pragma unroll
-      for (int i = 0; i < D; ++i)
+          for (int i = 0; i < D; ++i)
 #pragma unroll
-        for (int j = 0; j < D; ++j) acc[i][j] = 0.0;
-      uint32_t m = mask & ((NQ == 32) ? 0xffffffffu : ((1u << NQ) - 1u));
-      while (m) {
-        const int q = __builtin_ctz(m);
-        m &= m - 1u;
-        const double *dq = s_d + q * NDESC + NN;
-        const double w = s_w[q];
-        const double al = w * dq[0], be = w * dq[1], ga = w * dq[2], de = w * dq[3];
-        const double *g = s_g + (q * NP + p) * D, *h = s_g + (q * NP + pp) * D;
-        const double *ng = s_ng + (q * NP + p) * D, *nh = s_ng + (q * NP + pp) * D;
-        double gh = 0.0;
+            for (int jj = 0; jj < D; ++jj) Ji[i][jj] = s_Ji[qi * D * D + i * D + jj];
+          double g[D];
+          grad<D>(Ji, a.ref + (s_q[qi] * NP + p) * D, g);
+          const double *M = s_M + qi * NS * NS;
+          double *H = s_H + ql * D * NS * NP + p;
 #pragma unroll
-        for (int i = 0; i < D; ++i) gh += g[i] * h[i];
-        // block(i,j) of B_p^T (D - C) B_p': DEV gives 1/2 (g.h) d_ij
-        // + 1/2 h_i g_j - 1/3 g_i h_j
+          for (int d = 0; d < D; ++d) s_g[(ql * D + d) * NP + p] = g[d];
+          if constexpr (D == 3) {
 #pragma unroll
-        for (int i = 0; i < D; ++i)
-#pragma unroll
-          for (int j = 0; j < D; ++j)
-            acc[i][j] += al * ((i == j ? 0.5 * gh : 0.0) + 0.5 * h[i] * g[j] - g[i] * h[j] / 3.0) +
-                         be * ng[i] * nh[j] + ga * (ng[i] * h[j] + g[i] * nh[j]) +
-                         de * g[i] * h[j];
-      }
-      const int64_t idx = a.bpos[(int64_t)e * NP * NP + t];
-      VT *dst = Kt + idx * D * D;
-      if (a.elastic) {
-#pragma unroll
-        for (int i = 0; i < D; ++i)
-#pragma unroll
-          for (int j = 0; j < D; ++j) dst[i * D + j] += (VT)acc[i][j];
-      } else {
-        const bool fresh = a.epoch[idx] != a.cur;
-        if (fresh) {
-          if constexpr (sizeof(VT) == 8) {
-            const double *src = a.Ke + idx * D * D;
-#pragma unroll
-            for (int i = 0; i < D * D; ++i) dst[i] = (VT)(src[i] + acc[i / D][i % D]);
+            for (int kk = 0; kk < 6; ++kk) {
+              const double *m = M + kk * 6;
+              H[(0 * 6 + kk) * NP] = m[0] * g[0] + m[3] * g[1] + m[5] * g[2];
+              H[(1 * 6 + kk) * NP] = m[1] * g[1] + m[3] * g[0] + m[4] * g[2];
+              H[(2 * 6 + kk) * NP] = m[2] * g[2] + m[4] * g[1] + m[5] * g[0];
+            }
           } else {
-            const float *src = a.Ke32 + idx * D * D;
 #pragma unroll
-            for (int i = 0; i < D * D; ++i) dst[i] = (VT)((double)src[i] + acc[i / D][i % D]);
+            for (int kk = 0; kk < 3; ++kk) {
+              const double *m = M + kk * 3;
+              H[(0 * 3 + kk) * NP] = m[0] * g[0] + m[2] * g[1];
+              H[(1 * 3 + kk) * NP] = m[1] * g[1] + m[2] * g[0];
+            }
           }
-        } else {
-#pragma unroll
-          for (int i = 0; i < D * D; ++i) dst[i] = (VT)((double)dst[i] + acc[i / D][i % D]);
         }
-        a.epoch[idx] = a.cur;
+        __syncthreads();
+        // node blocks B_p^T H_p'
+#pragma unroll
+        for (int j = 0; j < NBT; ++j) {
+          if (tid + j * BS >= NPAIR) continue;
+          const int p = pp_[j], pq = pq_[j];
+          for (int ql = 0; ql < nc; ++ql) {
+            const double *gq = s_g + ql * D * NP;
+            const double *H = s_H + ql * D * NS * NP + pq;
+            if constexpr (D == 3) {
+              const double g0 = gq[p], g1 = gq[NP + p], g2 = gq[2 * NP + p];
+#pragma unroll
+              for (int jj = 0; jj < 3; ++jj) {
+                const double *h = H + jj * 6 * NP;
+                acc[j][0 * 3 + jj] += g0 * h[0] + g1 * h[3 * NP] + g2 * h[5 * NP];
+                acc[j][1 * 3 + jj] += g1 * h[1 * NP] + g0 * h[3 * NP] + g2 * h[4 * NP];
+                acc[j][2 * 3 + jj] += g2 * h[2 * NP] + g1 * h[4 * NP] + g0 * h[5 * NP];
+              }
+            } else {
+              const double g0 = gq[p], g1 = gq[NP + p];
+#pragma unroll
+              for (int jj = 0; jj < 2; ++jj) {
+                const double *h = H + jj * 3 * NP;
+                acc[j][0 * 2 + jj] += g0 * h[0] + g1 * h[2 * NP];
+                acc[j][1 * 2 + jj] += g1 * h[1 * NP] + g0 * h[2 * NP];
+              }
+            }
+          }
+        }
       }
     }
-  }
-}
-
-// Blocks of the elements of the previous plastic list that are elastic now
-// go back to K_elast.  Elements still plastic are rewritten by the colour
-// rounds (their blocks carry an old epoch).
-template <int ETID, typename VT>
-__global__ void k_restore(const int32_t *prev, const int32_t *prev_total, const uint32_t *emask,
-                          const int32_t *bpos, const VT *Ke, VT *Kt) {
-  using T = Et<ETID>;
-  constexpr int D = T::D, NP = T::NP;
-  const int64_t total = *prev_total;
-  for (int64_t k = blockIdx.x; k < total; k += gridDim.x) {
-    const int e = prev[k];
-    if (emask[e]) continue;
-    for (int t = threadIdx.x; t < NP * NP; t += blockDim.x) {
-      const int64_t idx = bpos[(int64_t)e * NP * NP + t];
+    // base values (K_elast for blocks not yet written in this assembly, else
+    // K_tangent) and the update of both blocks of each pair
 #pragma unroll
-      for (int i = 0; i < D * D; ++i) Kt[idx * D * D + i] = Ke[idx * D * D + i];
+    for (int j = 0; j < NBT; ++j) {
+      if (tid + j * BS >= NPAIR) continue;
+      const bool diag = pp_[j] == pq_[j];
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        if (side == 1 && diag) continue;
+        const int64_t idx = side == 0 ? i1[j] : i2[j];
+        const bool fresh = side == 0 ? f1[j] : f2[j];
+        if (!mask && !fresh) continue;  // left the plastic set, block already rewritten
+        double base[D * D];
+        if (a.elastic || !fresh) {
+#pragma unroll
+          for (int i = 0; i < D * D; ++i) base[i] = (double)Kt[idx * D * D + i];
+        } else if constexpr (sizeof(VT) == 8) {
+#pragma unroll
+          for (int i = 0; i < D * D; ++i) base[i] = a.Ke[idx * D * D + i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < D * D; ++i) base[i] = (double)a.Ke32[idx * D * D + i];
+        }
+        VT *dst = Kt + idx * D * D;
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+          for (int cc = 0; cc < D; ++cc)
+            dst[r * D + cc] = (VT)(base[r * D + cc] + (side == 0 ? acc[j][r * D + cc] : acc[j][cc * D + r]));
+        if (!a.elastic) a.epoch[idx] = a.cur;
+      }
     }
   }
 }
@@ -707,75 +789,88 @@ __global__ __launch_bounds__(256) void k_reduce(const double *partials, int nblk
 
 // ----------------------------------------------------------------------------
 // Stable compaction (wavefront ballot + block scan).  Items i < n (optionally
-// through a permutation, -1 = padding) with predicate src[item] != 0; kind 0:
-// uint8 source, kind 1: uint32 source (also counts set bits).
+// through a permutation, -1 = padding) with predicate (src | src2) != 0; kind
+// 0: uint8 source, kind 1: uint32 source (bitmask), src2 uint32 or null.
 // ----------------------------------------------------------------------------
 __device__ inline uint32_t cmp_value(const void *src, int kind, int64_t item) {
   if (item < 0) return 0u;
   return kind == 0 ? (uint32_t)((const uint8_t *)src)[item] : ((const uint32_t *)src)[item];
 }
 
-__global__ __launch_bounds__(CMP_THREADS) void k_compact_count(const void *src, int kind,
+__global__ __launch_bounds__(CMP_THREADS) void k_compact_count(const void *src,
+                                                               const uint32_t *src2, int kind,
                                                                const int32_t *perm, int64_t n,
-                                                               int32_t *counts,
-                                                               int32_t *counts2) {
-  __shared__ int32_t s_c[CMP_THREADS / 64], s_b[CMP_THREADS / 64];
+                                                               int32_t *counts, int32_t *counts2,
+                                                               int32_t *counts3) {
+  __shared__ int32_t s_c[CMP_THREADS / 64], s_b[CMP_THREADS / 64], s_z[CMP_THREADS / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t base = (int64_t)blockIdx.x * CMP_CHUNK;
-  int32_t cnt = 0, bits = 0;
+  int32_t cnt = 0, bits = 0, nz = 0;
   for (int k = 0; k < CMP_ITEMS; ++k) {
     const int64_t i = base + (int64_t)k * CMP_THREADS + tid;
-    uint32_t v = 0u;
-    if (i < n) v = cmp_value(src, kind, perm ? (int64_t)perm[i] : i);
-    const uint64_t b = __ballot(v != 0u);
-    cnt += __popcll(b);
+    uint32_t v = 0u, v2 = 0u;
+    if (i < n) {
+      const int64_t item = perm ? (int64_t)perm[i] : i;
+      v = cmp_value(src, kind, item);
+      if (src2 && item >= 0) v2 = src2[item];
+    }
+    cnt += __popcll(__ballot((v | v2) != 0u));
+    nz += __popcll(__ballot(v != 0u));
     bits += __popc(v);
   }
-  // wave-level sum of set bits
   for (int o = 32; o > 0; o >>= 1) bits += __shfl_down(bits, o, 64);
   if (lane == 0) {
     s_c[wv] = cnt;
     s_b[wv] = bits;
+    s_z[wv] = nz;
   }
   __syncthreads();
   if (tid == 0) {
-    int32_t c = 0, bb = 0;
+    int32_t c = 0, bb = 0, z = 0;
     for (int w = 0; w < CMP_THREADS / 64; ++w) {
       c += s_c[w];
       bb += s_b[w];
+      z += s_z[w];
     }
     counts[blockIdx.x] = c;
-    if (counts2) counts2[blockIdx.x] = bb;
+    counts2[blockIdx.x] = bb;
+    counts3[blockIdx.x] = z;
   }
 }
 
 // Exclusive scan of the block counts (single workgroup), colour offsets and
-// totals.  totals[0] = items, totals[1] = set bits.
+// totals: [0] selected items, [1] set bits, [2] items with src != 0.
 __global__ __launch_bounds__(1024) void k_compact_scan(const int32_t *counts,
-                                                       const int32_t *counts2, int nblk,
+                                                       const int32_t *counts2,
+                                                       const int32_t *counts3, int nblk,
                                                        int32_t *offsets,
                                                        const int32_t *colour_first_block,
                                                        int n_col, int32_t *colour_off,
                                                        int32_t *totals) {
   __shared__ int32_t s[1024];
   __shared__ int32_t s2[1024];
+  __shared__ int32_t s3[1024];
   const int tid = threadIdx.x;
   const int per = (nblk + 1023) / 1024;
   const int b0 = tid * per;
-  int32_t sum = 0, sum2 = 0;
+  int32_t sum = 0, sum2 = 0, sum3 = 0;
   for (int b = b0; b < b0 + per && b < nblk; ++b) {
     sum += counts[b];
-    if (counts2) sum2 += counts2[b];
+    sum2 += counts2[b];
+    sum3 += counts3[b];
   }
   s[tid] = sum;
   s2[tid] = sum2;
+  s3[tid] = sum3;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
     const int32_t v = tid >= o ? s[tid - o] : 0;
     const int32_t v2 = tid >= o ? s2[tid - o] : 0;
+    const int32_t v3 = tid >= o ? s3[tid - o] : 0;
     __syncthreads();
     s[tid] += v;
     s2[tid] += v2;
+    s3[tid] += v3;
     __syncthreads();
   }
   int32_t run = s[tid] - sum;  // exclusive prefix of this thread's range
@@ -787,6 +882,7 @@ __global__ __launch_bounds__(1024) void k_compact_scan(const int32_t *counts,
   if (tid == 0) {
     totals[0] = s[1023];
     totals[1] = s2[1023];
+    totals[2] = s3[1023];
     offsets[nblk] = s[1023];
   }
   __syncthreads();
@@ -797,7 +893,8 @@ __global__ __launch_bounds__(1024) void k_compact_scan(const int32_t *counts,
     }
 }
 
-__global__ __launch_bounds__(CMP_THREADS) void k_compact_scatter(const void *src, int kind,
+__global__ __launch_bounds__(CMP_THREADS) void k_compact_scatter(const void *src,
+                                                                 const uint32_t *src2, int kind,
                                                                  const int32_t *perm, int64_t n,
                                                                  const int32_t *offsets,
                                                                  int32_t *out) {
@@ -812,6 +909,7 @@ __global__ __launch_bounds__(CMP_THREADS) void k_compact_scatter(const void *src
     if (i < n) {
       item = perm ? (int64_t)perm[i] : i;
       v = cmp_value(src, kind, item);
+      if (src2 && item >= 0) v |= src2[item];
     }
     const uint64_t b = __ballot(v != 0u);
     const int rank = __popcll(b & ((1ull << lane) - 1ull));
@@ -1095,7 +1193,7 @@ static hipError_t constitutive_et(Ctx &c, const ConstArgs &ca) {
   a.flag = c.flag;
   a.desc = c.desc;
   a.Fe = c.Fe;
-  a.emask = c.emask;
+  a.emask = c.em[c.em_cur];
   a.eps_out = ca.eps_out;
   a.sig_out = ca.sig_out;
   a.D_out = ca.D_out;
@@ -1155,20 +1253,21 @@ hipError_t launch_reduce(Ctx &c, const double *partials, int nblk, int width, do
   return hipGetLastError();
 }
 
-hipError_t launch_compact(Ctx &c, int kind, const void *src, const int32_t *perm, int64_t n,
-                          int32_t *out, int32_t *colour_first_block, int n_col,
-                          int32_t *colour_off, int32_t *totals, int32_t *) {
+hipError_t launch_compact(Ctx &c, int kind, const void *src, const uint32_t *src2,
+                          const int32_t *perm, int64_t n, int32_t *out,
+                          int32_t *colour_first_block, int n_col, int32_t *colour_off,
+                          int32_t *totals) {
   const int nblk = ceil_div(n, CMP_CHUNK);
   if (nblk > c.cmp_cap) return hipErrorInvalidValue;
   if (nblk > 0)
-    hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(CMP_THREADS), 0, c.stream, src, kind,
-                       perm, n, c.cmp_counts, c.cmp_counts2);
+    hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(CMP_THREADS), 0, c.stream, src, src2,
+                       kind, perm, n, c.cmp_counts, c.cmp_counts2, c.cmp_counts3);
   hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, c.stream, c.cmp_counts,
-                     kind == 1 ? c.cmp_counts2 : (const int32_t *)nullptr, nblk, c.cmp_offsets,
-                     colour_first_block, n_col, colour_off, totals);
+                     c.cmp_counts2, c.cmp_counts3, nblk, c.cmp_offsets, colour_first_block, n_col,
+                     colour_off, totals);
   if (nblk > 0)
-    hipLaunchKernelGGL(k_compact_scatter, dim3(nblk), dim3(CMP_THREADS), 0, c.stream, src, kind,
-                       perm, n, c.cmp_offsets, out);
+    hipLaunchKernelGGL(k_compact_scatter, dim3(nblk), dim3(CMP_THREADS), 0, c.stream, src, src2,
+                       kind, perm, n, c.cmp_offsets, out);
   return hipGetLastError();
 }
 
@@ -1193,29 +1292,13 @@ static hipError_t elastic_et(Ctx &c) {
     a.K = c.mat.K;
     const int64_t cnt = a.k1 - a.k0;
     if (cnt == 0) continue;
-    const int grid = (int)(cnt < 8192 ? cnt : 8192);
+    const int grid = (int)(cnt < 65536 ? cnt : 65536);
     hipLaunchKernelGGL((k_assemble<ETID, double>), dim3(grid), dim3(Cfg::BS), 0, c.stream, a);
     RT(hipGetLastError());
   }
   return hipSuccess;
 }
 hipError_t launch_elastic_assembly(Ctx &c) { DISPATCH_ET(elastic_et, c) }
-
-template <int ETID>
-static hipError_t restore_et(Ctx &c) {
-  const int prev = c.asm_buf;
-  if (prev < 0) return hipSuccess;
-  const int grid = 2048;
-  if (c.opt.tangent_prec == EP_FP32)
-    hipLaunchKernelGGL((k_restore<ETID, float>), dim3(grid), dim3(64), 0, c.stream, c.plist[prev],
-                       c.coff[prev] + c.n_col, c.emask, c.bpos, c.Ke32, (float *)c.Kt);
-  else
-    hipLaunchKernelGGL((k_restore<ETID, double>), dim3(grid), dim3(64), 0, c.stream,
-                       c.plist[prev], c.coff[prev] + c.n_col, c.emask, c.bpos, c.Ke,
-                       (double *)c.Kt);
-  return hipGetLastError();
-}
-hipError_t launch_restore(Ctx &c) { DISPATCH_ET(restore_et, c) }
 
 template <int ETID>
 static hipError_t colour_et(Ctx &c, int colour, int epoch) {
@@ -1227,9 +1310,9 @@ static hipError_t colour_et(Ctx &c, int colour, int epoch) {
   a.n_n = c.n_n;
   a.n_int = c.n_int;
   a.desc = c.desc;
-  a.emask = c.emask;
-  a.list = c.plist[c.cur];
-  a.off = c.coff[c.cur];
+  a.emask = c.em[c.em_cur];
+  a.list = c.plist;
+  a.off = c.coff;
   a.colour = colour;
   a.bpos = c.bpos;
   a.Ke = c.Ke;
@@ -1242,7 +1325,7 @@ static hipError_t colour_et(Ctx &c, int colour, int epoch) {
   a.K = c.mat.K;
   const int64_t cnt = c.colour_size[colour];
   if (cnt == 0) return hipSuccess;
-  const int grid = (int)(cnt < 4096 ? cnt : 4096);
+  const int grid = (int)(cnt < 65536 ? cnt : 65536);
   if (c.opt.tangent_prec == EP_FP32)
     hipLaunchKernelGGL((k_assemble<ETID, float>), dim3(grid), dim3(Cfg::BS), 0, c.stream, a);
   else
