@@ -1,0 +1,55 @@
+"""Load-step driver around the C ABI: repeats ep_newton_step until the
+residual test passes (ALG-NEWTON, Section 4), then ep_commit_step.
+Orchestration only; every step of the path runs in the library."""
+from __future__ import annotations
+
+import time
+
+from . import _ep
+
+
+class NewtonError(RuntimeError):
+    pass
+
+
+def solve_load_step(ctx, f, u, max_newton=50):
+    """Newton iterations on u (device tensor, updated in place) for the load
+    vector f (device tensor).  Returns the list of per-iteration info dicts;
+    the last one has converged = 1."""
+    hist = []
+    for _ in range(max_newton + 1):
+        st, info = _ep.ep_newton_step(ctx.h, f, u)
+        info["status"] = st
+        hist.append(info)
+        if info["converged"]:
+            return hist
+        if st == _ep.EP_ENOTCONV:
+            raise NewtonError(f"PCG did not converge: {info}")
+    raise NewtonError(f"Newton did not converge in {max_newton} iterations: "
+                      f"{[h['res_rel'] for h in hist[-4:]]}")
+
+
+def solve_load_path(ctx, wl, u, steps=None, max_newton=50, callback=None, sync=None):
+    """Solves the load steps of workload wl in order (u holds the initial
+    displacement and is updated in place), committing the state after each.
+    Returns per-step records (Newton iterations, PCG iterations, plastic
+    points, wall time)."""
+    import torch
+    steps = range(len(wl.load_factors)) if steps is None else steps
+    f_unit = ctx.tensor(wl.f_unit)
+    records = []
+    for k in steps:
+        f = f_unit * float(wl.load_factors[k])
+        t0 = time.perf_counter()
+        hist = solve_load_step(ctx, f, u, max_newton)
+        ctx.commit_step(u)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        rec = {"step": k, "load": float(wl.load_factors[k]), "newton_its": len(hist) - 1,
+               "pcg_its": sum(h["pcg_its"] for h in hist), "res_rel": hist[-1]["res_rel"],
+               "n_plastic_ip": hist[-1]["n_plastic_ip"], "seconds": t,
+               "res_history": [h["res_rel"] for h in hist]}
+        records.append(rec)
+        if callback is not None:
+            callback(k, rec)
+    return records

@@ -1,0 +1,195 @@
+"""Semismooth Newton on the GPU (ep_newton_step / ep_commit_step, Jacobi-PCG
+inner solves) against the oracle's Newton with a direct sparse solve, on
+whole load paths of small workloads."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from paper_1805_04155_amd import _ep, solver  # noqa: E402
+from paper_1805_04155_amd import workloads as W  # noqa: E402
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def oracle_path(wl, steps, ep6=None, beta6=None, kappa=None, tol=1e-13):
+    mesh, mat = wl.mesh, wl.material
+    n = mesh.n_int
+    ep6 = np.zeros((n, 6)) if ep6 is None else ep6
+    beta6 = np.zeros((n, 6)) if beta6 is None else beta6
+    kappa = np.zeros(n) if kappa is None else kappa
+    u = np.zeros(mesh.n_dof)
+    dphi, w = O.geometry(mesh)
+    pat = O.pattern(mesh)
+    us, states = [], []
+    for k in steps:
+        u, it, res, out = O.newton_solve(mesh, mat, wl.free, wl.f(k), u, ep6, beta6, kappa,
+                                         tol=tol, dphi=dphi, w=w, pattern_=pat)
+        ep6, beta6, kappa = out["ep"], out["beta"], out["kappa"]
+        us.append(u.copy())
+        states.append((ep6, beta6, kappa, int(np.count_nonzero(out["flag"]))))
+    return us, states
+
+
+def gpu_path(wl, steps, options=None, state=None):
+    mesh = wl.mesh
+    opts = {"newton_rtol": 1e-12}
+    opts.update(options or {})
+    ctx = _ep.Context(mesh, wl.free, wl.material, options=opts)
+    if state is not None:
+        ctx.set_state(*state)
+    u = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
+    us, recs = [], []
+
+    def cb(k, rec):
+        us.append(_np(u).copy())
+        recs.append(rec)
+
+    solver.solve_load_path(ctx, wl, u, steps=steps, callback=cb)
+    st = ctx.get_state()
+    return ctx, us, recs, [_np(t) for t in st]
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("tangent", ["fp64", "fp32"])
+def test_p1_square_load_path(tangent):
+    """The whole P1-square load path (10 steps, last one plastic): GPU Newton
+    with PCG equals the oracle's Newton with a direct solve; the elastic
+    steps match the uniaxial closed form; the FP32 tangent reaches the same
+    solution (it only changes the convergence rate)."""
+    wl = W.workload_p1_square()
+    steps = range(10)
+    uo, so = oracle_path(wl, steps)
+    ctx, ug, recs, st = gpu_path(wl, steps, {"tangent_prec": _ep.EP_FP32 if tangent == "fp32" else 0})
+    try:
+        for k in steps:
+            assert recs[k]["res_rel"] <= 1e-12
+            assert _rel(ug[k], uo[k]) < 1e-9, k
+        # plastic strain after the last (plastic) step
+        assert recs[9]["n_plastic_ip"] == wl.mesh.n_int
+        ep_ref = O.ip6_to_state(so[-1][0], 2)
+        assert np.abs(st[0] - ep_ref).max() < 1e-9 * np.abs(ep_ref).max()
+        # elastic steps: homogeneous uniaxial closed form on the top-right node
+        mat = wl.material
+        t = wl.load_factors[0]
+        x = wl.mesh.coord
+        node = np.argmax(x[0] + x[1])
+        e22 = t * (1 - mat.nu ** 2) / mat.E
+        assert abs(ug[0][2 * node + 1] - e22 * 10.0) < 1e-9 * e22 * 10.0
+    finally:
+        ctx.close()
+
+
+def test_q2_slope_small_dp_path():
+    """Drucker-Prager plane strain on a small 9-node Q2 slope with gravity
+    ramp: GPU path equals the oracle on every step, including steps with a
+    growing plastic zone."""
+    wl = W.workload_q2_slope(16, 8, gamma_max=60.0, steps=6)
+    steps = range(6)
+    # nu = 0.49: the direct solve's residual floor is ~2e-13
+    uo, so = oracle_path(wl, steps, tol=1e-12)
+    ctx, ug, recs, st = gpu_path(wl, steps)
+    try:
+        for k in steps:
+            assert _rel(ug[k], uo[k]) < 1e-8, k
+            assert recs[k]["n_plastic_ip"] == so[k][3], k
+        assert so[-1][3] > 0
+    finally:
+        ctx.close()
+
+
+def test_q1_cube_seeded_vm_step():
+    """One plastic load step on a seeded von Mises Q1 cube (non-uniform
+    plastic zone): GPU equals oracle; committed state equals oracle."""
+    wl = W.workload_q1_cube(6)
+    ep, beta, kappa, _ = W.seeded_state(wl, 0.5, seed=3)
+    steps = [6]
+    uo, so = oracle_path(wl, steps, O.state_to_ip6(ep, 3), O.state_to_ip6(beta, 3))
+    ctx, ug, recs, st = gpu_path(wl, steps, state=(ep, beta, None))
+    try:
+        assert 0 < recs[0]["n_plastic_ip"] < wl.mesh.n_int
+        assert _rel(ug[0], uo[0]) < 1e-9
+        ref = O.ip6_to_state(so[0][0], 3)
+        assert np.abs(st[0] - ref).max() < 1e-9 * np.abs(ref).max()
+        refb = O.ip6_to_state(so[0][1], 3)
+        assert np.abs(st[1] - refb).max() < 1e-9 * np.abs(refb).max()
+    finally:
+        ctx.close()
+
+
+def test_q2_block_dp_hardening_steps():
+    """27-node hexahedra with Drucker-Prager cohesion hardening: two load
+    steps of the strip-pressure block, GPU vs oracle (u and kappa)."""
+    wl = W.workload_q2_block(4, 2, 2, q_max=4000.0, steps=4)
+    steps = range(4)
+    uo, so = oracle_path(wl, steps)
+    ctx, ug, recs, st = gpu_path(wl, steps)
+    try:
+        assert recs[-1]["n_plastic_ip"] > 0
+        for k in steps:
+            assert _rel(ug[k], uo[k]) < 1e-8, k
+        kref = so[-1][2]
+        assert np.abs(st[2] - kref).max() < 1e-8 * np.abs(kref).max()
+    finally:
+        ctx.close()
+
+
+def test_quadratic_convergence_with_forcing():
+    """With the forcing tolerance min(1e-2, |r|/|f|) the GPU Newton keeps
+    the local quadratic rate of the semismooth method."""
+    wl = W.workload_q1_cube(4)
+    ep, beta, kappa, _ = W.seeded_state(wl, 0.5, seed=0)
+    ctx, ug, recs, st = gpu_path(wl, [6], {"newton_rtol": 1e-14}, state=(ep, beta, None))
+    try:
+        r = recs[0]["res_history"]
+        ratios = [math.log(r[i + 1]) / math.log(r[i]) for i in range(len(r) - 1)
+                  if 1e-14 < r[i + 1] < r[i] < 1e-2]
+        assert ratios and max(ratios) > 1.7, r
+    finally:
+        ctx.close()
+
+
+def test_pcg_against_direct_solve():
+    wl = W.workload_q1_cube(5)
+    ep, beta, kappa, _ = W.seeded_state(wl, 0.5, seed=1)
+    ctx = _ep.Context(wl.mesh, wl.free, wl.material)
+    try:
+        ctx.set_state(ep, beta)
+        ctx.constitutive(ctx.tensor(np.zeros(wl.mesh.n_dof)), sig=False, D=False, flag=False)
+        ctx.assemble_tangent()
+        b = ctx.tensor(wl.f(3))
+        x, st, its, rel = ctx.pcg(b, 1e-12, 5000)
+        assert st == _ep.EP_OK and rel <= 1e-12
+        rp, ci, val = (_np(t) for t in ctx.csr(1))
+        import scipy.sparse.linalg as spla
+        K = O.csr_to_scipy(rp, ci, val, wl.mesh.n_dof)
+        q = wl.free.astype(bool)
+        xo = np.zeros(wl.mesh.n_dof)
+        xo[q] = spla.spsolve(K[q][:, q].tocsc(), wl.f(3)[q])
+        assert _rel(_np(x), xo) < 1e-9
+    finally:
+        ctx.close()
+
+
+def test_pcg_iteration_limit_is_reported():
+    """EP_ENOTCONV from the PCG limit is a status, not a failure of the run."""
+    wl = W.workload_q1_cube(4)
+    ctx = _ep.Context(wl.mesh, wl.free, wl.material, options={"pcg_max_it": 2,
+                                                              "pcg_check_every": 1})
+    try:
+        u = torch.zeros(wl.mesh.n_dof, dtype=torch.float64, device="cuda")
+        st, info = ctx.newton_step(ctx.tensor(wl.f(0)), u)
+        assert st == _ep.EP_ENOTCONV and info["pcg_its"] == 2
+        assert torch.isfinite(u).all()
+    finally:
+        ctx.close()
