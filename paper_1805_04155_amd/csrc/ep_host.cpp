@@ -585,7 +585,9 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   SETUP_HIP(dalloc(&c->cmp_offsets, c->cmp_cap + 1));
   SETUP_HIP(dalloc(&c->F, n_dof));
   SETUP_HIP(dalloc(&c->r, n_dof));
-  c->partials_cap = 2 * ((n_dof + 255) / 256) + 64;
+  // reductions: 2 per 256 dofs (PCG vectors, force gather) or 1 per SpMV
+  // block of up to 32 lanes per node
+  c->partials_cap = std::max<int64_t>(2 * ((n_dof + 255) / 256), (n_n * 32 + 255) / 256) + 64;
   SETUP_HIP(dalloc(&c->partials, c->partials_cap));
   SETUP_HIP(dalloc(&c->norms, 16));
   SETUP_HIP(hipHostMalloc((void **)&c->norms_h, 16 * sizeof(double), hipHostMallocDefault));
@@ -764,7 +766,10 @@ ep_status ep_newton_step(ep_ctx *ctx, const double *f, double *u, ep_newton_info
   }
   st = do_assemble(c);
   if (st) return st;
-  const double rtol = std::min(c->opt.pcg_forcing_max, info->res_rel);
+  // forcing term min(max, |r|/|f|), but no tighter than needed to reach the
+  // Newton tolerance in this step
+  const double rtol = std::min(c->opt.pcg_forcing_max,
+                               std::max(info->res_rel, 0.5 * c->opt.newton_rtol / info->res_rel));
   int its = 0;
   double rel = 0;
   const ep_status ps = do_pcg(c, c->r, c->px, rtol, c->opt.pcg_max_it, &its, &rel);

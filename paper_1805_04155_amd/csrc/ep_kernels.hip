@@ -274,13 +274,18 @@ __global__ __launch_bounds__(CT) void k_constitutive(KC a) {
     double Ji[D][D];
     const double det = jac_inv<D, NP>(xs, dr, Ji);
     const double w = fabs(det) * s_wq[q];
-    // strain E = B u (eq. local_strain-displ), engineering Voigt
+    // strain E = B u (eq. local_strain-displ), engineering Voigt.  The
+    // gradients sum to zero, so E = sum_{p>=1} g_p (u_p - u_0): the
+    // differences of nearby displacements are exact and the large common part
+    // of u (rigid motion, gravity sag) does not enter the rounding.
     double eps[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
+    for (int p = 1; p < NP; ++p) {
       double g[D];
       grad<D>(Ji, dr + p * D, g);
-      const double *up = us + p * D;
+      double up[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) up[d] = us[p * D + d] - us[d];
       if constexpr (D == 3) {
         eps[0] += g[0] * up[0];
         eps[1] += g[1] * up[1];
@@ -984,52 +989,69 @@ __global__ void k_diag_inv(int64_t n_n, const int32_t *bdiag, const VT *Kt, cons
 // PCG scalars on the device
 enum { SC_RZ = 0, SC_PQ, SC_RR, SC_TOL, SC_DONE, SC_ITS, SC_ALPHA, SC_BETA, SC_RR0, SC_N };
 
-// y = Q K x (row per thread, node blocks), optional fused direction update
-// x = z + beta*p_old (written to p_new for the own row), partial x.y
-template <int D, typename VT>
+// y = Q K x with G lanes per node row: the lanes of a group read consecutive
+// node blocks of the row (coalesced), each lane accumulates the dim rows of
+// the block row, and a butterfly over the G lanes (fixed order, identical
+// in every lane) reduces them.  Optional fused direction update
+// x = z + beta*p_old (p_new written for the own rows) and partial x.y.
+template <int D, typename VT, int G>
 __global__ __launch_bounds__(256) void k_spmv(int64_t n_n, const int32_t *bptr,
                                               const int32_t *bcol, const VT *val,
                                               const double *x, const uint8_t *freem, double *y,
                                               double *partials, const double *z,
                                               const double *pold, double *pnew, const double *sc) {
-  __shared__ double s[256];
+  __shared__ double s[256 / G];
   if (sc && sc[SC_DONE] != 0.0) return;
   const int tid = threadIdx.x;
-  const int64_t r = (int64_t)blockIdx.x * 256 + tid;
+  const int g = tid % G;
+  const int64_t m = ((int64_t)blockIdx.x * 256 + tid) / G;
   const double beta = sc ? sc[SC_BETA] : 0.0;
-  double dot = 0.0;
-  if (r < D * n_n) {
-    const int64_t m = r / D;
-    const int i = (int)(r - m * D);
-    double acc = 0.0;
-    const int b1 = bptr[m + 1];
-    for (int b = bptr[m]; b < b1; ++b) {
-      const int64_t c = bcol[b];
-      const VT *v = val + ((int64_t)b * D + i) * D;
+  double acc[D];
 #pragma unroll
-      for (int j = 0; j < D; ++j) {
-        const double xv = z ? z[D * c + j] + beta * pold[D * c + j] : x[D * c + j];
-        acc += (double)v[j] * xv;
+  for (int i = 0; i < D; ++i) acc[i] = 0.0;
+  if (m < n_n) {
+    const int b1 = bptr[m + 1];
+    for (int b = bptr[m] + g; b < b1; b += G) {
+      const int64_t c = bcol[b];
+      double xv[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) xv[j] = z ? z[D * c + j] + beta * pold[D * c + j] : x[D * c + j];
+      const VT *v = val + (int64_t)b * D * D;
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) acc[i] += (double)v[i * D + j] * xv[j];
+    }
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int i = 0; i < D; ++i) acc[i] += __shfl_xor(acc[i], o, G);
+  double dot = 0.0;
+  if (m < n_n && g == 0) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const int64_t r = D * m + i;
+      const double yv = freem[r] ? acc[i] : 0.0;
+      y[r] = yv;
+      double xr;
+      if (z) {
+        xr = z[r] + beta * pold[r];
+        pnew[r] = xr;
+      } else {
+        xr = x[r];
       }
+      dot += xr * yv;
     }
-    const double yv = freem[r] ? acc : 0.0;
-    y[r] = yv;
-    double xr;
-    if (z) {
-      xr = z[r] + beta * pold[r];
-      pnew[r] = xr;
-    } else {
-      xr = x[r];
-    }
-    dot = xr * yv;
   }
-  s[tid] = dot;
+  // block sum of the group leaders' dots, fixed order
+  if (g == 0) s[tid / G] = dot;
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (tid < h) s[tid] += s[tid + h];
-    __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int k = 0; k < 256 / G; ++k) t += s[k];
+    partials[blockIdx.x] = t;
   }
-  if (tid == 0) partials[blockIdx.x] = s[0];
 }
 
 // alpha = rz / pq
@@ -1393,20 +1415,45 @@ hipError_t launch_diag_inv(Ctx &c) {
   return hipGetLastError();
 }
 
-hipError_t launch_spmv(Ctx &c, const double *x, double *y, bool, double *partials) {
-  const int grid = ceil_div(c.n_dof, 256);
-  const bool f32 = c.opt.tangent_prec == EP_FP32;
-#define SPMV(D, VT)                                                                           \
-  hipLaunchKernelGGL((k_spmv<D, VT>), dim3(grid), dim3(256), 0, c.stream, c.n_n, c.bptr,      \
-                     c.bcol, (const VT *)c.Kt, x, c.freem, y, partials, (const double *)nullptr, \
-                     (const double *)nullptr, (double *)nullptr, (const double *)nullptr)
-  if (c.dim == 2) {
-    if (f32) SPMV(2, float); else SPMV(2, double);
-  } else {
-    if (f32) SPMV(3, float); else SPMV(3, double);
+// lanes per node row, from the mean row length
+static int spmv_lanes(const Ctx &c) {
+  const double deg = c.n_n > 0 ? (double)c.nnzb / (double)c.n_n : 1.0;
+  return deg <= 12 ? 4 : (deg <= 24 ? 8 : (deg <= 48 ? 16 : 32));
+}
+
+template <int D, typename VT>
+static hipError_t spmv_launch(Ctx &c, const double *x, double *y, double *partials, const double *z,
+                              const double *pold, double *pnew, const double *sc, int *nblk) {
+  const int G = spmv_lanes(c);
+  const int grid = ceil_div(c.n_n * G, 256);
+  *nblk = grid;
+  if (grid == 0) return hipSuccess;
+#define SPG(GG)                                                                              \
+  hipLaunchKernelGGL((k_spmv<D, VT, GG>), dim3(grid), dim3(256), 0, c.stream, c.n_n, c.bptr, \
+                     c.bcol, (const VT *)c.Kt, x, c.freem, y, partials, z, pold, pnew, sc)
+  switch (G) {
+    case 4: SPG(4); break;
+    case 8: SPG(8); break;
+    case 16: SPG(16); break;
+    default: SPG(32); break;
   }
-#undef SPMV
+#undef SPG
   return hipGetLastError();
+}
+
+static hipError_t spmv_any(Ctx &c, const double *x, double *y, double *partials, const double *z,
+                           const double *pold, double *pnew, const double *sc, int *nblk) {
+  const bool f32 = c.opt.tangent_prec == EP_FP32;
+  if (c.dim == 2)
+    return f32 ? spmv_launch<2, float>(c, x, y, partials, z, pold, pnew, sc, nblk)
+               : spmv_launch<2, double>(c, x, y, partials, z, pold, pnew, sc, nblk);
+  return f32 ? spmv_launch<3, float>(c, x, y, partials, z, pold, pnew, sc, nblk)
+             : spmv_launch<3, double>(c, x, y, partials, z, pold, pnew, sc, nblk);
+}
+
+hipError_t launch_spmv(Ctx &c, const double *x, double *y, bool, double *partials) {
+  int nblk = 0;
+  return spmv_any(c, x, y, partials, nullptr, nullptr, nullptr, nullptr, &nblk);
 }
 
 hipError_t launch_pcg_init(Ctx &c, const double *b, double *x) {
@@ -1422,22 +1469,12 @@ hipError_t launch_pcg_beta_init(Ctx &c, double rtol);
 
 hipError_t launch_pcg_iteration(Ctx &c, double *x) {
   const int grid = ceil_div(c.n_dof, 256);
-  const bool f32 = c.opt.tangent_prec == EP_FP32;
   double *pold = c.pp[c.pcur], *pnew = c.pp[1 - c.pcur];
   int tok = c.prof_begin(PROF_SPMV);
-#define SPMVF(D, VT)                                                                          \
-  hipLaunchKernelGGL((k_spmv<D, VT>), dim3(grid), dim3(256), 0, c.stream, c.n_n, c.bptr,      \
-                     c.bcol, (const VT *)c.Kt, (const double *)nullptr, c.freem, c.pq,          \
-                     c.partials, c.pz, pold, pnew, c.sc)
-  if (c.dim == 2) {
-    if (f32) SPMVF(2, float); else SPMVF(2, double);
-  } else {
-    if (f32) SPMVF(3, float); else SPMVF(3, double);
-  }
-#undef SPMVF
+  int nblk = 0;
+  RT(spmv_any(c, nullptr, c.pq, c.partials, c.pz, pold, pnew, c.sc, &nblk));
   c.prof_end(tok);
-  RT(hipGetLastError());
-  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(256), 0, c.stream, c.partials, grid, c.sc);
+  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(256), 0, c.stream, c.partials, nblk, c.sc);
   RT(hipGetLastError());
   tok = c.prof_begin(PROF_PCGVEC);
   hipLaunchKernelGGL(k_pcg_update, dim3(grid), dim3(256), 0, c.stream, c.n_dof, x, pnew, c.r,
