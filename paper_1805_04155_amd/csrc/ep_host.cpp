@@ -381,8 +381,11 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   if (opt_in) opt = *opt_in;
   if (opt.tangent_prec != EP_FP64 && opt.tangent_prec != EP_FP32)
     return fail("ep_setup: tangent_prec must be EP_FP64 or EP_FP32", EP_EINVAL);
-  if (opt.local_prec != EP_FP64)
-    return fail("ep_setup: local_prec other than EP_FP64 is not available", EP_EINVAL);
+  if (opt.local_prec != EP_FP64 && !(opt.local_prec == EP_FP32 || opt.local_prec == EP_BF16))
+    return fail("ep_setup: local_prec must be EP_FP64, EP_FP32 or EP_BF16", EP_EINVAL);
+  if (opt.local_prec != EP_FP64 && !(ed.id == ET_Q2_3D || ed.id == ET_P2_3D))
+    return fail("ep_setup: matrix-core local products (EP_FP32 / EP_BF16) are built for the "
+                "27-node hexahedron and the 10-node tetrahedron only", EP_EINVAL);
   if (opt.pcg_max_it <= 0) opt.pcg_max_it = 20000;
   if (opt.pcg_check_every <= 0) opt.pcg_check_every = 50;
 

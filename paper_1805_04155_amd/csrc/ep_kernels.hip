@@ -722,6 +722,280 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
 }
 
 // ----------------------------------------------------------------------------
+// Element-local products on the matrix cores (27-node hexahedra, 10-node
+// tetrahedra).  Delta K_e = B^T H with B the stacked B_q (6 n_q x 3 n_p) and
+// H = blockdiag(M_q) B, M_q = w_q (D_q - C): a (3 n_p) x (3 n_p) x (6 n_q)
+// product.  B and H are staged in LDS as BF16 (v_mfma_f32_16x16x32_bf16) or
+// FP32 (v_mfma_f32_16x16x4_f32) tiles, a chunk of QC points at a time, and
+// each wavefront accumulates upper-triangle 16x16 tiles of the (symmetric)
+// element matrix in FP32 registers.  The element matrix then goes through
+// LDS to the same epoch-stamped node-block scatter as the FP64 kernel.
+// Lane layouts (checked on gfx950): lane l holds A[l%16][k-group l/16],
+// B[k-group l/16][l%16], and the result rows 4(l/16)..4(l/16)+3 of column
+// l%16.
+// ----------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+template <int ETID, bool BF16>
+struct MfmaCfg {
+  using T = Et<ETID>;
+  static constexpr int NL = 3 * T::NP;
+  static constexpr int MP = ((NL + 15) / 16) * 16;
+  static constexpr int TT = MP / 16;
+  static constexpr int NT = TT * (TT + 1) / 2;
+  static constexpr int QC = T::NQ <= 11 ? T::NQ : 9;
+  static constexpr int KC = 6 * QC;
+  static constexpr int KK = BF16 ? 32 : 4;
+  static constexpr int KP = ((KC + KK - 1) / KK) * KK;
+  static constexpr int LDK = BF16 ? KP + 8 : KP + 1;  // bank-conflict-free strides
+  static constexpr int NPAIR = T::NP * (T::NP + 1) / 2;
+  static constexpr int NBT = (NPAIR + 255) / 256;
+  static constexpr int TPW = (NT + 3) / 4;
+};
+
+template <bool BF16> struct MfmaElem { using type = float; };
+template <> struct MfmaElem<true> { using type = __bf16; };
+
+template <int ETID, typename VT, bool BF16>
+__global__ __launch_bounds__(256) void k_assemble_mfma(KA a) {
+  using T = Et<ETID>;
+  using C = MfmaCfg<ETID, BF16>;
+  using ET = typename MfmaElem<BF16>::type;
+  constexpr int NP = T::NP, NQ = T::NQ, NB2 = NP * NP;
+  constexpr int NL = C::NL, MP = C::MP, TT = C::TT, NT = C::NT, QC = C::QC, KC = C::KC;
+  constexpr int KK = C::KK, KP = C::KP, LDK = C::LDK, NPAIR = C::NPAIR, NBT = C::NBT;
+  constexpr int TPW = C::TPW;
+  static_assert(T::D == 3, "3D elements");
+  __shared__ ET s_B[MP * LDK];
+  __shared__ ET s_H[MP * LDK];
+  __shared__ float s_K[NL * NL];
+  __shared__ double s_x[NP * 3];
+  __shared__ double s_M[NQ * 36];
+  __shared__ double s_Ji[NQ * 9];
+  __shared__ int s_q[NQ];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r16 = lane & 15, kg = lane >> 4;
+  // padding rows / columns stay zero for the whole kernel
+  for (int t = tid; t < MP * LDK; t += 256) {
+    const int m = t / LDK, kk = t - (t / LDK) * LDK;
+    if (m >= NL || kk >= KC) {
+      s_B[t] = (ET)0.0f;
+      s_H[t] = (ET)0.0f;
+    }
+  }
+  int pp_[NBT], pq_[NBT];
+#pragma unroll
+  for (int j = 0; j < NBT; ++j) {
+    int t = tid + j * 256, p = 0;
+    if (t >= NPAIR) t = 0;
+    while (t >= NP - p) {
+      t -= NP - p;
+      ++p;
+    }
+    pp_[j] = p;
+    pq_[j] = p + t;
+  }
+  int64_t k0 = a.k0, k1 = a.k1;
+  if (a.off) {
+    k0 = a.off[a.colour];
+    k1 = a.off[a.colour + 1];
+  }
+  VT *Kt = (VT *)a.Kt;
+  const uint32_t qmask = (1u << NQ) - 1u;
+  for (int64_t k = k0 + blockIdx.x; k < k1; k += gridDim.x) {
+    const int e = a.list[k];
+    if (e < 0) continue;
+    const uint32_t mask = a.emask[e] & qmask;
+    const int nq = __popc(mask);
+    int64_t i1[NBT], i2[NBT];
+    bool f1[NBT], f2[NBT];
+#pragma unroll
+    for (int j = 0; j < NBT; ++j) {
+      const bool on = tid + j * 256 < NPAIR;
+      i1[j] = on ? (int64_t)a.bpos[(int64_t)e * NB2 + pp_[j] * NP + pq_[j]] : 0;
+      i2[j] = on ? (int64_t)a.bpos[(int64_t)e * NB2 + pq_[j] * NP + pp_[j]] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < NBT; ++j) {
+      const bool on = tid + j * 256 < NPAIR;
+      f1[j] = on ? (a.epoch[i1[j]] != a.cur) : false;
+      f2[j] = on ? (a.epoch[i2[j]] != a.cur) : false;
+    }
+    double acc[NBT][9];
+#pragma unroll
+    for (int j = 0; j < NBT; ++j)
+#pragma unroll
+      for (int i = 0; i < 9; ++i) acc[j][i] = 0.0;
+    if (mask) {
+      __syncthreads();  // LDS of the previous element is no longer read
+      if (tid < NP * 3) {
+        const int64_t node = a.elem[(int64_t)e * NP + tid / 3];
+        s_x[tid] = a.coord[(tid % 3) * a.n_n + node];
+      }
+      if (tid < NQ && ((mask >> tid) & 1u)) s_q[__popc(mask & ((1u << tid) - 1u))] = tid;
+      __syncthreads();
+      if (tid < nq) {
+        const int q = s_q[tid];
+        double Ji[3][3];
+        const double det = jac_inv<3, NP>(s_x, a.ref + q * NP * 3, Ji);
+        const double w = fabs(det) * a.ref[NQ * NP * 3 + q];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int jj = 0; jj < 3; ++jj) s_Ji[tid * 9 + i * 3 + jj] = Ji[i][jj];
+        double dsc[10];
+        const int64_t ip = (int64_t)e * NQ + q;
+#pragma unroll
+        for (int c = 0; c < 10; ++c) dsc[c] = a.desc[c * a.n_int + ip];
+        tangent_matrix<3>(dsc, false, a.G, a.K, w, s_M + tid * 36);
+      }
+      f32x4_t tacc[TPW];
+#pragma unroll
+      for (int s = 0; s < TPW; ++s) tacc[s] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      for (int c0 = 0; c0 < nq; c0 += QC) {
+        const int nc = nq - c0 < QC ? nq - c0 : QC;
+        __syncthreads();  // previous chunk consumed
+        for (int t = tid; t < QC * NP; t += 256) {
+          const int ql = t / NP, p = t - (t / NP) * NP;
+          double bc[3][6], hc[3][6];
+          if (ql < nc) {
+            const int qi = c0 + ql;
+            double Ji[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int jj = 0; jj < 3; ++jj) Ji[i][jj] = s_Ji[qi * 9 + i * 3 + jj];
+            double g[3];
+            grad<3>(Ji, a.ref + (s_q[qi] * NP + p) * 3, g);
+            // columns (p, 0..2) of B_q, rows 11, 22, 33, 12, 23, 13
+            const double z = 0.0;
+            const double b0[6] = {g[0], z, z, g[1], z, g[2]};
+            const double b1[6] = {z, g[1], z, g[0], g[2], z};
+            const double b2[6] = {z, z, g[2], z, g[1], g[0]};
+#pragma unroll
+            for (int rr = 0; rr < 6; ++rr) {
+              bc[0][rr] = b0[rr];
+              bc[1][rr] = b1[rr];
+              bc[2][rr] = b2[rr];
+            }
+            const double *M = s_M + qi * 36;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int rr = 0; rr < 6; ++rr) {
+                double h = 0.0;
+#pragma unroll
+                for (int l = 0; l < 6; ++l) h += M[rr * 6 + l] * bc[i][l];
+                hc[i][rr] = h;
+              }
+          } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int rr = 0; rr < 6; ++rr) {
+                bc[i][rr] = 0.0;
+                hc[i][rr] = 0.0;
+              }
+          }
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int rr = 0; rr < 6; ++rr) {
+              s_B[(3 * p + i) * LDK + 6 * ql + rr] = (ET)(float)bc[i][rr];
+              s_H[(3 * p + i) * LDK + 6 * ql + rr] = (ET)(float)hc[i][rr];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < TPW; ++s) {
+          int t = wv + 4 * s;
+          if (t >= NT) break;
+          int tm = 0;
+          while (t >= TT - tm) {
+            t -= TT - tm;
+            ++tm;
+          }
+          const int tn = tm + t;
+          const ET *ra = s_B + (16 * tm + r16) * LDK;
+          const ET *rb = s_H + (16 * tn + r16) * LDK;
+#pragma unroll
+          for (int ks = 0; ks < KP / KK; ++ks) {
+            if constexpr (BF16) {
+              const bf16x8_t av = *(const bf16x8_t *)(ra + ks * 32 + kg * 8);
+              const bf16x8_t bv = *(const bf16x8_t *)(rb + ks * 32 + kg * 8);
+              tacc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, tacc[s], 0, 0, 0);
+            } else {
+              tacc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[ks * 4 + kg], rb[ks * 4 + kg],
+                                                             tacc[s], 0, 0, 0);
+            }
+          }
+        }
+      }
+      // tiles -> element matrix in LDS
+#pragma unroll
+      for (int s = 0; s < TPW; ++s) {
+        int t = wv + 4 * s;
+        if (t >= NT) break;
+        int tm = 0;
+        while (t >= TT - tm) {
+          t -= TT - tm;
+          ++tm;
+        }
+        const int tn = tm + t;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = 16 * tm + 4 * kg + i, n = 16 * tn + r16;
+          if (m < NL && n < NL) s_K[m * NL + n] = tacc[s][i];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < NBT; ++j) {
+        if (tid + j * 256 >= NPAIR) continue;
+#pragma unroll
+        for (int r3 = 0; r3 < 3; ++r3)
+#pragma unroll
+          for (int c3 = 0; c3 < 3; ++c3) {
+            const int m = 3 * pp_[j] + r3, n = 3 * pq_[j] + c3;
+            acc[j][r3 * 3 + c3] = (double)(m <= n ? s_K[m * NL + n] : s_K[n * NL + m]);
+          }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NBT; ++j) {
+      if (tid + j * 256 >= NPAIR) continue;
+      const bool diag = pp_[j] == pq_[j];
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        if (side == 1 && diag) continue;
+        const int64_t idx = side == 0 ? i1[j] : i2[j];
+        const bool fresh = side == 0 ? f1[j] : f2[j];
+        if (!mask && !fresh) continue;
+        double base[9];
+        if (!fresh) {
+#pragma unroll
+          for (int i = 0; i < 9; ++i) base[i] = (double)Kt[idx * 9 + i];
+        } else if constexpr (sizeof(VT) == 8) {
+#pragma unroll
+          for (int i = 0; i < 9; ++i) base[i] = a.Ke[idx * 9 + i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < 9; ++i) base[i] = (double)a.Ke32[idx * 9 + i];
+        }
+        VT *dst = Kt + idx * 9;
+#pragma unroll
+        for (int r3 = 0; r3 < 3; ++r3)
+#pragma unroll
+          for (int c3 = 0; c3 < 3; ++c3)
+            dst[r3 * 3 + c3] = (VT)(base[r3 * 3 + c3] + (side == 0 ? acc[j][r3 * 3 + c3] : acc[j][c3 * 3 + r3]));
+        a.epoch[idx] = a.cur;
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
 // Deterministic node gather of the element force vectors, residual and
 // partial norms.
 // ----------------------------------------------------------------------------
@@ -1348,7 +1622,22 @@ static hipError_t colour_et(Ctx &c, int colour, int epoch) {
   const int64_t cnt = c.colour_size[colour];
   if (cnt == 0) return hipSuccess;
   const int grid = (int)(cnt < 65536 ? cnt : 65536);
-  if (c.opt.tangent_prec == EP_FP32)
+  const bool f32 = c.opt.tangent_prec == EP_FP32;
+  if constexpr (ETID == ET_Q2_3D || ETID == ET_P2_3D) {
+    if (c.opt.local_prec == EP_BF16 || c.opt.local_prec == EP_FP32) {
+      const bool bf = c.opt.local_prec == EP_BF16;
+#define MF(VT, BF) \
+  hipLaunchKernelGGL((k_assemble_mfma<ETID, VT, BF>), dim3(grid), dim3(256), 0, c.stream, a)
+      if (f32) {
+        if (bf) MF(float, true); else MF(float, false);
+      } else {
+        if (bf) MF(double, true); else MF(double, false);
+      }
+#undef MF
+      return hipGetLastError();
+    }
+  }
+  if (f32)
     hipLaunchKernelGGL((k_assemble<ETID, float>), dim3(grid), dim3(Cfg::BS), 0, c.stream, a);
   else
     hipLaunchKernelGGL((k_assemble<ETID, double>), dim3(grid), dim3(Cfg::BS), 0, c.stream, a);
