@@ -221,7 +221,8 @@ ep_status ep_get_csr(ep_ctx *ctx, int32_t which, int32_t *row_ptr, int32_t *col_
  * the entry (dof(e,a), dof(e,b)), local dof a = dim*p + i. */
 ep_status ep_get_position_map(ep_ctx *ctx, int32_t *pos);
 
-/* y = Q (K_tangent (Q x)) on free dofs, y = 0 on Dirichlet dofs. */
+/* y = Q (K_tangent x): the product on free dofs, y = 0 on Dirichlet dofs
+ * (x is used as given, also on Dirichlet dofs). */
 ep_status ep_spmv(ep_ctx *ctx, const double *x, double *y);
 
 /* Solves Q K_tangent Q x = Q b by Jacobi-PCG from x = 0 to
@@ -236,6 +237,125 @@ ep_status ep_pcg(ep_ctx *ctx, const double *b, double *x, double rtol, int32_t m
  * 6 PCG vector update) and resets it.  Synchronises. */
 ep_status ep_profile(ep_ctx *ctx, int32_t enable);
 ep_status ep_profile_read(ep_ctx *ctx, int32_t k, double *ms, int64_t *count);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start (not part of the paper's method).  A per-point MLP
+ * 13 -> 128 -> 128 -> 7 (ReLU) is trained on samples of the exact return
+ * map (Sections 2.2, 2.3) and predicts, for a trial state, the stress and
+ * whether the point is plastic.  ep_warm_start turns the prediction at an
+ * extrapolated displacement into a Newton start: the predicted plastic set
+ * selects the tangent branch, the predicted stress gives the residual, and
+ * one linear solve gives the start; the exact residual decides whether it
+ * is kept.  The converged solution is that of the exact return map.
+ *
+ * Features (one row of EP_MLP_XS floats per point):
+ *   x[0:6]  = s_in (eps - eps_p)   trial elastic strain, 3D Voigt
+ *                                  (engineering shears; plane strain: the
+ *                                  embedded strain, 23 = 13 = 0)
+ *   x[6:12] = s_in eps_p           plastic strain
+ *   x[12]   = s_in kappa           Drucker-Prager hardening variable
+ *   x[13:16] = 0
+ * Targets / outputs (one row of EP_MLP_YS floats):
+ *   y[0:6] = s_out (sigma - sigma_tr), the plastic correction of the 3D
+ *   Voigt stress (sigma_tr = C (eps - eps_p), the elastic trial stress; the
+ *   correction is 0 at elastic points), y[6] = plastic flag (targets: 0 or
+ *   1; outputs: logit), y[7] = 0.  The predicted stress is
+ *   sigma_tr + S y[0:6].
+ * with s_in = E/S and s_out = 1/S, S = sqrt(3/2) Y (von Mises) or c
+ * (Drucker-Prager).  The von Mises back stress is not a feature: the
+ * generator and the warm start use beta = a eps_p (as tensors), which
+ * linear kinematic hardening keeps from a state with beta_0 = a eps_p0.
+ *
+ * Parameters: one float array of EP_MLP_NPARAM values, in the order
+ *   W1[128][13], b1[128], W2[128][128], b2[128], W3[7][128], b3[7]
+ * (W[out][in]).  Loss of a batch of n samples:
+ *   L = (1/n) sum_s [ (1/6) sum_{j<6} (y_j - t_j)^2
+ *                     + log(1 + exp(y_6)) - t_6 y_6 ].
+ * ------------------------------------------------------------------------ */
+#define EP_MLP_IN 13
+#define EP_MLP_HID 128
+#define EP_MLP_OUT 7
+#define EP_MLP_XS 16
+#define EP_MLP_YS 8
+#define EP_MLP_NPARAM 19207
+
+typedef struct ep_mlp ep_mlp;
+
+typedef struct {
+  double res_rel_pred;       /* |Q(f - B^T W sigma_hat)| / |Q f| at u_pred  */
+  double res_rel_start;      /* exact res_rel at u_prev (plain start)       */
+  double res_rel_warm;       /* exact res_rel at the warm start             */
+  int32_t pcg_its;           /* iterations of the warm-start solve          */
+  int32_t accepted;          /* 1: u_out = warm start, 0: u_out = u_prev    */
+  int64_t n_plastic_pred;    /* points predicted plastic                    */
+} ep_warm_info;
+
+/* Creates a network whose products use prec = EP_FP32 or EP_BF16 operands
+ * (FP32 accumulation, FP32 parameters and Adam moments), with all
+ * parameters 0; batches up to max_batch samples.  Work goes to hip_stream
+ * (NULL: the default stream).  EP_EINVAL for another prec or
+ * max_batch < 1; EP_ENOMEM. */
+ep_status ep_mlp_create(int32_t prec, int64_t max_batch, void *hip_stream, ep_mlp **out);
+void ep_mlp_destroy(ep_mlp *mlp);
+const char *ep_mlp_last_error(const ep_mlp *mlp);
+
+/* Copies params[EP_MLP_NPARAM] (device) in / out; set also clears the Adam
+ * moments and step count. */
+ep_status ep_mlp_set_params(ep_mlp *mlp, const float *params);
+ep_status ep_mlp_get_params(ep_mlp *mlp, float *params);
+
+/* Y[n][EP_MLP_YS] = network(X[n][EP_MLP_XS]) (any n >= 0). */
+ep_status ep_mlp_forward(ep_mlp *mlp, const float *X, int64_t n, float *Y);
+
+/* Gradient of L over the batch (X, T), 1 <= n <= max_batch: grad
+ * [EP_MLP_NPARAM] and loss (one float) may be NULL.  Deterministic: fixed
+ * tiles of 32 samples, summed in tile order. */
+ep_status ep_mlp_loss_grad(ep_mlp *mlp, const float *X, const float *T, int64_t n,
+                           float *grad, float *loss);
+
+/* One Adam step (beta1 = 0.9, beta2 = 0.999, eps = 1e-8, bias-corrected)
+ * with learning rate lr on the batch gradient; loss as above. */
+ep_status ep_mlp_adam_step(ep_mlp *mlp, const float *X, const float *T, int64_t n, float lr,
+                           float *loss);
+
+/* Training samples from the exact return map (Sections 2.2, 2.3): sample j
+ * takes the pooled state i = idx[j] (0 <= i < n_pool) - strain
+ * eps_pool[6][n_pool], plastic strain ep_pool[6][n_pool], back stress
+ * beta_pool[6][n_pool] (von Mises; NULL = a*ep) or kappa_pool[n_pool]
+ * (Drucker-Prager; NULL = 0) - adds the strain increment deps[6][n], and
+ * writes the features X[n][EP_MLP_XS] and targets T[n][EP_MLP_YS] of the
+ * trial state eps_pool + deps.  3D Voigt throughout.  Enqueued on
+ * hip_stream.  A sample whose index lies outside the pool gets all-zero
+ * rows (checked on the device; no error is reported). */
+ep_status ep_mlp_datagen(const ep_material *material, int64_t n, const int64_t *idx,
+                         int64_t n_pool, const double *eps_pool, const double *ep_pool,
+                         const double *beta_pool, const double *kappa_pool,
+                         const double *deps, float *X, float *T, void *hip_stream);
+
+/* Per-point features of the context's mesh at displacement u with the
+ * committed state: X[n_int][EP_MLP_XS]. */
+ep_status ep_mlp_features(ep_ctx *ctx, const double *u, float *X);
+
+/* Secant predictor of a load step's start (no network): u_out = u_prev +
+ * extrap * (u_prev - u_prev2) on free dofs, u_prev on Dirichlet dofs
+ * (u_prev2 NULL: u_out = u_prev).  u_out may alias u_prev. */
+ep_status ep_predictor(ep_ctx *ctx, const double *u_prev, const double *u_prev2, double extrap,
+                       double *u_out);
+
+/* Learned Newton start for load vector f.  u_pred = u_prev + extrap *
+ * (u_prev - u_prev2) (u_prev2 NULL: u_pred = u_prev).  At u_pred the
+ * network gives sigma_hat and the plastic set; the tangent is K_elast +
+ * B^T (D_hat - D_e) B with D_hat the consistent tangent of the trial state
+ * on the predicted branch (radius ratio capped at 1 where the exact test
+ * says elastic), the residual is Q(f - B^T W sigma_hat) with
+ * sigma_hat = sigma_tr + S y[0:6] at predicted-plastic points and the
+ * elastic trial stress elsewhere, and Jacobi-PCG to relative tolerance pcg_rtol
+ * gives w = u_pred + du.  The exact residuals at w and at u_prev then
+ * decide: u_out = w if res(w) < res(u_prev), else u_prev.  u_out may alias
+ * u_prev.  Writes info (host).  Synchronises. */
+ep_status ep_warm_start(ep_ctx *ctx, ep_mlp *mlp, const double *f, const double *u_prev,
+                        const double *u_prev2, double extrap, double pcg_rtol, double *u_out,
+                        ep_warm_info *info);
 
 #ifdef __cplusplus
 }

@@ -224,14 +224,15 @@ def csr_to_scipy(row_ptr, col_idx, val, n):
 
 def newton_solve(mesh, material, free, f, u0, ep6, beta6, kappa, *, tol=1e-10,
                  max_it=50, linear="direct", dphi=None, w=None, pattern_=None,
-                 history=None):
+                 history=None, raise_on_limit=True):
     """Solve one load step: find u with |Q(f - F(u))| <= tol |Q f|.
 
     The first iterate is u0 (the previous step's displacement on free dofs;
     Dirichlet values are already in u0).  The linear solve is either a sparse
     direct solve (scipy, tiny meshes) or the oracle's Jacobi-PCG with
     forcing tolerance min(1e-2, |r|/|f|).  Returns (u, its, residual history,
-    last constitutive output)."""
+    last constitutive output); at max_it iterations it raises, or returns the
+    last iterate if raise_on_limit is False."""
     import scipy.sparse.linalg as spla
     if dphi is None:
         dphi, w = geometry(mesh)
@@ -254,6 +255,8 @@ def newton_solve(mesh, material, free, f, u0, ep6, beta6, kappa, *, tol=1e-10,
         if rel <= tol:
             return u, it, res, out
         if it == max_it:
+            if not raise_on_limit:
+                return u, it, res, out
             break
         _, _, val = assemble(mesh, dphi, w, out["D"], row_ptr, col_idx)
         if linear == "direct":

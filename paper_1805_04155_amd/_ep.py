@@ -62,6 +62,14 @@ class ep_newton_info(C.Structure):
                 ("n_plastic_ip", C.c_int64), ("n_plastic_elem", C.c_int64)]
 
 
+class ep_warm_info(C.Structure):
+    _fields_ = [("res_rel_pred", C.c_double), ("res_rel_start", C.c_double),
+                ("res_rel_warm", C.c_double), ("pcg_its", C.c_int32), ("accepted", C.c_int32),
+                ("n_plastic_pred", C.c_int64)]
+
+
+MLP_IN, MLP_HID, MLP_OUT, MLP_XS, MLP_YS, MLP_NPARAM = 13, 128, 7, 16, 8, 19207
+
 _lib = None
 
 
@@ -96,6 +104,18 @@ def lib():
             "ep_pcg": [P, P, P, D, I32, P, P],
             "ep_profile": [P, I32],
             "ep_profile_read": [P, I32, P, P],
+            "ep_mlp_create": [I32, I64, P, P],
+            "ep_mlp_destroy": [P],
+            "ep_mlp_last_error": [P],
+            "ep_mlp_set_params": [P, P],
+            "ep_mlp_get_params": [P, P],
+            "ep_mlp_forward": [P, P, I64, P],
+            "ep_mlp_loss_grad": [P, P, P, I64, P, P],
+            "ep_mlp_adam_step": [P, P, P, I64, C.c_float, P],
+            "ep_mlp_datagen": [P, I64, P, I64, P, P, P, P, P, P, P, P],
+            "ep_mlp_features": [P, P, P],
+            "ep_warm_start": [P, P, P, P, P, D, D, P, P],
+            "ep_predictor": [P, P, P, D, P],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -103,6 +123,8 @@ def lib():
             fn.restype = C.c_int
         L.ep_destroy.restype = None
         L.ep_last_error.restype = C.c_char_p
+        L.ep_mlp_destroy.restype = None
+        L.ep_mlp_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -111,7 +133,10 @@ EXPORTED = ["ep_setup", "ep_destroy", "ep_last_error", "ep_set_stream", "ep_get_
             "ep_set_state", "ep_get_state", "ep_geometry", "ep_strain", "ep_constitutive",
             "ep_assemble_tangent", "ep_internal_force", "ep_newton_step", "ep_commit_step",
             "ep_get_plastic", "ep_get_csr", "ep_get_position_map", "ep_spmv", "ep_pcg",
-            "ep_profile", "ep_profile_read"]
+            "ep_profile", "ep_profile_read", "ep_mlp_create", "ep_mlp_destroy",
+            "ep_mlp_last_error", "ep_mlp_set_params", "ep_mlp_get_params", "ep_mlp_forward",
+            "ep_mlp_loss_grad", "ep_mlp_adam_step", "ep_mlp_datagen", "ep_mlp_features",
+            "ep_warm_start", "ep_predictor"]
 
 
 def _ptr(t):
@@ -139,6 +164,11 @@ def _stream():
 # Same names as the C ABI
 # --------------------------------------------------------------------------
 
+def _material(material):
+    return ep_material(EP_VM if material.model == "VM" else EP_DP, material.E, material.nu,
+                       material.Y, material.a, material.eta, material.c)
+
+
 def ep_setup(mesh, free, material, options=None, quadrature=None, stream=None):
     """mesh: workloads.Mesh; free: uint8 (n_dof,); material: workloads.Material;
     options: dict of ep_options fields."""
@@ -148,8 +178,7 @@ def ep_setup(mesh, free, material, options=None, quadrature=None, stream=None):
     free = np.ascontiguousarray(free, dtype=np.uint8)
     m = ep_mesh(dim, et, mesh.n_nodes, mesh.n_elems, coord.ctypes.data, elem.ctypes.data,
                 free.ctypes.data)
-    mat = ep_material(EP_VM if material.model == "VM" else EP_DP, material.E, material.nu,
-                      material.Y, material.a, material.eta, material.c)
+    mat = _material(material)
     opt = ep_options(EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2)
     for k, v in (options or {}).items():
         setattr(opt, k, v)
@@ -372,3 +401,129 @@ class Context:
         x = self._empty((self.sizes["n_dof"],))
         st, its, rel = ep_pcg(self.h, b, x, rtol, max_it)
         return x, st, its, rel
+
+    def mlp_features(self, u):
+        X = self._empty((self.sizes["n_int"], MLP_XS), self.torch.float32)
+        ep_mlp_features(self.h, u, X)
+        return X
+
+    def warm_start(self, mlp, f, u_prev, u_prev2, extrap, pcg_rtol, u_out):
+        return ep_warm_start(self.h, mlp.h, f, u_prev, u_prev2, extrap, pcg_rtol, u_out)
+
+
+# ---- learned warm start ----
+
+def _check_mlp(m, st):
+    if st != EP_OK:
+        msg = lib().ep_mlp_last_error(m)
+        raise EpError(st, msg.decode() if msg else "")
+    return st
+
+
+def ep_mlp_create(prec, max_batch, stream=None):
+    h = C.c_void_p()
+    _check(None, lib().ep_mlp_create(prec, max_batch,
+                                     stream if stream is not None else _stream(), C.byref(h)))
+    return h
+
+
+def ep_mlp_destroy(m):
+    lib().ep_mlp_destroy(m)
+
+
+def ep_mlp_last_error(m):
+    return lib().ep_mlp_last_error(m).decode()
+
+
+def ep_mlp_set_params(m, params):
+    _check_mlp(m, lib().ep_mlp_set_params(m, _ptr(params)))
+
+
+def ep_mlp_get_params(m, params):
+    _check_mlp(m, lib().ep_mlp_get_params(m, _ptr(params)))
+
+
+def ep_mlp_forward(m, X, n, Y):
+    _check_mlp(m, lib().ep_mlp_forward(m, _ptr(X), n, _ptr(Y)))
+
+
+def ep_mlp_loss_grad(m, X, T, n, grad=None, loss=None):
+    _check_mlp(m, lib().ep_mlp_loss_grad(m, _ptr(X), _ptr(T), n, _ptr(grad), _ptr(loss)))
+
+
+def ep_mlp_adam_step(m, X, T, n, lr, loss=None):
+    _check_mlp(m, lib().ep_mlp_adam_step(m, _ptr(X), _ptr(T), n, float(lr), _ptr(loss)))
+
+
+def ep_mlp_datagen(material, n, idx, n_pool, eps_pool, ep_pool, beta_pool, kappa_pool, deps,
+                   X, T, stream=None):
+    mat = _material(material)
+    _check(None, lib().ep_mlp_datagen(C.byref(mat), n, _ptr(idx), n_pool, _ptr(eps_pool),
+                                      _ptr(ep_pool), _ptr(beta_pool), _ptr(kappa_pool),
+                                      _ptr(deps), _ptr(X), _ptr(T),
+                                      stream if stream is not None else _stream()))
+
+
+def ep_mlp_features(ctx, u, X):
+    _check(ctx, lib().ep_mlp_features(ctx, _ptr(u), _ptr(X)))
+
+
+def ep_predictor(ctx, u_prev, u_prev2, extrap, u_out):
+    _check(ctx, lib().ep_predictor(ctx, _ptr(u_prev), _ptr(u_prev2), float(extrap), _ptr(u_out)))
+
+
+def ep_warm_start(ctx, m, f, u_prev, u_prev2, extrap, pcg_rtol, u_out):
+    info = ep_warm_info()
+    st = lib().ep_warm_start(ctx, m, _ptr(f), _ptr(u_prev), _ptr(u_prev2), float(extrap),
+                             float(pcg_rtol), _ptr(u_out), C.byref(info))
+    if st not in (EP_OK, EP_ENOTCONV):
+        _check(ctx, st)
+    return st, {k: getattr(info, k) for k, _ in ep_warm_info._fields_}
+
+
+class Mlp:
+    """Owns an ep_mlp handle; torch tensors for inputs and outputs."""
+
+    def __init__(self, prec=EP_FP32, max_batch=8192):
+        import torch
+        self.torch = torch
+        self.prec = prec
+        self.max_batch = max_batch
+        self.h = ep_mlp_create(prec, max_batch)
+
+    def close(self):
+        if self.h is not None:
+            ep_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        t = self.torch.as_tensor(np.ascontiguousarray(params, dtype=np.float32)).cuda() \
+            if not isinstance(params, self.torch.Tensor) else params.contiguous()
+        ep_mlp_set_params(self.h, t)
+        self.torch.cuda.synchronize()
+
+    def params(self):
+        p = self.torch.empty(MLP_NPARAM, dtype=self.torch.float32, device="cuda")
+        ep_mlp_get_params(self.h, p)
+        return p
+
+    def forward(self, X):
+        n = X.shape[0]
+        Y = self.torch.empty((n, MLP_YS), dtype=self.torch.float32, device="cuda")
+        ep_mlp_forward(self.h, X, n, Y)
+        return Y
+
+    def loss_grad(self, X, T):
+        g = self.torch.empty(MLP_NPARAM, dtype=self.torch.float32, device="cuda")
+        loss = self.torch.empty(1, dtype=self.torch.float32, device="cuda")
+        ep_mlp_loss_grad(self.h, X, T, X.shape[0], g, loss)
+        return g, loss
+
+    def adam_step(self, X, T, lr, loss=None):
+        ep_mlp_adam_step(self.h, X, T, X.shape[0], lr, loss)

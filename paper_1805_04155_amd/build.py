@@ -16,7 +16,7 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
-SOURCES = ["ep_kernels.hip", "ep_host.cpp"]
+SOURCES = ["ep_kernels.hip", "ep_mlp.hip", "ep_host.cpp"]
 
 
 def build(verbose: bool = False) -> str:

@@ -16,7 +16,39 @@ using namespace ep;
 
 namespace ep {
 hipError_t launch_pcg_beta_init(Ctx &c, double rtol);
+
+const char *material_error(const ep_material *mat) {
+  if (!(mat->E > 0) || !(mat->nu >= 0 && mat->nu < 0.5)) return "need E > 0 and 0 <= nu < 0.5";
+  if (mat->model == EP_VM) {
+    if (!(mat->Y > 0) || !(mat->a >= 0)) return "von Mises needs Y > 0, a >= 0";
+  } else if (mat->model == EP_DP) {
+    if (!(mat->eta > 0) || !(mat->c > 0) || !(mat->a >= 0))
+      return "Drucker-Prager needs eta > 0, c > 0, a >= 0";
+  } else {
+    return "unknown model";
+  }
+  return nullptr;
 }
+
+// shear and bulk moduli from E and nu (Section 2.1)
+MatC make_matc(const ep_material &mat) {
+  MatC m{};
+  m.model = mat.model;
+  m.G = mat.E / (2.0 * (1.0 + mat.nu));
+  m.K = mat.E / (3.0 * (1.0 - 2.0 * mat.nu));
+  m.a = mat.a;
+  m.Y = mat.Y;
+  m.eta = mat.eta;
+  m.c = mat.c;
+  return m;
+}
+
+void mlp_scales(const MatC &m, double E, double &s_in, double &s_out) {
+  const double S = m.model == EP_VM ? std::sqrt(1.5) * m.Y : m.c;
+  s_in = E / S;
+  s_out = 1.0 / S;
+}
+}  // namespace ep
 
 namespace {
 
@@ -192,7 +224,7 @@ void free_ctx(Ctx *c) {
                   c->Fe, c->em[0], c->em[1], c->plist, c->coff, c->ptotals, c->cmp_counts,
                   c->cmp_counts2, c->cmp_counts3, c->cmp_offsets, c->F, c->r, c->partials,
                   c->norms, c->pz, c->pp[0], c->pp[1], c->pq, c->px, c->dinv, c->sc,
-                  c->iscratch};
+                  c->iscratch, c->mlp_x, c->mlp_y, c->wu_pred, c->wu_warm};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->norms_h) (void)hipHostFree(c->norms_h);
@@ -252,9 +284,14 @@ void Ctx::prof_collect() {
 // ---------------------------------------------------------------------------
 namespace {
 
-ep_status do_constitutive(Ctx *c, const double *u, double *sig, double *D, uint8_t *flag) {
+ep_status do_constitutive(Ctx *c, const double *u, double *sig, double *D, uint8_t *flag,
+                          const float *learned_y = nullptr) {
   ConstArgs a{};
   a.u = u;
+  if (learned_y) {
+    a.learned = 2;
+    a.mlp_y = learned_y;
+  }
   a.return_map = true;
   a.sig_out = sig;
   a.D_out = D;
@@ -328,6 +365,29 @@ ep_status do_pcg(Ctx *c, const double *b, double *x, double rtol, int max_it, in
   return EP_OK;
 }
 
+// exact residual |Q(f - F(u))| / |Q f| (constitutive pass + force gather);
+// synchronises
+ep_status exact_residual(Ctx *c, const double *f, const double *u, double *res_rel) {
+  ep_status st = do_constitutive(c, u, nullptr, nullptr, nullptr);
+  if (st) return st;
+  st = do_residual(c, f, nullptr);
+  if (st) return st;
+  HIPC(hipMemcpyAsync(c->norms_h, c->norms, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPC(hipStreamSynchronize(c->stream));
+  const double rn = std::sqrt(c->norms_h[0]), fn = std::sqrt(c->norms_h[1]);
+  *res_rel = fn > 0 ? rn / fn : rn;
+  return EP_OK;
+}
+
+ep_status ensure_warm_buffers(Ctx *c) {
+  if (c->mlp_x) return EP_OK;
+  HIPC(dalloc(&c->mlp_x, c->n_int * EP_MLP_XS));
+  HIPC(dalloc(&c->mlp_y, c->n_int * EP_MLP_YS));
+  HIPC(dalloc(&c->wu_pred, c->n_dof));
+  HIPC(dalloc(&c->wu_warm, c->n_dof));
+  return EP_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -361,16 +421,7 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   if ((int64_t)mesh->dim * mesh->n_nodes >= (int64_t)1 << 31 ||
       mesh->n_elems * ed.n_p * ed.n_p >= (int64_t)1 << 31)
     return fail("ep_setup: mesh too large for 32-bit indices", EP_EINVAL);
-  if (!(mat->E > 0) || !(mat->nu >= 0 && mat->nu < 0.5))
-    return fail("ep_setup: need E > 0 and 0 <= nu < 0.5", EP_EINVAL);
-  if (mat->model == EP_VM) {
-    if (!(mat->Y > 0) || !(mat->a >= 0)) return fail("ep_setup: von Mises needs Y > 0, a >= 0", EP_EINVAL);
-  } else if (mat->model == EP_DP) {
-    if (!(mat->eta > 0) || !(mat->c > 0) || !(mat->a >= 0))
-      return fail("ep_setup: Drucker-Prager needs eta > 0, c > 0, a >= 0", EP_EINVAL);
-  } else {
-    return fail("ep_setup: unknown model", EP_EINVAL);
-  }
+  if (const char *bad = material_error(mat)) return fail(std::string("ep_setup: ") + bad, EP_EINVAL);
   const int64_t n_n = mesh->n_nodes, n_e = mesh->n_elems;
   const int dim = ed.dim, n_p = ed.n_p, n_q = ed.n_q;
   for (int64_t i = 0; i < n_e * n_p; ++i)
@@ -418,13 +469,8 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   c->n_int = n_e * n_q;
   c->n_dof = dim * n_n;
   c->opt = opt;
-  c->mat.model = mat->model;
-  c->mat.G = mat->E / (2.0 * (1.0 + mat->nu));
-  c->mat.K = mat->E / (3.0 * (1.0 - 2.0 * mat->nu));
-  c->mat.a = mat->a;
-  c->mat.Y = mat->Y;
-  c->mat.eta = mat->eta;
-  c->mat.c = mat->c;
+  c->mat = make_matc(*mat);
+  c->E = mat->E;
 
   auto bail = [&](ep_status s) {
     g_setup_err = c->err;
@@ -875,6 +921,89 @@ ep_status ep_profile_read(ep_ctx *ctx, int32_t k, double *ms, int64_t *count) {
   if (count) *count = c->prof_n[k];
   c->prof_ms[k] = 0;
   c->prof_n[k] = 0;
+  return EP_OK;
+}
+
+
+ep_status ep_mlp_features(ep_ctx *ctx, const double *u, float *X) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!u || !X) return EP_EINVAL;
+  ConstArgs a{};
+  a.u = u;
+  a.learned = 1;
+  a.mlp_x = X;
+  HIPC(launch_constitutive(*c, a));
+  return EP_OK;
+}
+
+ep_status ep_predictor(ep_ctx *ctx, const double *u_prev, const double *u_prev2, double extrap,
+                       double *u_out) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!u_prev || !u_out || !std::isfinite(extrap)) return EP_EINVAL;
+  HIPC(launch_extrapolate(*c, u_prev, u_prev2, extrap, u_out));
+  return EP_OK;
+}
+
+ep_status ep_warm_start(ep_ctx *ctx, ep_mlp *mlp, const double *f, const double *u_prev,
+                        const double *u_prev2, double extrap, double pcg_rtol, double *u_out,
+                        ep_warm_info *info) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!mlp || !f || !u_prev || !u_out || !info || !(pcg_rtol > 0) || !std::isfinite(extrap)) {
+    c->err = "ep_warm_start: invalid argument";
+    return EP_EINVAL;
+  }
+  std::memset(info, 0, sizeof(*info));
+  const MlpImpl *m = reinterpret_cast<const MlpImpl *>(mlp);
+  if (m->stream != c->stream) HIPC(hipStreamSynchronize(m->stream));
+  ep_status st = ensure_warm_buffers(c);
+  if (st) return st;
+  // exact residual of the plain start
+  st = exact_residual(c, f, u_prev, &info->res_rel_start);
+  if (st) return st;
+  // prediction at the extrapolated displacement
+  HIPC(launch_extrapolate(*c, u_prev, u_prev2, extrap, c->wu_pred));
+  ConstArgs fa{};
+  fa.u = c->wu_pred;
+  fa.learned = 1;
+  fa.mlp_x = c->mlp_x;
+  HIPC(launch_constitutive(*c, fa));
+  HIPC(launch_mlp_forward(*m, c->mlp_x, c->n_int, c->mlp_y, c->stream));
+  st = do_constitutive(c, c->wu_pred, nullptr, nullptr, nullptr, c->mlp_y);
+  if (st) return st;
+  st = do_residual(c, f, nullptr);
+  if (st) return st;
+  int32_t tot[3];
+  HIPC(hipMemcpyAsync(c->norms_h, c->norms, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPC(hipMemcpyAsync(tot, c->ptotals, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPC(hipStreamSynchronize(c->stream));
+  {
+    const double rn = std::sqrt(c->norms_h[0]), fn = std::sqrt(c->norms_h[1]);
+    info->res_rel_pred = fn > 0 ? rn / fn : rn;
+  }
+  info->n_plastic_pred = tot[1];
+  // one solve with the predicted tangent and residual
+  st = do_assemble(c);
+  if (st) return st;
+  int its = 0;
+  double rel = 0;
+  const ep_status ps = do_pcg(c, c->r, c->px, pcg_rtol, c->opt.pcg_max_it, &its, &rel);
+  if (ps != EP_OK && ps != EP_ENOTCONV) return ps;
+  info->pcg_its = its;
+  HIPC(hipMemcpyAsync(c->wu_warm, c->wu_pred, c->n_dof * sizeof(double), hipMemcpyDeviceToDevice,
+                      c->stream));
+  HIPC(launch_axpy_free(*c, c->px, c->wu_warm));
+  // the exact residual decides
+  st = exact_residual(c, f, c->wu_warm, &info->res_rel_warm);
+  if (st) return st;
+  info->accepted = std::isfinite(info->res_rel_warm) && info->res_rel_warm < info->res_rel_start;
+  const double *src = info->accepted ? c->wu_warm : u_prev;
+  if (src != u_out)
+    HIPC(hipMemcpyAsync(u_out, src, c->n_dof * sizeof(double), hipMemcpyDeviceToDevice,
+                        c->stream));
+  HIPC(hipStreamSynchronize(c->stream));
   return EP_OK;
 }
 

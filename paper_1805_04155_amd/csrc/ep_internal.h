@@ -51,6 +51,12 @@ struct ConstArgs {
   uint8_t *flag_out;     // [n_int] or nullptr (internal flag always written)
   bool commit;           // write the updated state
   bool force;            // element force vectors + plastic mask
+  // learned warm start: 1 = write MLP features to mlp_x instead of the
+  // return map; 2 = take the plastic flag and stress from the MLP outputs
+  // mlp_y (tangent of the trial state on the predicted branch)
+  int learned = 0;
+  float *mlp_x = nullptr;       // [n_int][EP_MLP_XS]
+  const float *mlp_y = nullptr; // [n_int][EP_MLP_YS]
 };
 hipError_t launch_constitutive(Ctx &c, const ConstArgs &a);
 hipError_t launch_geometry(Ctx &c, double *dphi, double *w, int32_t *bad_count);
@@ -76,6 +82,34 @@ hipError_t launch_spmv(Ctx &c, const double *x, double *y, bool fused_p, double 
 hipError_t launch_pcg_init(Ctx &c, const double *b, double *x);
 hipError_t launch_pcg_iteration(Ctx &c, double *x);
 hipError_t launch_axpy_free(Ctx &c, const double *du, double *u);
+// u_out = u + t (u - u2) on free dofs, u on Dirichlet dofs (u2 == nullptr: copy)
+hipError_t launch_extrapolate(Ctx &c, const double *u, const double *u2, double t, double *u_out);
+
+// ---- MLP (ep_mlp.hip) ----
+struct MlpImpl {
+  std::string err;
+  int prec = EP_FP32;
+  int64_t max_batch = 0;
+  hipStream_t stream = nullptr;
+  float *params = nullptr, *m1 = nullptr, *m2 = nullptr;
+  float *part = nullptr, *part_loss = nullptr;  // per-tile partial gradients
+  int64_t step = 0;                             // Adam steps taken
+};
+hipError_t launch_mlp_forward(const MlpImpl &m, const float *X, int64_t n, float *Y,
+                              hipStream_t s);
+hipError_t launch_mlp_train(MlpImpl &m, const float *X, const float *T, int64_t n, float *grad,
+                            float *loss, bool adam, float lr, float bc1, float bc2);
+hipError_t launch_mlp_datagen(const MatC &mat, int64_t n, const int64_t *idx, int64_t n_pool,
+                              const double *eps_pool, const double *ep_pool,
+                              const double *beta_pool, const double *kappa_pool,
+                              const double *deps, float *X, float *T, double s_in, double s_out,
+                              hipStream_t s);
+int64_t mlp_tile_samples();
+// feature / output scales of a material: s_in = E/S, s_out = 1/S
+void mlp_scales(const MatC &m, double E, double &s_in, double &s_out);
+// material checks shared by ep_setup and the sample generator (ep_host.cpp)
+const char *material_error(const ep_material *mat);  // nullptr if valid
+MatC make_matc(const ep_material &mat);
 
 // ---- context ----
 struct Ctx {
@@ -157,6 +191,11 @@ struct Ctx {
   double *pz = nullptr, *pp[2] = {nullptr, nullptr}, *pq = nullptr, *px = nullptr,
          *dinv = nullptr, *sc = nullptr, *sc_h = nullptr;
   int pcur = 0;
+
+  // learned warm start (allocated at first use)
+  float *mlp_x = nullptr, *mlp_y = nullptr;  // [n_int][16], [n_int][8]
+  double *wu_pred = nullptr, *wu_warm = nullptr;  // [n_dof]
+  double E = 0.0;
 
   // profiling
   bool prof = false;

@@ -13,6 +13,7 @@
 // matrices uses colour rounds (elements of one colour share no node) and no
 // floating-point atomics.
 #include "ep_internal.h"
+#include "ep_return_map.h"
 
 namespace ep {
 
@@ -80,133 +81,6 @@ __device__ inline void grad(const double Ji[D][D], const double *drp, double g[D
 }
 
 // ----------------------------------------------------------------------------
-// Return maps on Voigt vectors.  eps, ep: strain-type (engineering shears);
-// sig, beta, n: stress-type.  desc receives the tangent increment
-//   D - C = alpha*DEV + b*n n^T + g*(n 1^T + 1 n^T) + d*1 1^T
-// as [n(6), alpha, b, g, d] with DEV the deviatoric projector mapping
-// strain-type to stress-type vectors and 1 = (1,1,1,0,0,0).
-// ----------------------------------------------------------------------------
-__device__ inline void trial(const MatC &m, const double eps[6], const double ep[6], double dv[6],
-                             double &tr) {
-  double e[6];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) e[i] = eps[i] - ep[i];
-  tr = e[0] + e[1] + e[2];
-  const double t3 = tr / 3.0;
-  dv[0] = e[0] - t3;
-  dv[1] = e[1] - t3;
-  dv[2] = e[2] - t3;
-  dv[3] = 0.5 * e[3];
-  dv[4] = 0.5 * e[4];
-  dv[5] = 0.5 * e[5];
-}
-
-// von Mises, linear kinematic hardening (eqs. T_kinematic, DT_kinematic, T_other)
-__device__ inline int rm_vm(const MatC &m, const double eps[6], double ep[6], double beta[6],
-                           double sig[6], double desc[10], bool commit) {
-#pragma clang fp contract(off)
-  double dv[6], tr;
-  trial(m, eps, ep, dv, tr);
-  const double G2 = 2.0 * m.G;
-  double s[6];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    sig[i] = G2 * dv[i] + (i < 3 ? m.K * tr : 0.0);
-    s[i] = G2 * dv[i] - beta[i];
-  }
-  const double ns = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2] +
-                         2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
-  const double crit = ns - m.Y;
-  if (!(crit > 0.0)) return 0;
-  const double h = G2 + m.a;
-  const double dl = crit / h;
-  const double c1 = G2 * G2 / h;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    const double n = s[i] / ns;
-    desc[i] = n;
-    sig[i] -= G2 * dl * n;
-    if (commit) {
-      ep[i] += (i < 3 ? 1.0 : 2.0) * dl * n;
-      beta[i] += m.a * dl * n;
-    }
-  }
-  desc[6] = c1 * (m.Y / ns - 1.0);
-  desc[7] = -c1 * m.Y / ns;
-  desc[8] = 0.0;
-  desc[9] = 0.0;
-  return 1;
-}
-
-// Drucker-Prager with yield function |s|/sqrt2 + eta p - (c + a kappa)
-// (Section 2.3; a = 0 perfect plasticity).  1 = smooth cone, 2 = apex.
-__device__ inline int rm_dp(const MatC &m, const double eps[6], double ep[6], double &kappa,
-                           double sig[6], double desc[10], bool commit) {
-#pragma clang fp contract(off)
-  const double r2 = 1.4142135623730951;
-  double dv[6], tr;
-  trial(m, eps, ep, dv, tr);
-  const double G2 = 2.0 * m.G;
-  const double p = m.K * tr;
-  const double dd = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2] +
-                    2.0 * (dv[3] * dv[3] + dv[4] * dv[4] + dv[5] * dv[5]);
-  const double rho = G2 * sqrt(dd);
-#pragma unroll
-  for (int i = 0; i < 6; ++i) sig[i] = G2 * dv[i] + (i < 3 ? p : 0.0);
-  const double ck = m.c + m.a * kappa;
-  const double Ke2 = m.K * m.eta * m.eta;
-  const double crit1 = rho / r2 + m.eta * p - ck;
-  const double crit2 = m.eta * p - ck - (Ke2 + m.a) * rho / (r2 * m.G);
-  if (!(crit1 > 0.0)) return 0;
-  if (crit2 <= 0.0) {
-    const double h = m.G + Ke2 + m.a;
-    const double dl = crit1 / h;
-    const double c2 = 2.0 * r2 * m.G * m.G * dl / rho;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      const double n = G2 * dv[i] / rho;
-      desc[i] = n;
-      sig[i] -= dl * (r2 * m.G * n + (i < 3 ? m.K * m.eta : 0.0));
-      if (commit) ep[i] += i < 3 ? dl * (n / r2 + m.eta / 3.0) : 2.0 * dl * n / r2;
-    }
-    desc[6] = -c2;
-    desc[7] = c2 - 2.0 * m.G * m.G / h;
-    desc[8] = -r2 * m.G * m.K * m.eta / h;
-    desc[9] = -Ke2 * m.K / h;
-    if (commit) kappa += dl;
-    return 1;
-  }
-  const double dl = (m.eta * p - ck) / (Ke2 + m.a);
-  const double pk = p - m.K * m.eta * dl;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    sig[i] = i < 3 ? pk : 0.0;
-    desc[i] = 0.0;
-    if (commit) ep[i] = i < 3 ? eps[i] - pk / (3.0 * m.K) : eps[i];
-  }
-  desc[6] = -G2;
-  desc[7] = 0.0;
-  desc[8] = 0.0;
-  desc[9] = -Ke2 * m.K / (Ke2 + m.a);
-  if (commit) kappa += dl;
-  return 2;
-}
-
-// Full Voigt tangent entry (I, J) = C + (D - C) from the descriptor.
-__device__ inline double tangent_entry(const MatC &m, const double *desc, bool plastic, int I,
-                                       int J) {
-  const double one_I = I < 3 ? 1.0 : 0.0, one_J = J < 3 ? 1.0 : 0.0;
-  const double dev = (I == J ? (I < 3 ? 1.0 : 0.5) : 0.0) - one_I * one_J / 3.0;
-  double v = 2.0 * m.G * dev + m.K * one_I * one_J;
-  if (plastic) {
-    const double nI = desc[I], nJ = desc[J];
-    v += desc[6] * dev + desc[7] * nI * nJ + desc[8] * (nI * one_J + one_I * nJ) +
-         desc[9] * one_I * one_J;
-  }
-  return v;
-}
-
-// ----------------------------------------------------------------------------
 // Fused constitutive pass: strain, return map, tangent descriptor, element
 // force vectors and plastic bitmask.  One thread per integration point; the
 // EPB elements of a block stage their node coordinates and displacements in
@@ -227,11 +101,18 @@ struct KC {
   double *eps_out, *sig_out, *D_out;
   uint8_t *flag_out;
   int rm, commit, force;
+  float *mlp_x;          // features out (LM = 1)
+  const float *mlp_y;    // network outputs in (LM = 2)
+  double s_in, S;        // feature scale E/S and stress scale S
 };
 
 constexpr int CT = 256;  // threads of the constitutive kernel
 
-template <int ETID, int MODEL>
+// LM = 0: exact return map.  LM = 1: per-point features of the learned warm
+// start instead (trial elastic strain, plastic strain, kappa, scaled).
+// LM = 2: plastic flag and stress from the network outputs; the tangent
+// descriptor is that of the trial state on the predicted branch.
+template <int ETID, int MODEL, int LM>
 __global__ __launch_bounds__(CT) void k_constitutive(KC a) {
   using T = Et<ETID>;
   constexpr int D = T::D, NP = T::NP, NQ = T::NQ;
@@ -310,7 +191,20 @@ __global__ __launch_bounds__(CT) void k_constitutive(KC a) {
       }
     }
     double sig[6] = {0, 0, 0, 0, 0, 0};
-    if (a.rm) {
+    if constexpr (LM == 1) {
+      double ep[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int c = 0; c < NSC; ++c) ep[c] = a.ep[c * N + ip];
+      const double kap = MODEL == EP_DP ? a.kappa[ip] : 0.0;
+      float *x = a.mlp_x + ip * EP_MLP_XS;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        x[c] = (float)(a.s_in * (eps[c] - ep[c]));
+        x[6 + c] = (float)(a.s_in * ep[c]);
+      }
+      x[12] = (float)(a.s_in * kap);
+      x[13] = x[14] = x[15] = 0.f;
+    } else if (a.rm) {
       double ep[6] = {0, 0, 0, 0, 0, 0}, bt[6] = {0, 0, 0, 0, 0, 0}, kap = 0.0;
 #pragma unroll
       for (int c = 0; c < NSC; ++c) ep[c] = a.ep[c * N + ip];
@@ -321,9 +215,26 @@ __global__ __launch_bounds__(CT) void k_constitutive(KC a) {
         kap = a.kappa[ip];
       }
       double desc[10];
-      const bool commit = a.commit != 0;
-      const int f = MODEL == EP_VM ? rm_vm(a.m, eps, ep, bt, sig, desc, commit)
-                                   : rm_dp(a.m, eps, ep, kap, sig, desc, commit);
+      const bool commit = LM == 0 && a.commit != 0;
+      int f;
+      if constexpr (LM == 2) {
+        // stress: elastic trial, plus the network's plastic correction at
+        // points it predicts plastic
+        const float *y = a.mlp_y + ip * EP_MLP_YS;
+        f = y[6] > 0.f ? 1 : 0;
+        double dv[6], tr;
+        trial(a.m, eps, ep, dv, tr);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sig[c] = 2.0 * a.m.G * dv[c] + (c < 3 ? a.m.K * tr : 0.0);
+        if (f) {
+          f = predicted_tangent(a.m, eps, ep, bt, kap, desc);
+#pragma unroll
+          for (int c = 0; c < 6; ++c) sig[c] += a.S * (double)y[c];
+        }
+      } else {
+        f = MODEL == EP_VM ? rm_vm(a.m, eps, ep, bt, sig, desc, commit)
+                           : rm_dp(a.m, eps, ep, kap, sig, desc, commit);
+      }
       a.flag[ip] = (uint8_t)f;
       if (a.flag_out) a.flag_out[ip] = (uint8_t)f;
       if (f) {
@@ -353,7 +264,7 @@ __global__ __launch_bounds__(CT) void k_constitutive(KC a) {
             a.D_out[(I * NSTR + J) * N + ip] = tangent_entry(a.m, desc, f != 0, vI, vJ);
           }
       }
-      if (a.commit && f) {
+      if (commit && f) {
 #pragma unroll
         for (int c = 0; c < NSC; ++c) a.ep[c * N + ip] = ep[c];
         if (MODEL == EP_VM) {
@@ -1462,6 +1373,14 @@ __global__ void k_axpy_free(int64_t n, const double *du, const uint8_t *freem, d
   if (i < n && freem[i]) u[i] += du[i];
 }
 
+__global__ void k_extrapolate(int64_t n, const double *u, const double *u2, double t,
+                              const uint8_t *freem, double *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = u[i];
+  out[i] = (u2 && freem[i]) ? v + t * (v - u2[i]) : v;
+}
+
 __global__ void k_to_float(const double *src, float *dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = (float)src[i];
@@ -1497,12 +1416,25 @@ static hipError_t constitutive_et(Ctx &c, const ConstArgs &ca) {
   a.rm = ca.return_map;
   a.commit = ca.commit;
   a.force = ca.force;
+  a.mlp_x = ca.mlp_x;
+  a.mlp_y = ca.mlp_y;
+  double s_out;
+  mlp_scales(c.mat, c.E, a.s_in, s_out);
+  a.S = 1.0 / s_out;
   const int grid = ceil_div(c.n_e, EPB);
   if (grid == 0) return hipSuccess;
-  if (c.mat.model == EP_VM)
-    hipLaunchKernelGGL((k_constitutive<ETID, EP_VM>), dim3(grid), dim3(CT), 0, c.stream, a);
-  else
-    hipLaunchKernelGGL((k_constitutive<ETID, EP_DP>), dim3(grid), dim3(CT), 0, c.stream, a);
+#define CONST_LAUNCH(MODEL, LM) \
+  hipLaunchKernelGGL((k_constitutive<ETID, MODEL, LM>), dim3(grid), dim3(CT), 0, c.stream, a)
+  if (c.mat.model == EP_VM) {
+    if (ca.learned == 1) CONST_LAUNCH(EP_VM, 1);
+    else if (ca.learned == 2) CONST_LAUNCH(EP_VM, 2);
+    else CONST_LAUNCH(EP_VM, 0);
+  } else {
+    if (ca.learned == 1) CONST_LAUNCH(EP_DP, 1);
+    else if (ca.learned == 2) CONST_LAUNCH(EP_DP, 2);
+    else CONST_LAUNCH(EP_DP, 0);
+  }
+#undef CONST_LAUNCH
   return hipGetLastError();
 }
 
@@ -1786,6 +1718,13 @@ hipError_t launch_axpy_free(Ctx &c, const double *du, double *u) {
   if (c.n_dof == 0) return hipSuccess;
   hipLaunchKernelGGL(k_axpy_free, dim3(ceil_div(c.n_dof, 256)), dim3(256), 0, c.stream, c.n_dof,
                      du, c.freem, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_extrapolate(Ctx &c, const double *u, const double *u2, double t, double *out) {
+  if (c.n_dof == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_extrapolate, dim3(ceil_div(c.n_dof, 256)), dim3(256), 0, c.stream, c.n_dof,
+                     u, u2, t, c.freem, out);
   return hipGetLastError();
 }
 

@@ -427,6 +427,27 @@ def workload_q1_cube(n=64) -> Workload:
                     54.0 * np.arange(1, 11, dtype=np.float64))
 
 
+def cyclic_factors(steps: int = 30, t_max: float = 540.0):
+    """Traction history zeta(t) * t_max at t_k = 4k/steps, k = 1..steps, with
+    zeta piecewise linear: 0 -> 1 on [0, 1], down to -1 at t = 3, back to 0
+    at t = 4 (the loading / unloading / reverse loading history of the
+    paper's von Mises example, Section 8.2)."""
+    out = []
+    for k in range(1, steps + 1):
+        t = 4.0 * k / steps
+        z = t if t <= 1.0 else (1.0 - (t - 1.0) if t <= 3.0 else -1.0 + (t - 3.0))
+        out.append(z * t_max)
+    return np.array(out)
+
+
+def workload_q1_cube_cyclic(n=64, steps=30) -> Workload:
+    """The Q1 cube under the cyclic traction history (learned warm start
+    workload): same mesh, material and supports as workload_q1_cube."""
+    wl = workload_q1_cube(n)
+    return Workload("q1_cube_vm_cyclic", wl.mesh, wl.material, wl.free, wl.f_unit,
+                    cyclic_factors(steps, 540.0))
+
+
 def _block_bcs(mesh):
     return free_mask(mesh, [(2, 0.0, [0, 1, 2]), (0, 0.0, [0]), (0, 2.0, [0]),
                             (1, 0.0, [1]), (1, 1.0, [1])])

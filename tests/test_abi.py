@@ -36,7 +36,7 @@ def test_struct_layouts_match_header():
     """ctypes structures mirror the header field by field."""
     text = open(os.path.join(ROOT, "include", "ep.h")).read()
     for st in ("ep_mesh", "ep_material", "ep_options", "ep_sizes", "ep_newton_info",
-               "ep_quadrature"):
+               "ep_quadrature", "ep_warm_info"):
         m = re.search(r"typedef struct \{([^{}]*)\}\s*" + st + ";", text)
         assert m, st
         body = re.sub(r"/\*.*?\*/", "", m.group(1), flags=re.S)
@@ -57,3 +57,13 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_ep, "_lib", None)
     with pytest.raises(ImportError):
         _ep.lib()
+
+
+def test_mlp_constants_match_header():
+    text = open(os.path.join(ROOT, "include", "ep.h")).read()
+    for name, val in (("IN", _ep.MLP_IN), ("HID", _ep.MLP_HID), ("OUT", _ep.MLP_OUT),
+                      ("XS", _ep.MLP_XS), ("YS", _ep.MLP_YS), ("NPARAM", _ep.MLP_NPARAM)):
+        m = re.search(r"#define EP_MLP_" + name + r"\s+(\d+)", text)
+        assert m and int(m.group(1)) == val, name
+    assert _ep.MLP_NPARAM == (_ep.MLP_IN * _ep.MLP_HID + _ep.MLP_HID + _ep.MLP_HID ** 2
+                              + _ep.MLP_HID + _ep.MLP_OUT * _ep.MLP_HID + _ep.MLP_OUT)

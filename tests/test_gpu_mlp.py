@@ -1,0 +1,304 @@
+"""The learned warm start on the GPU against the FP64 oracle (oracle/mlp.py):
+training samples, forward pass, loss gradient (FP32 and BF16 products, FP32
+accumulation), Adam, per-point features and the warm start itself; then what
+a trained network gains on a cyclic load path."""
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from gpu_cases import make_case  # noqa: E402
+from paper_1805_04155_amd import _ep, learned, solver  # noqa: E402
+from paper_1805_04155_amd import workloads as W  # noqa: E402
+
+PREC = {"fp32": _ep.EP_FP32, "bf16": _ep.EP_BF16}
+# relative gradient error bounds: FP32 products accumulate ~1e-7 relative
+# rounding per term over <= 128-term sums and 32-sample tiles; BF16 operands
+# carry 2^-9 relative rounding each
+GTOL = {"fp32": 1e-5, "bf16": 3e-2}
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def _params(seed):
+    p = M.he_uniform(seed)
+    p += 0.05 * np.random.default_rng(seed + 1).standard_normal(p.shape)
+    return p.astype(np.float32)
+
+
+def _batch(seed, n):
+    rng = np.random.default_rng(seed)
+    X = np.zeros((n, M.XS), np.float32)
+    X[:, :M.NI] = rng.standard_normal((n, M.NI))
+    T = np.zeros((n, M.YS), np.float32)
+    T[:, :6] = rng.standard_normal((n, 6))
+    T[:, 6] = rng.integers(0, 2, n)
+    return X, T
+
+
+def _pool(material, n, seed, a=0.8):
+    rng = np.random.default_rng(seed)
+    scale = (material.Y if material.model == "VM" else material.c) / material.E
+    eps = a * scale * rng.standard_normal((6, n))
+    if material.model == "DP":
+        eps[:3] += scale * rng.uniform(-1, 4, n)
+    ep = 0.3 * scale * rng.standard_normal((6, n))
+    if material.model == "VM":
+        ep[:3] -= ep[:3].mean(axis=0)
+    kappa = scale * rng.uniform(0, 1, n)
+    return eps, ep, kappa
+
+
+@pytest.mark.parametrize("model", ["vm", "dph"])
+def test_datagen_parity(model):
+    mat = W.VM_MATERIAL if model == "vm" else W.dp_material_3d_hardening()
+    n_pool, n = 5000, 3001
+    eps, ep, kappa = _pool(mat, n_pool, 1, a=0.5)
+    rng = np.random.default_rng(2)
+    idx = rng.integers(0, n_pool, n)
+    idx[[5, 100, 3000]] = [-1, n_pool, 10 ** 9]
+    scale = (mat.Y if mat.model == "VM" else mat.c) / mat.E
+    deps = 0.25 * scale * rng.standard_normal((6, n))
+    beta = M.back_stress(mat, ep.T).T if model == "vm" else None
+    Xo, To = M.datagen(mat, idx, eps, ep, beta, kappa if model == "dph" else None, deps)
+    X = torch.empty((n, M.XS), dtype=torch.float32, device="cuda")
+    T = torch.empty((n, M.YS), dtype=torch.float32, device="cuda")
+    _ep.ep_mlp_datagen(mat, n, _dev(idx, torch.int64), n_pool, _dev(eps, torch.float64),
+                       _dev(ep, torch.float64),
+                       _dev(beta, torch.float64) if beta is not None else None,
+                       _dev(kappa, torch.float64) if model == "dph" else None,
+                       _dev(deps, torch.float64), X, T)
+    X, T = _np(X), _np(T)
+    assert np.array_equal(X, Xo)                      # same FP64 values, one rounding
+    assert np.array_equal(T[:, 6:], To[:, 6:])        # plastic flags bit for bit
+    assert 0.1 < To[:, 6].mean() < 0.9
+    # targets sigma - sigma_tr: one rounding of FP64 values that agree to
+    # ~1e-15 of the trial stress
+    ok = (idx >= 0) & (idx < n_pool)
+    e = eps[:, np.where(ok, idx, 0)] + deps - ep[:, np.where(ok, idx, 0)]
+    G, K = mat.shear, mat.bulk
+    tr_scale = (2 * G + 3 * K) * np.abs(e).max(axis=0)[:, None] / (1.0 / M.scales(mat)[1])
+    row = np.abs(To[:, :6]).max(axis=1, keepdims=True)
+    assert (np.abs(T[:, :6] - To[:, :6]) <= 2.0 ** -23 * row + 1e-13 * tr_scale).all()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n", [5, 1000])
+def test_forward_parity(prec, n):
+    p = _params(3)
+    X, _ = _batch(4, n)
+    mlp = _ep.Mlp(PREC[prec], 64)
+    try:
+        mlp.set_params(p)
+        Y = _np(mlp.forward(_dev(X)))
+        Yo, _ = M.forward(p.astype(np.float64), X)
+        assert not Y[:, 7].any()
+        err = np.linalg.norm(Y[:, :7] - Yo) / np.linalg.norm(Yo)
+        assert err <= (1e-6 if prec == "fp32" else 2e-2), err
+    finally:
+        mlp.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n", [1000, 8192])
+def test_loss_gradient_parity(prec, n):
+    p = _params(5)
+    X, T = _batch(6, n)
+    mlp = _ep.Mlp(PREC[prec], 8192)
+    try:
+        mlp.set_params(p)
+        g, loss = mlp.loss_grad(_dev(X), _dev(T))
+        g, loss = _np(g).astype(np.float64), float(_np(loss)[0])
+        Lo, go = M.loss_grad(p.astype(np.float64), X, T)
+        assert abs(loss - Lo) <= GTOL[prec] * Lo
+        err = np.linalg.norm(g - go) / np.linalg.norm(go)
+        assert err <= GTOL[prec], err
+        # every block of the parameter vector, not only the large ones
+        k = 0
+        for name, shape in M.SIZES:
+            sz = int(np.prod(shape))
+            e = np.linalg.norm(g[k:k + sz] - go[k:k + sz]) / np.linalg.norm(go[k:k + sz])
+            assert e <= 3 * GTOL[prec], (name, e)
+            k += sz
+        g2, _ = mlp.loss_grad(_dev(X), _dev(T))
+        assert np.array_equal(_np(g2), g.astype(np.float32))  # deterministic
+    finally:
+        mlp.close()
+
+
+def test_adam_step_parity():
+    p = _params(7)
+    X, T = _batch(8, 4096)
+    lr = 1e-3
+    mlp = _ep.Mlp(_ep.EP_FP32, 4096)
+    try:
+        mlp.set_params(p)
+        mlp.adam_step(_dev(X), _dev(T), lr)
+        dp = _np(mlp.params()).astype(np.float64) - p
+        _, go = M.loss_grad(p.astype(np.float64), X, T)
+        po, _, _ = M.adam_step(p.astype(np.float64), 0.0, 0.0, go, lr, 1)
+        dpo = po - p
+        # first step: lr g / (|g| + eps); where |g| is not tiny both sides move
+        # by lr sign(g)
+        big = np.abs(go) > 1e-4 * np.abs(go).max()
+        assert big.mean() > 0.5
+        assert np.abs(dp[big] - dpo[big]).max() <= 1e-3 * lr + 2e-7 * np.abs(p[big]).max()
+        assert np.abs(dp).max() <= 1.001 * lr
+    finally:
+        mlp.close()
+
+
+def test_training_reduces_loss():
+    """A few hundred Adam steps on exact return-map samples: the loss drops
+    and held-out plastic flags are mostly right."""
+    mat = W.VM_MATERIAL
+    eps, ep, _ = _pool(mat, 20000, 9)
+    pool = learned.Pool()
+    pool.parts.append(tuple(_dev(a, torch.float64) for a in
+                            (eps, ep, M.back_stress(mat, ep.T).T, np.zeros(20000))))
+    ds = (0.01 * mat.Y / mat.E, 2.0 * mat.Y / mat.E)
+    X, T = learned.make_samples(mat, pool, 200000, seed=10, deps_std=ds)
+    Xh, Th = learned.make_samples(mat, pool, 20000, seed=11, deps_std=ds)
+    mlp = _ep.Mlp(_ep.EP_FP32, 4096)
+    try:
+        mlp.set_params(M.he_uniform(12).astype(np.float32))
+        g, l0 = mlp.loss_grad(Xh[:4096], Th[:4096])
+        _, hist = learned.train(mlp, X, T, epochs=4, batch=4096, lr_max=2e-3, lr_min=1e-4,
+                                log_every=50)
+        _, l1 = mlp.loss_grad(Xh[:4096], Th[:4096])
+        l0, l1 = float(l0.item()), float(l1.item())
+        assert l1 < 0.2 * l0, (l0, l1, hist)
+        ev = learned.evaluate(mlp, Xh, Th)
+        assert ev["accuracy"] > 0.9, ev
+    finally:
+        mlp.close()
+
+
+@pytest.mark.parametrize("case", ["q1_3d_vm", "q2_2d_dp", "p2_3d_dph"])
+def test_features_parity(case):
+    mesh, free, mat, u, (ep, beta, kappa) = make_case(case)
+    ctx = _ep.Context(mesh, free, mat)
+    try:
+        ctx.set_state(ep, beta if mat.model == "VM" else None,
+                      kappa if mat.model == "DP" else None)
+        X = _np(ctx.mlp_features(ctx.tensor(u)))
+        kap = kappa if mat.model == "DP" else np.zeros(mesh.n_int)
+        Xo = M.features(mesh, mat, u, O.state_to_ip6(ep, mesh.dim), kap)
+        row = np.abs(Xo).max(axis=1, keepdims=True)
+        # FP64 strains agree to ~1e-15 relative before the FP32 rounding
+        assert (np.abs(X - Xo) <= 1.2e-7 * row).all()
+        assert not X[:, 13:].any()
+    finally:
+        ctx.close()
+
+
+def test_warm_start_parity():
+    """ep_warm_start (tight PCG) against the oracle's warm start with the
+    same FP32 network evaluated in FP64: predicted plastic set, residuals,
+    acceptance; the candidate's exact residual to the network's precision."""
+    wl = W.workload_q1_cube(4)
+    mesh, mat = wl.mesh, wl.material
+    ep, beta, kappa, _ = W.seeded_state(wl, 0.5, seed=4)
+    ep6, beta6 = O.state_to_ip6(ep, 3), O.state_to_ip6(beta, 3)
+    kap = np.zeros(mesh.n_int)
+    u4, *_ = O.newton_solve(mesh, mat, wl.free, wl.f(4), np.zeros(mesh.n_dof), ep6, beta6, kap,
+                            tol=1e-12)
+    u5, *_ = O.newton_solve(mesh, mat, wl.free, wl.f(5), u4, ep6, beta6, kap, tol=1e-12)
+    f = wl.f(6)
+    extrap = 1.0
+    # a network whose logits stay clear of 0 at every point (so that the
+    # FP32 and FP64 evaluations take the same decisions)
+    p = _params(21)
+    P = M.unpack(p.astype(np.float64))
+    P["b3"][6] += 3.0 * np.sign(P["b3"][6] + 1e-9)
+    p = M.pack(P).astype(np.float32)
+
+    def net(X):
+        return M.forward(p.astype(np.float64), X)[0]
+
+    u_o, info_o = M.warm_start(mesh, mat, wl.free, f, u5, u4, extrap, ep6, beta6, kap, net)
+    Xo = M.features(mesh, mat, u5 + extrap * (u5 - u4) * wl.free, ep6, kap)
+    logit = net(Xo)[:, 6]
+    assert np.abs(logit).min() > 1e-3
+    ctx = _ep.Context(mesh, wl.free, mat, options={"pcg_max_it": 20000})
+    mlp = _ep.Mlp(_ep.EP_FP32, 64)
+    try:
+        ctx.set_state(ep, beta, None)
+        mlp.set_params(p)
+        uo = ctx.tensor(u5)
+        st, info = ctx.warm_start(mlp, ctx.tensor(f), uo, ctx.tensor(u4), extrap, 1e-13, uo)
+        assert st == _ep.EP_OK
+        assert info["n_plastic_pred"] == info_o["n_plastic_pred"]
+        assert 0 < info["n_plastic_pred"] < mesh.n_int
+        assert abs(info["res_rel_start"] - info_o["res_rel_start"]) <= 1e-9 * info_o["res_rel_start"]
+        assert abs(info["res_rel_pred"] - info_o["res_rel_pred"]) <= 1e-5 * info_o["res_rel_pred"]
+        assert abs(info["res_rel_warm"] - info_o["res_rel_warm"]) <= 1e-4 * info_o["res_rel_warm"]
+        assert info["accepted"] == info_o["accepted"]
+        assert np.abs(_np(uo) - u_o).max() <= 1e-4 * np.abs(u_o).max()
+    finally:
+        mlp.close()
+        ctx.close()
+
+
+def _cube_cyclic(n, steps):
+    return W.workload_q1_cube_cyclic(n, steps)
+
+
+def test_trained_warm_start_gain():
+    """What the trained network gains: on the cyclic cube path (50% seeded
+    plastic), Newton iterations with the trained network's warm start
+    (counting its solve as an iteration) against no warm start and against
+    the same warm start with the untrained network; the converged
+    displacements agree.  The secant predictor alone is reported beside."""
+    n, steps = 8, 30
+    wl = _cube_cyclic(n, steps)
+    mesh, mat = wl.mesh, wl.material
+    opts = {"newton_rtol": 1e-10}
+    # training run (seed 1) -> pool -> samples -> training
+    ep1, beta1, _, _ = W.seeded_state(wl, 0.5, seed=1)
+    ctx = _ep.Context(mesh, wl.free, mat, options=opts)
+    pool = learned.Pool()
+    u = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
+    ctx.set_state(ep1, beta1, None)
+    learned.training_path(ctx, wl, u, pool)
+    ctx.close()
+    sy = 450.0 / mat.E
+    X, T = learned.make_samples(mat, pool, 8_000_000, seed=2, deps_std=(0.01 * sy, 2 * sy))
+    trained = _ep.Mlp(_ep.EP_FP32, 8192)
+    untrained = _ep.Mlp(_ep.EP_FP32, 8192)
+    init = M.he_uniform(3).astype(np.float32)
+    trained.set_params(init)
+    untrained.set_params(init)
+    learned.train(trained, X, T, epochs=3, batch=8192, lr_max=1e-3, lr_min=1e-5)
+    del X, T
+    # measured run (seed 0)
+    ep0, beta0, _, _ = W.seeded_state(wl, 0.5, seed=0)
+    res = {}
+    for name, mlp, ex in (("plain", None, False), ("predictor", None, True),
+                          ("untrained", untrained, True), ("trained", trained, True)):
+        c = _ep.Context(mesh, wl.free, mat, options=opts)
+        c.set_state(ep0, beta0, None)
+        uu = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
+        recs = learned.solve_path_warm(c, wl, uu, mlp, extrapolate=ex)
+        res[name] = (sum(r["newton_its"] for r in recs), _np(uu), recs)
+        c.close()
+    trained.close()
+    untrained.close()
+    its = {k: v[0] for k, v in res.items()}
+    ref = res["plain"][1]
+    for k in ("predictor", "untrained", "trained"):
+        assert np.abs(res[k][1] - ref).max() <= 1e-7 * np.abs(ref).max(), k
+    acc = sum(r["warm"]["accepted"] for r in res["trained"][2])
+    print("newton iterations", its, "trained warm starts accepted", acc, "of", steps)
+    assert its["trained"] < its["plain"], its
+    assert its["trained"] < its["untrained"], its
