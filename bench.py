@@ -13,6 +13,17 @@ quadrilaterals (131072 elements, 1179648 integration points), Drucker-Prager
 perfect plasticity (c0 = 450, phi = 20 deg, E = 20000, nu = 0.49), half of the
 elements seeded plastic.
 
+Also measured (unless --no-newton), as extra objects of the same line:
+  newton: time to |Q(f - F)| <= 1e-10 |Q f| summed over a load path, for the
+    plain FP64 solver and its variants: FP32 tangent values; the secant
+    predictor; the learned warm start (network trained on the GPU by the
+    library's kernels from a separate training path, FP32 and BF16 products)
+    on the 64^3 Q1 cube under the cyclic traction history; and matrix-core
+    local products (FP32, BF16) on the Q2 / P2 blocks' 20-step paths;
+  local_precision: incremental tangent error of the FP32 / BF16 local
+    products against the FP64 path, and the assembly kernel's matrix-core
+    rate, on the Q2 / P2 blocks with half of the elements seeded plastic.
+
 Prints one JSON line (rank 0, one GPU).
 """
 from __future__ import annotations
@@ -20,6 +31,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -28,6 +40,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
+# useful flops of the element-local product per plastic point, exploiting the
+# three nonzeros per column of B: 2 (3 (d n_p)^2 + 54 n_p)
+LOCAL_FLOPS_PER_IP = {"Q2_3D": 2 * (3 * 81 ** 2 + 54 * 27), "P2_3D": 2 * (3 * 30 ** 2 + 54 * 10)}
 KERNEL_SRC = os.path.join(ROOT, "paper_1805_04155_amd", "csrc", "ep_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_q2_slope.json")
 
@@ -99,6 +115,205 @@ def cpu_baseline(wl, ep, beta, kappa, u):
                       "and sparsity pattern precomputed"}
 
 
+def log(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _state_args(mat, ep, beta, kappa):
+    return (ep, beta if mat.model == "VM" else None, kappa if mat.model == "DP" else None)
+
+
+def run_path(wl, state, options, mlp=None, extrapolate=False, keep_u=False, steps=None):
+    """One load path solved to |Q(f - F)| <= 1e-10 |Q f| per step; wall time
+    from the first Newton evaluation to the last commit (setup excluded)."""
+    import torch
+    from paper_1805_04155_amd import _ep, learned
+    opts = {"newton_rtol": 1e-10}
+    opts.update(options)
+    ctx = _ep.Context(wl.mesh, wl.free, wl.material, options=opts)
+    ctx.set_state(*state)
+    u = torch.zeros(wl.mesh.n_dof, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = learned.solve_path_warm(ctx, wl, u, mlp, steps=steps, extrapolate=extrapolate)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ctx.close()
+    out = {"seconds": round(t, 3), "newton_its": sum(r["newton_its"] for r in recs),
+           "pcg_its": sum(r["pcg_its"] for r in recs),
+           "max_final_res_rel": max(r["res_rel"] for r in recs),
+           "final_plastic_points": recs[-1]["n_plastic_ip"]}
+    if mlp is not None:
+        out["warm_starts_accepted"] = sum(r["warm"]["accepted"] for r in recs)
+    return out, (u if keep_u else None)
+
+
+def _du(u, ref):
+    return float(((u - ref).abs().max() / ref.abs().max()).item())
+
+
+def newton_report(cube_n, n_samples, block):
+    """Metric 2: time-to-1e-10 summed over load paths, plain FP64 against
+    the mixed-precision and learned variants."""
+    import numpy as np
+    import torch
+    from paper_1805_04155_amd import _ep, learned
+    from paper_1805_04155_amd import workloads as W
+    rep = {}
+    # warm-up of every kernel on a small path (not reported)
+    small = W.workload_q1_cube_cyclic(6, 30)
+    st = _state_args(small.material, *W.seeded_state(small, 0.5, seed=0)[:3])
+    run_path(small, st, {}, steps=range(3))
+    # learned warm start on the cyclic cube
+    wl = W.workload_q1_cube_cyclic(cube_n, 30)
+    mat = wl.material
+    sy = math.sqrt(1.5) * mat.Y
+    t0 = time.perf_counter()
+    ctx = _ep.Context(wl.mesh, wl.free, mat, options={"newton_rtol": 1e-10})
+    ctx.set_state(*_state_args(mat, *W.seeded_state(wl, 0.5, seed=1)[:3]))
+    pool = learned.Pool()
+    u = torch.zeros(wl.mesh.n_dof, dtype=torch.float64, device="cuda")
+    learned.training_path(ctx, wl, u, pool)
+    ctx.close()
+    del u
+    t_path = time.perf_counter() - t0
+    log(f"training path {t_path:.1f} s")
+    t0 = time.perf_counter()
+    ds = (0.01 * sy / mat.E, 2.0 * sy / mat.E)
+    X, T = learned.make_samples(mat, pool, n_samples, seed=2, deps_std=ds)
+    Xh, Th = learned.make_samples(mat, pool, 1_000_000, seed=4, deps_std=ds)
+    t_gen = time.perf_counter() - t0
+    del pool
+    nets, training = {}, {"training_path_s": round(t_path, 3), "samples": n_samples,
+                          "datagen_s": round(t_gen, 3), "epochs": 3, "batch": 8192,
+                          "sample_increments": "N(0, s^2), s log-uniform in "
+                                               "[0.01, 2] sigma_y/E per sample"}
+    init = W.mlp_he_uniform(3).astype(np.float32)
+    for prec in ("fp32", "bf16"):
+        m = _ep.Mlp(_ep.EP_FP32 if prec == "fp32" else _ep.EP_BF16, 8192)
+        m.set_params(init)
+        sec, hist = learned.train(m, X, T, epochs=3, batch=8192, lr_max=1e-3, lr_min=1e-5,
+                                  log_every=2000)
+        ev = learned.evaluate(m, Xh, Th)
+        training[prec] = {"train_s": round(sec, 3), "final_loss": hist[-1][1] if hist else None,
+                          "held_out": {k: round(v, 5) for k, v in ev.items()}}
+        log(f"trained {prec}: {training[prec]}")
+        nets[prec] = m
+    untrained = _ep.Mlp(_ep.EP_FP32, 8192)
+    untrained.set_params(init)
+    del X, T, Xh, Th
+    torch.cuda.empty_cache()
+    st0 = _state_args(mat, *W.seeded_state(wl, 0.5, seed=0)[:3])
+    variants = {}
+    variants["plain_fp64"], u_ref = run_path(wl, st0, {}, keep_u=True)
+    log(f"cube plain_fp64: {variants['plain_fp64']}")
+    runs = [("fp32_tangent", {"tangent_prec": _ep.EP_FP32}, None, False),
+            ("secant_predictor", {}, None, True),
+            ("learned_fp32", {}, nets["fp32"], True),
+            ("learned_bf16", {}, nets["bf16"], True),
+            ("learned_untrained", {}, untrained, True)]
+    for name, opts, m, ex in runs:
+        r, uu = run_path(wl, st0, opts, mlp=m, extrapolate=ex, keep_u=True)
+        r["du_rel_vs_plain"] = _du(uu, u_ref)
+        variants[name] = r
+        log(f"cube {name}: {r}")
+        del uu
+    for m in list(nets.values()) + [untrained]:
+        m.close()
+    base = variants["plain_fp64"]["seconds"]
+    for v in variants.values():
+        v["speedup_vs_plain"] = round(base / v["seconds"], 3)
+    rep["q1_cube_cyclic"] = {
+        "workload": f"unit cube, {cube_n}^3 Q1 hexahedra ({wl.mesh.n_int} points), von Mises "
+                    "kinematic, half of the elements seeded plastic (seed 0; training path "
+                    "seed 1), 30 steps of the cyclic traction history x 540",
+        "variants": variants, "training": training}
+    # matrix-core local products on the blocks
+    for name, fn in (("q2_block", W.workload_q2_block), ("p2_block", W.workload_p2_block)):
+        wl = fn(*block)
+        st0 = _state_args(wl.material, *W.seeded_state(wl, 0.0, seed=0)[:3])
+        variants = {}
+        variants["plain_fp64"], u_ref = run_path(wl, st0, {}, keep_u=True)
+        log(f"{name} plain_fp64: {variants['plain_fp64']}")
+        for lp in ("fp32", "bf16"):
+            r, uu = run_path(wl, st0, {"local_prec": _ep.EP_FP32 if lp == "fp32" else _ep.EP_BF16},
+                             keep_u=True)
+            r["du_rel_vs_plain"] = _du(uu, u_ref)
+            variants[f"local_{lp}"] = r
+            log(f"{name} local_{lp}: {r}")
+        base = variants["plain_fp64"]["seconds"]
+        for v in variants.values():
+            v["speedup_vs_plain"] = round(base / v["seconds"], 3)
+        rep[name] = {"workload": f"2x1x1 block, {block[0]}x{block[1]}x{block[2]} "
+                                 f"{'27-node hexahedra' if name == 'q2_block' else 'P2 tetrahedra'} "
+                                 f"({wl.mesh.n_int} points), Drucker-Prager with linear "
+                                 "hardening, strip pressure ramped to 4000 in 20 steps",
+                     "variants": variants}
+    return rep
+
+
+def local_precision_report(block):
+    """Matrix-core local products on the blocks at a seeded state: tangent
+    error against the FP64 path (relative Frobenius norm, and the largest
+    entry error relative to its row scale) and the assembly kernel's rate."""
+    import numpy as np
+    import torch
+    from paper_1805_04155_amd import _ep
+    from paper_1805_04155_amd import workloads as W
+    out = {}
+    for name, fn, et in (("q2_block", W.workload_q2_block, "Q2_3D"),
+                         ("p2_block", W.workload_p2_block, "P2_3D")):
+        wl = fn(*block)
+        mesh, mat = wl.mesh, wl.material
+        ep, beta, kappa, _ = W.seeded_state(wl, 0.5, seed=0)
+        rec = {}
+        K64 = None
+        for lp in ("fp64", "fp32", "bf16"):
+            ctx = _ep.Context(mesh, wl.free, mat, options={
+                "local_prec": {"fp64": _ep.EP_FP64, "fp32": _ep.EP_FP32, "bf16": _ep.EP_BF16}[lp]})
+            ctx.set_state(*_state_args(mat, ep, beta, kappa))
+            u = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
+            for _ in range(3):
+                _ep.ep_constitutive(ctx.h, u)
+                _ep.ep_assemble_tangent(ctx.h)
+            torch.cuda.synchronize()
+            n_ip, n_el = _ep.ep_get_plastic(ctx.h)
+            _ep.ep_profile(ctx.h, 1)
+            reps = 10
+            for _ in range(reps):
+                _ep.ep_constitutive(ctx.h, u)
+                _ep.ep_assemble_tangent(ctx.h)
+            torch.cuda.synchronize()
+            ms, cnt = _ep.ep_profile_read(ctx.h, "assembly")
+            _ep.ep_profile(ctx.h, 0)
+            _, _, val = ctx.csr(1)
+            r = {"assembly_ms": round(ms / reps, 4), "plastic_points": n_ip}
+            flops = LOCAL_FLOPS_PER_IP[et] * n_ip
+            r["local_product_TFLOP_s"] = round(flops / (ms / reps / 1e3) / 1e12, 2)
+            if lp == "fp64":
+                K64 = val.clone()
+            else:
+                r["mfma_utilization_lower_bound"] = round(
+                    r["local_product_TFLOP_s"] / MFMA_PEAK_TFLOPS[lp], 5)
+                r["K_rel_frobenius_error_vs_fp64"] = float(
+                    (torch.linalg.norm(val - K64) / torch.linalg.norm(K64)).item())
+            rec[lp] = r
+            log(f"local precision {name} {lp}: {r}")
+            ctx.close()
+            del val, u
+        del K64
+        torch.cuda.empty_cache()
+        out[name] = {"workload": f"{block[0]}x{block[1]}x{block[2]} block, "
+                                 f"{mesh.n_int} points, half of the elements seeded plastic",
+                     "local_flops_per_plastic_point": LOCAL_FLOPS_PER_IP[et],
+                     "note": "matrix-core rate = useful local-product flops / whole assembly "
+                             "kernel time (scatter included): a lower bound on the matrix "
+                             "cores' utilisation",
+                     "precisions": rec}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +324,13 @@ def main():
     ap.add_argument("--tangent", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-calibration-copy", action="store_true")
+    ap.add_argument("--local-prec", choices=["fp64", "fp32", "bf16"], default="fp64",
+                    help="element-local products (27-node hexahedra, P2 tetrahedra only)")
+    ap.add_argument("--no-newton", action="store_true",
+                    help="skip the time-to-1e-10 load paths and the local-precision report")
+    ap.add_argument("--newton-cube-n", type=int, default=64)
+    ap.add_argument("--newton-samples", type=float, default=20e6)
+    ap.add_argument("--newton-block", default="32,16,16")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hot path is built and timed on a single "
@@ -129,8 +351,10 @@ def main():
     u_np = W.random_displacement(mesh, 1, 1e-6 * h, wl.free)
 
     tb = 8 if args.tangent == "fp64" else 4
+    lp = {"fp64": _ep.EP_FP64, "fp32": _ep.EP_FP32, "bf16": _ep.EP_BF16}[args.local_prec]
     ctx = _ep.Context(mesh, wl.free, mat,
-                      options={"tangent_prec": _ep.EP_FP64 if tb == 8 else _ep.EP_FP32})
+                      options={"tangent_prec": _ep.EP_FP64 if tb == 8 else _ep.EP_FP32,
+                               "local_prec": lp})
     ctx.set_state(ep, beta if mat.model == "VM" else None, kappa if mat.model == "DP" else None)
     u = ctx.tensor(u_np)
     F = torch.empty(mesh.n_dof, dtype=torch.float64, device="cuda")
@@ -194,9 +418,17 @@ def main():
                 "avg_launch_ms": round(d["ms_per_step"] / n_launch, 5),
                 "traffic": traffic}
 
+    ctx.close()
+    del ctx, F, u
+    torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, ep, beta, kappa, u_np)
+    newton = local = None
+    if not args.no_newton:
+        block = tuple(int(x) for x in args.newton_block.split(","))
+        local = local_precision_report(block)
+        newton = newton_report(args.newton_cube_n, int(args.newton_samples), block)
 
     mdesc = {"q2_slope": "plane strain 40x20 rectangle, 512x256 9-node Q2 quads (131072 elements, "
                          "1179648 points), Drucker-Prager perfect c0=450 phi=20deg E=20000 nu=0.49",
@@ -211,12 +443,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {mdesc}", "plastic_fraction_seeded": args.plastic_fraction,
                    "plastic_elements": n_el, "plastic_points": n_ip, "tangent": args.tangent,
+                   "local_products": args.local_prec,
                    "step": "constitutive + compaction + incremental K assembly + internal force"},
         "roofline": roofline,
         "kernels": per_kernel,
         "cpu_baseline": cpu,
+        "newton": newton,
+        "local_precision": local,
     }
-    ctx.close()
     print(json.dumps(line), flush=True)
 
 

@@ -113,18 +113,6 @@ def adam_step(params, m, v, grad, lr, t, b1=0.9, b2=0.999, eps=1e-8):
     return params - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def he_uniform(seed):
-    """He-uniform initial weights (bound sqrt(6 / fan_in)), zero biases."""
-    rng = np.random.default_rng(seed)
-    d = {}
-    for name, shape in SIZES:
-        if name.startswith("W"):
-            d[name] = rng.uniform(-1.0, 1.0, shape) * math.sqrt(6.0 / shape[1])
-        else:
-            d[name] = np.zeros(shape)
-    return pack(d)
-
-
 # ---------------------------------------------------------------------------
 # Encoding and sample generation
 # ---------------------------------------------------------------------------

@@ -571,3 +571,25 @@ def random_displacement(mesh: Mesh, seed: int, scale: float, free=None):
     if free is not None:
         u = u * free
     return u
+
+
+# --------------------------------------------------------------------------
+# Seeded initial weights of the warm-start network
+# --------------------------------------------------------------------------
+
+MLP_SIZES = [("W1", (128, 13)), ("b1", (128,)), ("W2", (128, 128)), ("b2", (128,)),
+             ("W3", (7, 128)), ("b3", (7,))]
+
+
+def mlp_he_uniform(seed):
+    """He-uniform initial parameters of the 13-128-128-7 network in the
+    library's layout (W[out][in], then bias, per layer): weights uniform in
+    +-sqrt(6 / fan_in), biases zero.  float64 vector of 19207 values."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape in MLP_SIZES:
+        if name.startswith("W"):
+            parts.append((rng.uniform(-1.0, 1.0, shape) * math.sqrt(6.0 / shape[1])).ravel())
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate(parts)

@@ -31,7 +31,7 @@ def _dev(a, dtype=torch.float32):
 
 
 def _params(seed):
-    p = M.he_uniform(seed)
+    p = W.mlp_he_uniform(seed)
     p += 0.05 * np.random.default_rng(seed + 1).standard_normal(p.shape)
     return p.astype(np.float32)
 
@@ -171,7 +171,7 @@ def test_training_reduces_loss():
     Xh, Th = learned.make_samples(mat, pool, 20000, seed=11, deps_std=ds)
     mlp = _ep.Mlp(_ep.EP_FP32, 4096)
     try:
-        mlp.set_params(M.he_uniform(12).astype(np.float32))
+        mlp.set_params(W.mlp_he_uniform(12).astype(np.float32))
         g, l0 = mlp.loss_grad(Xh[:4096], Th[:4096])
         _, hist = learned.train(mlp, X, T, epochs=4, batch=4096, lr_max=2e-3, lr_min=1e-4,
                                 log_every=50)
@@ -276,7 +276,7 @@ def test_trained_warm_start_gain():
     X, T = learned.make_samples(mat, pool, 8_000_000, seed=2, deps_std=(0.01 * sy, 2 * sy))
     trained = _ep.Mlp(_ep.EP_FP32, 8192)
     untrained = _ep.Mlp(_ep.EP_FP32, 8192)
-    init = M.he_uniform(3).astype(np.float32)
+    init = W.mlp_he_uniform(3).astype(np.float32)
     trained.set_params(init)
     untrained.set_params(init)
     learned.train(trained, X, T, epochs=3, batch=8192, lr_max=1e-3, lr_min=1e-5)

@@ -42,7 +42,7 @@ def test_gradient_matches_central_differences():
     """Backpropagation against central differences of the loss in FP64 at
     every bias of the output layer and a random sample of all parameters."""
     X, T = _batch(0)
-    p = M.he_uniform(1)
+    p = W.mlp_he_uniform(1)
     p += 0.05 * np.random.default_rng(2).standard_normal(p.shape)  # nonzero biases
     L, g = M.loss_grad(p, X, T)
     assert abs(L - M.loss(p, X, T)) <= 1e-15 * abs(L)
@@ -106,7 +106,7 @@ def test_adam_under_constant_gradient():
 
 
 def test_he_uniform_bounds_and_variance():
-    P = M.unpack(M.he_uniform(7))
+    P = M.unpack(W.mlp_he_uniform(7))
     for name, fan in (("W1", 13), ("W2", 128), ("W3", 128)):
         w = P[name]
         assert np.abs(w).max() <= math.sqrt(6.0 / fan)
