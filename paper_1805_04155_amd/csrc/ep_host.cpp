@@ -427,6 +427,13 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   for (int64_t i = 0; i < n_e * n_p; ++i)
     if (mesh->elem[i] < 0 || mesh->elem[i] >= n_n)
       return fail("ep_setup: node id out of range in elem", EP_EINVAL);
+  // the nodes of an element are distinct (the assembly ranks them)
+  for (int64_t e = 0; e < n_e; ++e) {
+    const int32_t *en = mesh->elem + e * n_p;
+    for (int i = 0; i < n_p; ++i)
+      for (int j = i + 1; j < n_p; ++j)
+        if (en[i] == en[j]) return fail("ep_setup: repeated node in an element", EP_EINVAL);
+  }
 
   ep_options opt{EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2};
   if (opt_in) opt = *opt_in;

@@ -403,9 +403,44 @@ struct AsmCfg {
   static constexpr int NPAIR = T::NP * (T::NP + 1) / 2;
   static constexpr int BS = NPAIR <= 64 ? 64 : (NPAIR <= 128 ? 128 : 256);
   static constexpr int NBT = (NPAIR + BS - 1) / BS;
-  static constexpr int QC = T::NQ <= 11 ? T::NQ : 9;  // points per LDS chunk
+  // points per LDS chunk (4 for the 8-node hexahedron: LDS bounds its
+  // occupancy)
+  static constexpr int QC = ETID == ET_Q1_3D ? 4 : (T::NQ <= 11 ? T::NQ : 9);
   static constexpr int WPE = T::D == 2 ? 6 : 4;       // occupancy target (waves/SIMD)
+  // quadrilaterals and 8-node hexahedra stage the element matrix in LDS and
+  // scatter it row by row in column order: on structured meshes an element's
+  // blocks in a row form runs of consecutive nodes, so consecutive lanes write
+  // consecutive blocks (simplices have no such runs)
+  static constexpr bool SORTED = ETID == ET_Q1_2D || ETID == ET_Q2_2D || ETID == ET_Q1_3D;
+  static constexpr int NSLOT = SORTED ? (T::NP * T::NP + BS - 1) / BS : 1;
 };
+
+// dim x dim block loads / stores, 16-byte vectors where the block size allows
+template <int D, typename VT>
+__device__ inline void block_load(const VT *p, double *v) {
+  if constexpr (D == 2 && sizeof(VT) == 8) {
+    const double2 a = ((const double2 *)p)[0], b = ((const double2 *)p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  } else if constexpr (D == 2) {
+    const float4 a = *(const float4 *)p;
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) v[i] = (double)p[i];
+  }
+}
+template <int D, typename VT>
+__device__ inline void block_store(VT *p, const double *v) {
+  if constexpr (D == 2 && sizeof(VT) == 8) {
+    ((double2 *)p)[0] = double2{v[0], v[1]};
+    ((double2 *)p)[1] = double2{v[2], v[3]};
+  } else if constexpr (D == 2) {
+    *(float4 *)p = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+  } else {
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) p[i] = (VT)v[i];
+  }
+}
 
 // Voigt M = C + (alpha DEV + b n n^T + g (n 1^T + 1 n^T) + d 1 1^T) scaled by
 // w, in the stored components (3D: 6, plane strain: 11, 22, 12).
@@ -450,12 +485,21 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
   constexpr int NPAIR = Cfg::NPAIR, QC = Cfg::QC, NB2 = NP * NP;
   constexpr int NS = D == 3 ? 6 : 3;
   constexpr int NDESC = D == 3 ? 10 : 7;
+  constexpr bool SORTED = Cfg::SORTED;
+  constexpr int NSLOT = Cfg::NSLOT;
   static_assert(NP * D <= BS && NQ <= BS, "one thread per coordinate and per point");
   __shared__ double s_x[NP * D];
   __shared__ double s_M[NQ * NS * NS];     // w (D_q - C), all points of the element
   __shared__ double s_Ji[NQ * D * D];
   __shared__ double s_g[QC * D * NP];      // [q][d][p]
-  __shared__ double s_H[QC * D * NS * NP]; // [q][j][k][p]
+  // H = M B per (point, node) [q][j][k][p]; after the local product the same
+  // LDS holds the element matrix [p][p'][r][c] (sorted scatter)
+  constexpr int NH_ = QC * D * NS * NP, NK_ = SORTED ? NB2 * D * D : 0;
+  __shared__ double s_HK[NH_ > NK_ ? NH_ : NK_];
+  double *const s_H = s_HK;
+  double *const s_K = s_HK;
+  __shared__ int s_node[NP];
+  __shared__ int s_ord[NP];                // local nodes by ascending global id
   __shared__ int s_q[NQ];                  // plastic points in order
   const int tid = threadIdx.x;
   int64_t k0 = a.k0, k1 = a.k1;
@@ -465,12 +509,14 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
   }
   VT *Kt = (VT *)a.Kt;
   const uint32_t qmask = NQ == 32 ? 0xffffffffu : ((1u << NQ) - 1u);
-  // node pairs of this thread
+  // node pairs p <= p' of this thread (element-local product)
   int pp_[NBT], pq_[NBT];
+  bool pon[NBT];
 #pragma unroll
   for (int j = 0; j < NBT; ++j) {
     int t = tid + j * BS, p = 0;
-    if (t >= NPAIR) t = 0;
+    pon[j] = t < NPAIR;
+    if (!pon[j]) t = 0;
     while (t >= NP - p) {
       t -= NP - p;
       ++p;
@@ -483,20 +529,47 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
     if (e < 0) continue;  // padding of the colour-major order (uniform)
     const uint32_t mask = (a.elastic ? 0xffffffffu : a.emask[e]) & qmask;
     const int nq = __popc(mask);
-    // block indices (p,p') and (p',p), freshness of this assembly
-    int64_t i1[NBT], i2[NBT];
-    bool f1[NBT], f2[NBT];
+    // scatter targets: sorted mode, slot t = p * NP + r is block (p, s_ord[r]);
+    // pair mode, the blocks (p, p') and (p', p) of this thread's pairs
+    int64_t i1[SORTED ? NSLOT : NBT], i2[SORTED ? 1 : NBT];
+    bool f1[SORTED ? NSLOT : NBT], f2[SORTED ? 1 : NBT];
+    if constexpr (SORTED) {
+      __syncthreads();  // LDS of the previous element is no longer read
+      if (tid < NP) s_node[tid] = a.elem[(int64_t)e * NP + tid];
+      __syncthreads();
+      if (tid < NP) {
+        int r = 0;
+        const int me = s_node[tid];
 #pragma unroll
-    for (int j = 0; j < NBT; ++j) {
-      const bool on = tid + j * BS < NPAIR;
-      i1[j] = on ? (int64_t)a.bpos[(int64_t)e * NB2 + pp_[j] * NP + pq_[j]] : 0;
-      i2[j] = on ? (int64_t)a.bpos[(int64_t)e * NB2 + pq_[j] * NP + pp_[j]] : 0;
-    }
+        for (int j = 0; j < NP; ++j) r += (s_node[j] < me) ? 1 : 0;
+        s_ord[r] = tid;
+      }
+      __syncthreads();
 #pragma unroll
-    for (int j = 0; j < NBT; ++j) {
-      const bool on = tid + j * BS < NPAIR;
-      f1[j] = (!a.elastic && on) ? (a.epoch[i1[j]] != a.cur) : false;
-      f2[j] = (!a.elastic && on) ? (a.epoch[i2[j]] != a.cur) : false;
+      for (int sl = 0; sl < NSLOT; ++sl) {
+        const int t = tid + sl * BS;
+        const bool on = t < NB2;
+        const int p = on ? t / NP : 0, pc = on ? s_ord[t - (t / NP) * NP] : 0;
+        i1[sl] = on ? (int64_t)a.bpos[(int64_t)e * NB2 + p * NP + pc] : 0;
+      }
+#pragma unroll
+      for (int sl = 0; sl < NSLOT; ++sl) {
+        const bool on = tid + sl * BS < NB2;
+        f1[sl] = (!a.elastic && on) ? (a.epoch[i1[sl]] != a.cur) : false;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NBT; ++j) {
+        const bool on = pon[j];
+        i1[j] = on ? (int64_t)a.bpos[(int64_t)e * NB2 + pp_[j] * NP + pq_[j]] : 0;
+        i2[j] = on ? (int64_t)a.bpos[(int64_t)e * NB2 + pq_[j] * NP + pp_[j]] : 0;
+      }
+#pragma unroll
+      for (int j = 0; j < NBT; ++j) {
+        const bool on = pon[j];
+        f1[j] = (!a.elastic && on) ? (a.epoch[i1[j]] != a.cur) : false;
+        f2[j] = (!a.elastic && on) ? (a.epoch[i2[j]] != a.cur) : false;
+      }
     }
     double acc[NBT][D * D];
 #pragma unroll
@@ -504,9 +577,9 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
 #pragma unroll
       for (int i = 0; i < D * D; ++i) acc[j][i] = 0.0;
     if (mask) {
-      __syncthreads();  // LDS of the previous element is no longer read
+      if constexpr (!SORTED) __syncthreads();  // LDS of the previous element is no longer read
       if (tid < NP * D) {
-        const int64_t node = a.elem[(int64_t)e * NP + tid / D];
+        const int64_t node = SORTED ? s_node[tid / D] : a.elem[(int64_t)e * NP + tid / D];
         s_x[tid] = a.coord[(tid % D) * a.n_n + node];
       }
       if (tid < NQ) {
@@ -570,7 +643,7 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
         // node blocks B_p^T H_p'
 #pragma unroll
         for (int j = 0; j < NBT; ++j) {
-          if (tid + j * BS >= NPAIR) continue;
+          if (!pon[j]) continue;
           const int p = pp_[j], pq = pq_[j];
           for (int ql = 0; ql < nc; ++ql) {
             const double *gq = s_g + ql * D * NP;
@@ -596,37 +669,77 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
           }
         }
       }
+      if constexpr (SORTED) {
+        __syncthreads();  // H is no longer read
+        // element matrix to LDS: block (p, p') and its transpose (p', p)
+#pragma unroll
+        for (int j = 0; j < NBT; ++j) {
+          if (!pon[j]) continue;
+          const int p = pp_[j], pq = pq_[j];
+#pragma unroll
+          for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+              s_K[(p * NP + pq) * D * D + r * D + c] = acc[j][r * D + c];
+              s_K[(pq * NP + p) * D * D + c * D + r] = acc[j][r * D + c];
+            }
+        }
+        __syncthreads();
+      }
     }
     // base values (K_elast for blocks not yet written in this assembly, else
-    // K_tangent) and the update of both blocks of each pair
+    // K_tangent) plus the element's contribution
+    if constexpr (SORTED) {
 #pragma unroll
-    for (int j = 0; j < NBT; ++j) {
-      if (tid + j * BS >= NPAIR) continue;
-      const bool diag = pp_[j] == pq_[j];
-#pragma unroll
-      for (int side = 0; side < 2; ++side) {
-        if (side == 1 && diag) continue;
-        const int64_t idx = side == 0 ? i1[j] : i2[j];
-        const bool fresh = side == 0 ? f1[j] : f2[j];
+      for (int sl = 0; sl < NSLOT; ++sl) {
+        const int t = tid + sl * BS;
+        if (t >= NB2) continue;
+        const bool fresh = f1[sl];
         if (!mask && !fresh) continue;  // left the plastic set, block already rewritten
-        double base[D * D];
-        if (a.elastic || !fresh) {
+        const int64_t idx = i1[sl];
+        double v[D * D];
+        if (a.elastic || !fresh) block_load<D>(Kt + idx * D * D, v);
+        else if constexpr (sizeof(VT) == 8) block_load<D>(a.Ke + idx * D * D, v);
+        else block_load<D>(a.Ke32 + idx * D * D, v);
+        if (mask) {
+          const int p = t / NP, pc = s_ord[t - (t / NP) * NP];
+          const double *kb = s_K + (p * NP + pc) * D * D;
 #pragma unroll
-          for (int i = 0; i < D * D; ++i) base[i] = (double)Kt[idx * D * D + i];
-        } else if constexpr (sizeof(VT) == 8) {
-#pragma unroll
-          for (int i = 0; i < D * D; ++i) base[i] = a.Ke[idx * D * D + i];
-        } else {
-#pragma unroll
-          for (int i = 0; i < D * D; ++i) base[i] = (double)a.Ke32[idx * D * D + i];
+          for (int i = 0; i < D * D; ++i) v[i] += kb[i];
         }
-        VT *dst = Kt + idx * D * D;
-#pragma unroll
-        for (int r = 0; r < D; ++r)
-#pragma unroll
-          for (int cc = 0; cc < D; ++cc)
-            dst[r * D + cc] = (VT)(base[r * D + cc] + (side == 0 ? acc[j][r * D + cc] : acc[j][cc * D + r]));
+        block_store<D>(Kt + idx * D * D, v);
         if (!a.elastic) a.epoch[idx] = a.cur;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NBT; ++j) {
+        if (!pon[j]) continue;
+        const bool diag = pp_[j] == pq_[j];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          if (side == 1 && diag) continue;
+          const int64_t idx = side == 0 ? i1[j] : i2[j];
+          const bool fresh = side == 0 ? f1[j] : f2[j];
+          if (!mask && !fresh) continue;  // left the plastic set, block already rewritten
+          double base[D * D];
+          if (a.elastic || !fresh) {
+#pragma unroll
+            for (int i = 0; i < D * D; ++i) base[i] = (double)Kt[idx * D * D + i];
+          } else if constexpr (sizeof(VT) == 8) {
+#pragma unroll
+            for (int i = 0; i < D * D; ++i) base[i] = a.Ke[idx * D * D + i];
+          } else {
+#pragma unroll
+            for (int i = 0; i < D * D; ++i) base[i] = (double)a.Ke32[idx * D * D + i];
+          }
+          VT *dst = Kt + idx * D * D;
+#pragma unroll
+          for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int cc = 0; cc < D; ++cc)
+              dst[r * D + cc] = (VT)(base[r * D + cc] + (side == 0 ? acc[j][r * D + cc] : acc[j][cc * D + r]));
+          if (!a.elastic) a.epoch[idx] = a.cur;
+        }
       }
     }
   }

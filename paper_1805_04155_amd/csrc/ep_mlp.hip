@@ -245,22 +245,30 @@ __global__ __launch_bounds__(256) void k_mlp_tile(MlpArgs a) {
   }
 }
 
-// grad = sum of the block partials in block order; optionally one Adam step
-// (bias corrections bc1 = 1 - beta1^t, bc2 = 1 - beta2^t from the host).
+// grad = sum of the block partials in a fixed order (4 interleaved partial
+// sums per parameter, combined in LDS); optionally one Adam step (bias
+// corrections bc1 = 1 - beta1^t, bc2 = 1 - beta2^t from the host).
+constexpr int RED_P = 64;  // parameters per block of the reduction
 __global__ __launch_bounds__(256) void k_mlp_reduce(const float *part, const float *part_loss,
                                                      int nblk, float inv_n, float *grad,
                                                      float *loss, float *params, float *m1,
                                                      float *m2, float lr, float bc1, float bc2,
                                                      int adam) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p == 0 && loss) {
+  __shared__ float s[4][RED_P];
+  const int lane = threadIdx.x & (RED_P - 1), grp = threadIdx.x / RED_P;
+  const int p = blockIdx.x * RED_P + lane;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && loss) {
     float l = 0.f;
     for (int b = 0; b < nblk; ++b) l += part_loss[b];
     loss[0] = l * inv_n;
   }
-  if (p >= NPAR) return;
   float g = 0.f;
-  for (int b = 0; b < nblk; ++b) g += part[(int64_t)b * NPAR + p];
+  if (p < NPAR)
+    for (int b = grp; b < nblk; b += 4) g += part[(int64_t)b * NPAR + p];
+  s[grp][lane] = g;
+  __syncthreads();
+  if (grp != 0 || p >= NPAR) return;
+  g = (s[0][lane] + s[1][lane]) + (s[2][lane] + s[3][lane]);
   if (grad) grad[p] = g;
   if (adam) {
     const float a1 = 0.9f * m1[p] + 0.1f * g;
@@ -351,7 +359,7 @@ hipError_t launch_mlp_train(MlpImpl &m, const float *X, const float *T, int64_t 
     hipLaunchKernelGGL((k_mlp_tile<true, true>), dim3(nblk), dim3(256), 0, m.stream, a);
   else
     hipLaunchKernelGGL((k_mlp_tile<false, true>), dim3(nblk), dim3(256), 0, m.stream, a);
-  hipLaunchKernelGGL(k_mlp_reduce, dim3(blocks_of(NPAR, 256)), dim3(256), 0, m.stream, m.part,
+  hipLaunchKernelGGL(k_mlp_reduce, dim3(blocks_of(NPAR, RED_P)), dim3(256), 0, m.stream, m.part,
                      m.part_loss, nblk, a.inv_n, grad, loss, m.params, m.m1, m.m2, lr, bc1, bc2,
                      adam ? 1 : 0);
   return hipGetLastError();

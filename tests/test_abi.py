@@ -67,3 +67,42 @@ def test_mlp_constants_match_header():
         assert m and int(m.group(1)) == val, name
     assert _ep.MLP_NPARAM == (_ep.MLP_IN * _ep.MLP_HID + _ep.MLP_HID + _ep.MLP_HID ** 2
                               + _ep.MLP_HID + _ep.MLP_OUT * _ep.MLP_HID + _ep.MLP_OUT)
+
+
+def _setup_error(mesh, free, mat, options=None):
+    import ctypes as C
+    with pytest.raises(_ep.EpError) as ei:
+        _ep.ep_setup(mesh, free, mat, options, stream=C.c_void_p(0))
+    return ei.value
+
+
+@pytest.mark.parametrize("what", ["node_range", "repeated_node", "nu", "yield", "local_prec",
+                                  "tangent_prec"])
+def test_setup_rejects_invalid_input(lib, what):
+    """Invalid meshes, materials and options are refused at setup with
+    EP_EINVAL and a message, before any device work (runs without a GPU)."""
+    import numpy as np
+    from paper_1805_04155_amd import workloads as W
+    mesh = W.mesh_q1_3d(2, 2, 2, 1.0, 1.0, 1.0)
+    free = np.ones(mesh.n_dof, np.uint8)
+    mat = W.VM_MATERIAL
+    opts = None
+    if what == "node_range":
+        elem = mesh.elem.copy()
+        elem[3, 2] = mesh.n_nodes
+        mesh = W.Mesh(mesh.etype, mesh.coord, elem)
+    elif what == "repeated_node":
+        elem = mesh.elem.copy()
+        elem[5, 1] = elem[5, 6]
+        mesh = W.Mesh(mesh.etype, mesh.coord, elem)
+    elif what == "nu":
+        mat = W.Material("VM", E=1000.0, nu=0.5, Y=1.0, a=0.0)
+    elif what == "yield":
+        mat = W.Material("DP", E=1000.0, nu=0.3, eta=0.0, c=1.0)
+    elif what == "local_prec":
+        opts = {"local_prec": _ep.EP_BF16}   # matrix-core products: Q2-27 / P2 only
+    else:
+        opts = {"tangent_prec": _ep.EP_BF16}
+    err = _setup_error(mesh, free, mat, opts)
+    assert err.status == _ep.EP_EINVAL
+    assert str(err)
