@@ -225,6 +225,8 @@ void free_ctx(Ctx *c) {
                   c->cmp_counts2, c->cmp_counts3, c->cmp_offsets, c->F, c->r, c->partials,
                   c->norms, c->pz, c->pp[0], c->pp[1], c->pq, c->px, c->dinv, c->sc,
                   c->iscratch, c->mlp_x, c->mlp_y, c->wu_pred, c->wu_warm};
+  if (c->pcg_graph) (void)hipGraphExecDestroy(c->pcg_graph);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->norms_h) (void)hipHostFree(c->norms_h);
@@ -339,6 +341,45 @@ ep_status do_residual(Ctx *c, const double *f, double *F_out) {
   return EP_OK;
 }
 
+// n PCG iterations.  Even chunks without profiling replay a HIP graph of
+// the chunk (captured once per solution vector and chunk length; the
+// iterations alternate two search-direction buffers, so an even chunk ends
+// where it started); otherwise the kernels are launched one by one.
+ep_status pcg_chunk(Ctx *c, double *x, int n) {
+  if (c->prof || n < 2 || n % 2 != 0) {
+    for (int k = 0; k < n; ++k) HIPC(launch_pcg_iteration(*c, x));
+    return EP_OK;
+  }
+  if (!c->pcg_graph || c->pcg_graph_x != x || c->pcg_graph_n != n) {
+    if (c->pcg_graph) {
+      HIPC(hipGraphExecDestroy(c->pcg_graph));
+      c->pcg_graph = nullptr;
+    }
+    if (!c->gstream) HIPC(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+    hipStream_t user = c->stream;
+    const int pcur = c->pcur;
+    c->stream = c->gstream;
+    hipError_t e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
+    for (int k = 0; k < n && e == hipSuccess; ++k) e = launch_pcg_iteration(*c, x);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(c->gstream, &g);
+    c->stream = user;
+    c->pcur = pcur;
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->pcg_graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->pcg_graph = nullptr;
+      c->err = std::string("PCG graph capture: ") + hipGetErrorString(e);
+      return EP_EDEVICE;
+    }
+    c->pcg_graph_x = x;
+    c->pcg_graph_n = n;
+  }
+  HIPC(hipGraphLaunch(c->pcg_graph, c->stream));
+  return EP_OK;
+}
+
 ep_status do_pcg(Ctx *c, const double *b, double *x, double rtol, int max_it, int *its,
                  double *relres) {
   HIPC(launch_diag_inv(*c));
@@ -350,7 +391,8 @@ ep_status do_pcg(Ctx *c, const double *b, double *x, double rtol, int max_it, in
   while (!done) {
     const int n = std::min(chunk, max_it - done_its);
     if (n <= 0) break;
-    for (int k = 0; k < n; ++k) HIPC(launch_pcg_iteration(*c, x));
+    const ep_status st = pcg_chunk(c, x, n);
+    if (st) return st;
     done_its += n;
     HIPC(hipMemcpyAsync(c->sc_h, c->sc, 16 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPC(hipStreamSynchronize(c->stream));
@@ -464,6 +506,9 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   Ctx *c = new Ctx();
   c->stream = (hipStream_t)hip_stream;
   (void)hipGetDevice(&c->dev);
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->dev) !=
+          hipSuccess || c->n_cu < 1)
+    c->n_cu = 256;
   c->et = ed.id;
   c->dim = dim;
   c->n_p = n_p;

@@ -116,6 +116,7 @@ struct Ctx {
   std::string err;
   hipStream_t stream = nullptr;
   int dev = 0;
+  int n_cu = 256;          // compute units of the device
 
   // sizes
   int et = 0;            // EtId
@@ -191,6 +192,14 @@ struct Ctx {
   double *pz = nullptr, *pp[2] = {nullptr, nullptr}, *pq = nullptr, *px = nullptr,
          *dinv = nullptr, *sc = nullptr, *sc_h = nullptr;
   int pcur = 0;
+
+  // PCG iterations replayed as a HIP graph: captured on gstream (a stream of
+  // the context, default priority) for a chunk of pcg_graph_n iterations
+  // updating pcg_graph_x
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t pcg_graph = nullptr;
+  const double *pcg_graph_x = nullptr;
+  int pcg_graph_n = 0;
 
   // learned warm start (allocated at first use)
   float *mlp_x = nullptr, *mlp_y = nullptr;  // [n_int][16], [n_int][8]

@@ -113,12 +113,12 @@ constexpr int CT = 256;  // threads of the constitutive kernel
 // LM = 2: plastic flag and stress from the network outputs; the tangent
 // descriptor is that of the trial state on the predicted branch.
 template <int ETID, int MODEL, int LM>
-__global__ __launch_bounds__(CT) void k_constitutive(KC a) {
+__global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(Et<ETID>::D == 2 ? 5 : 1, 8)))
+void k_constitutive(KC a) {
   using T = Et<ETID>;
   constexpr int D = T::D, NP = T::NP, NQ = T::NQ;
   constexpr int EPB = CT / NQ;
-  constexpr int NS = D == 3 ? 6 : 3;  // stress components entering B^T sigma
-  constexpr int NF = NS + D * D;      // per point: w*sigma, J^{-1}
+  constexpr int NF = D * D;           // per point: A = w sigma J^{-T} (see the force phase)
   constexpr int NSC = D == 3 ? 6 : 4; // stored state components
   constexpr int NSTR = D == 3 ? 6 : 3;
   __shared__ double s_ref[NQ * NP * D];
@@ -276,24 +276,34 @@ __global__ __launch_bounds__(CT) void k_constitutive(KC a) {
       }
     }
     if (a.force) {
-      double *sf = s_f + tid * NF;
+      // grad phi_p = J^{-1} dphi_p, so sigma grad phi_p = (sigma J^{-1}) dphi_p:
+      // one D x D matrix per point instead of sigma and J^{-1}
+      double sm[D][D];
       if constexpr (D == 3) {
-#pragma unroll
-        for (int i = 0; i < 6; ++i) sf[i] = w * sig[i];
+        sm[0][0] = sig[0]; sm[1][1] = sig[1]; sm[2][2] = sig[2];
+        sm[0][1] = sm[1][0] = sig[3];
+        sm[1][2] = sm[2][1] = sig[4];
+        sm[0][2] = sm[2][0] = sig[5];
       } else {
-        sf[0] = w * sig[0];
-        sf[1] = w * sig[1];
-        sf[2] = w * sig[3];
+        sm[0][0] = sig[0]; sm[1][1] = sig[1];
+        sm[0][1] = sm[1][0] = sig[3];
       }
+      double *sf = s_f + tid * NF;
 #pragma unroll
       for (int i = 0; i < D; ++i)
 #pragma unroll
-        for (int j = 0; j < D; ++j) sf[NS + i * D + j] = Ji[i][j];
+        for (int j = 0; j < D; ++j) {
+          double v = 0.0;
+#pragma unroll
+          for (int k = 0; k < D; ++k) v += sm[i][k] * Ji[k][j];
+          sf[i * D + j] = w * v;
+        }
     }
   }
   __syncthreads();
   if (!a.force) return;
   // F_e[p] = sum_q w_q sigma_q grad phi_p(q)  (B^T (WEIGHT .* S), Section 7)
+  //        = sum_q A_q dphi_p(q) with A_q = w_q sigma_q J_q^{-1}
   for (int t = tid; t < EPB * NP; t += CT) {
     const int elx = t / NP, p = t - (t / NP) * NP;
     const int64_t ee = e0 + elx;
@@ -302,22 +312,12 @@ __global__ __launch_bounds__(CT) void k_constitutive(KC a) {
 #pragma unroll
     for (int i = 0; i < D; ++i) f[i] = 0.0;
     for (int qq = 0; qq < NQ; ++qq) {
-      const double *sf = s_f + (elx * NQ + qq) * NF;
-      double Ji[D][D];
+      const double *A = s_f + (elx * NQ + qq) * NF;
+      const double *dr = s_ref + (qq * NP + p) * D;
 #pragma unroll
       for (int i = 0; i < D; ++i)
 #pragma unroll
-        for (int j = 0; j < D; ++j) Ji[i][j] = sf[NS + i * D + j];
-      double g[D];
-      grad<D>(Ji, s_ref + (qq * NP + p) * D, g);
-      if constexpr (D == 3) {
-        f[0] += sf[0] * g[0] + sf[3] * g[1] + sf[5] * g[2];
-        f[1] += sf[3] * g[0] + sf[1] * g[1] + sf[4] * g[2];
-        f[2] += sf[5] * g[0] + sf[4] * g[1] + sf[2] * g[2];
-      } else {
-        f[0] += sf[0] * g[0] + sf[2] * g[1];
-        f[1] += sf[2] * g[0] + sf[1] * g[1];
-      }
+        for (int j = 0; j < D; ++j) f[i] += A[i * D + j] * dr[j];
     }
 #pragma unroll
     for (int i = 0; i < D; ++i) a.Fe[(ee * NP + p) * D + i] = f[i];
@@ -524,10 +524,26 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
     pp_[j] = p;
     pq_[j] = p + t;
   }
-  for (int64_t k = k0 + blockIdx.x; k < k1; k += gridDim.x) {
-    const int e = a.list[k];
-    if (e < 0) continue;  // padding of the colour-major order (uniform)
-    const uint32_t mask = (a.elastic ? 0xffffffffu : a.emask[e]) & qmask;
+  // software pipeline over the elements of this block: the list entry, mask
+  // and node ids of the next element are loaded while the current one is
+  // processed
+  int64_t k = k0 + blockIdx.x;
+  int e_n = k < k1 ? a.list[k] : -1;
+  uint32_t m_n = (e_n >= 0 && !a.elastic) ? a.emask[e_n] : 0xffffffffu;
+  int node_n = (e_n >= 0 && tid < NP) ? a.elem[(int64_t)e_n * NP + tid] : 0;
+  for (; k < k1; k += gridDim.x) {
+    const int e = e_n;
+    const uint32_t mask = m_n & qmask;
+    const int node_cur = node_n;
+    {
+      const int64_t kn = k + gridDim.x;
+      e_n = kn < k1 ? a.list[kn] : -1;
+    }
+    if (e < 0) {  // padding of the colour-major order (uniform)
+      m_n = (e_n >= 0 && !a.elastic) ? a.emask[e_n] : 0xffffffffu;
+      node_n = (e_n >= 0 && tid < NP) ? a.elem[(int64_t)e_n * NP + tid] : 0;
+      continue;
+    }
     const int nq = __popc(mask);
     // scatter targets: sorted mode, slot t = p * NP + r is block (p, s_ord[r]);
     // pair mode, the blocks (p, p') and (p', p) of this thread's pairs
@@ -535,7 +551,7 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
     bool f1[SORTED ? NSLOT : NBT], f2[SORTED ? 1 : NBT];
     if constexpr (SORTED) {
       __syncthreads();  // LDS of the previous element is no longer read
-      if (tid < NP) s_node[tid] = a.elem[(int64_t)e * NP + tid];
+      if (tid < NP) s_node[tid] = node_cur;
       __syncthreads();
       if (tid < NP) {
         int r = 0;
@@ -687,6 +703,8 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
         __syncthreads();
       }
     }
+    m_n = (e_n >= 0 && !a.elastic) ? a.emask[e_n] : 0xffffffffu;
+    node_n = (e_n >= 0 && tid < NP) ? a.elem[(int64_t)e_n * NP + tid] : 0;
     // base values (K_elast for blocks not yet written in this assembly, else
     // K_tangent) plus the element's contribution
     if constexpr (SORTED) {
@@ -1667,6 +1685,10 @@ static hipError_t colour_et(Ctx &c, int colour, int epoch) {
   const int64_t cnt = c.colour_size[colour];
   if (cnt == 0) return hipSuccess;
   const int grid = (int)(cnt < 65536 ? cnt : 65536);
+  // the FP64/FP32 kernel loops over elements with a software pipeline: a grid
+  // of about twice the resident blocks gives each block a few elements
+  const int gcap = 48 * c.n_cu;
+  const int gpipe = grid < gcap ? grid : gcap;
   const bool f32 = c.opt.tangent_prec == EP_FP32;
   if constexpr (ETID == ET_Q2_3D || ETID == ET_P2_3D) {
     if (c.opt.local_prec == EP_BF16 || c.opt.local_prec == EP_FP32) {
@@ -1683,9 +1705,9 @@ static hipError_t colour_et(Ctx &c, int colour, int epoch) {
     }
   }
   if (f32)
-    hipLaunchKernelGGL((k_assemble<ETID, float>), dim3(grid), dim3(Cfg::BS), 0, c.stream, a);
+    hipLaunchKernelGGL((k_assemble<ETID, float>), dim3(gpipe), dim3(Cfg::BS), 0, c.stream, a);
   else
-    hipLaunchKernelGGL((k_assemble<ETID, double>), dim3(grid), dim3(Cfg::BS), 0, c.stream, a);
+    hipLaunchKernelGGL((k_assemble<ETID, double>), dim3(gpipe), dim3(Cfg::BS), 0, c.stream, a);
   return hipGetLastError();
 }
 hipError_t launch_colour_assembly(Ctx &c, int colour, int epoch) {
