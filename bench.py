@@ -71,9 +71,10 @@ def kernel_bytes(mesh, mat, counts, tangent_bytes):
     blk = NP * NP
     return {
         # coords + displacement once per node, connectivity, state per point,
-        # flag, descriptor of plastic points, element force vectors, mask
+        # flag, descriptor of plastic points, element force vectors and
+        # their node-order slots, mask
         "constitutive": 2 * 8 * n_dof + 4 * NP * n_e + state * n_int + n_int
-        + 8 * ndesc * pi + 8 * D * NP * n_e + 4 * n_e,
+        + 8 * ndesc * pi + (8 * D + 4) * NP * n_e + 4 * n_e,
         # per listed element: position map, epoch read + write, base value
         # read, tangent write, mask; per plastic element its connectivity and
         # coordinates; per plastic point its tangent descriptor
@@ -81,7 +82,8 @@ def kernel_bytes(mesh, mat, counts, tangent_bytes):
         + 8 * ndesc * pi,
         # colour-major order and two masks read, list written
         "compaction": counts["n_perm"] * 4 + 8 * n_e + 4 * listed,
-        "force": 4 * (n_n + 1) + 4 * NP * n_e + 8 * D * NP * n_e + n_dof * (8 + 1 + 8),
+        # node offsets, element force vectors (node order), f, free mask, F/r
+        "force": 4 * (n_n + 1) + 8 * D * NP * n_e + n_dof * (8 + 1 + 8),
     }
 
 

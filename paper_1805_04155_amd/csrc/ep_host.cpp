@@ -219,7 +219,7 @@ hipError_t upload(T *d, const std::vector<T> &h, hipStream_t s) {
 void free_ctx(Ctx *c) {
   if (!c) return;
   void *ptrs[] = {c->coord, c->elem, c->freem, c->ref, c->bptr, c->bcol, c->bdiag, c->bpos,
-                  c->Ke, c->Ke32, c->Kt, c->epoch, c->n2e_ptr, c->n2e, c->ecol_perm,
+                  c->Ke, c->Ke32, c->Kt, c->epoch, c->n2e_ptr, c->fslot, c->ecol_perm,
                   c->d_colour_first_block, c->ep_s, c->beta_s, c->kappa_s, c->flag, c->desc,
                   c->Fe, c->em[0], c->em[1], c->plist, c->coff, c->ptotals, c->cmp_counts,
                   c->cmp_counts2, c->cmp_counts3, c->cmp_offsets, c->F, c->r, c->partials,
@@ -540,13 +540,17 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
 
   const int32_t *E = mesh->elem;
   // node -> (element, local node), ascending element
-  std::vector<int32_t> n2e_ptr(n_n + 1, 0), n2e(n_e * n_p);
+  std::vector<int32_t> n2e_ptr(n_n + 1, 0), n2e(n_e * n_p), fslot(n_e * n_p);
   for (int64_t i = 0; i < n_e * n_p; ++i) n2e_ptr[E[i] + 1]++;
   for (int64_t m = 0; m < n_n; ++m) n2e_ptr[m + 1] += n2e_ptr[m];
   {
     std::vector<int32_t> fill(n2e_ptr.begin(), n2e_ptr.end() - 1);
     for (int64_t e = 0; e < n_e; ++e)
-      for (int p = 0; p < n_p; ++p) n2e[fill[E[e * n_p + p]]++] = (int32_t)(e * n_p + p);
+      for (int p = 0; p < n_p; ++p) {
+        const int32_t k = fill[E[e * n_p + p]]++;
+        n2e[k] = (int32_t)(e * n_p + p);
+        fslot[e * n_p + p] = k;  // element force vectors are stored node by node
+      }
   }
   // node adjacency -> node-block CSR
   std::vector<int32_t> deg(n_n, 0);
@@ -663,7 +667,7 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   }
   SETUP_HIP(dalloc(&c->epoch, nnzb));
   SETUP_HIP(dalloc(&c->n2e_ptr, n_n + 1));
-  SETUP_HIP(dalloc(&c->n2e, n_e * n_p));
+  SETUP_HIP(dalloc(&c->fslot, n_e * n_p));
   SETUP_HIP(dalloc(&c->ecol_perm, (int64_t)perm.size()));
   SETUP_HIP(dalloc(&c->d_colour_first_block, n_col + 1));
   SETUP_HIP(dalloc(&c->ep_s, c->n_sc * n_int));
@@ -711,7 +715,7 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   SETUP_HIP(upload(c->bdiag, bdiag, s));
   SETUP_HIP(upload(c->bpos, bpos, s));
   SETUP_HIP(upload(c->n2e_ptr, n2e_ptr, s));
-  SETUP_HIP(upload(c->n2e, n2e, s));
+  SETUP_HIP(upload(c->fslot, fslot, s));
   SETUP_HIP(upload(c->ecol_perm, perm, s));
   SETUP_HIP(upload(c->d_colour_first_block, c->colour_first_block, s));
   SETUP_HIP(hipMemsetAsync(c->ep_s, 0, sizeof(double) * c->n_sc * n_int, s));

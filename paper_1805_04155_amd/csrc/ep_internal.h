@@ -143,9 +143,11 @@ struct Ctx {
   int32_t *epoch = nullptr;    // [nnzb]
   int epoch_counter = 0;
 
-  // node -> (element, local node), ascending element
+  // element force vectors are stored node by node: the entries of node m
+  // (one per incident element, ascending element) are n2e_ptr[m] ..
+  // n2e_ptr[m+1]-1, and element e's local node p writes entry fslot[e*n_p+p]
   int32_t *n2e_ptr = nullptr;  // [n_n+1]
-  int32_t *n2e = nullptr;      // [n_e*n_p], entries e*n_p + p
+  int32_t *fslot = nullptr;    // [n_e*n_p]
 
   // colouring
   std::vector<int64_t> colour_size;        // host
@@ -160,7 +162,7 @@ struct Ctx {
   double *kappa_s = nullptr;   // [n_int]
   uint8_t *flag = nullptr;     // [n_int]
   double *desc = nullptr;      // [n_desc][n_int]
-  double *Fe = nullptr;        // [n_e*n_p][dim]
+  double *Fe = nullptr;        // [n_e*n_p][dim], in node order (fslot)
   // plastic-point bitmask per element, two buffers: the one written by the
   // last constitutive pass and the one the last assembly used
   uint32_t *em[2] = {nullptr, nullptr};   // [n_e] each

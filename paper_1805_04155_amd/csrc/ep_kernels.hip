@@ -97,6 +97,7 @@ struct KC {
   uint8_t *flag;
   double *desc;
   double *Fe;
+  const int32_t *fslot;
   uint32_t *emask;
   double *eps_out, *sig_out, *D_out;
   uint8_t *flag_out;
@@ -319,8 +320,9 @@ void k_constitutive(KC a) {
 #pragma unroll
         for (int j = 0; j < D; ++j) f[i] += A[i * D + j] * dr[j];
     }
+    const int64_t slot = a.fslot[ee * NP + p];
 #pragma unroll
-    for (int i = 0; i < D; ++i) a.Fe[(ee * NP + p) * D + i] = f[i];
+    for (int i = 0; i < D; ++i) a.Fe[slot * D + i] = f[i];
   }
   for (int t = tid; t < EPB; t += CT)
     if (e0 + t < a.n_e) a.emask[e0 + t] = s_mask[t];
@@ -1043,7 +1045,7 @@ __global__ __launch_bounds__(256) void k_assemble_mfma(KA a) {
 // ----------------------------------------------------------------------------
 template <int D>
 __global__ __launch_bounds__(256) void k_force_gather(int64_t n_n, const int32_t *n2e_ptr,
-                                                      const int32_t *n2e, const double *Fe,
+                                                      const double *Fe,
                                                       const double *f, const uint8_t *freem,
                                                       double *F_out, double *r_out,
                                                       double *partials) {
@@ -1056,10 +1058,9 @@ __global__ __launch_bounds__(256) void k_force_gather(int64_t n_n, const int32_t
 #pragma unroll
     for (int i = 0; i < D; ++i) s[i] = 0.0;
     const int k1 = n2e_ptr[m + 1];
-    for (int k = n2e_ptr[m]; k < k1; ++k) {
-      const int64_t ent = n2e[k];
+    for (int64_t k = n2e_ptr[m]; k < k1; ++k) {
 #pragma unroll
-      for (int i = 0; i < D; ++i) s[i] += Fe[ent * D + i];
+      for (int i = 0; i < D; ++i) s[i] += Fe[k * D + i];
     }
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -1539,6 +1540,7 @@ static hipError_t constitutive_et(Ctx &c, const ConstArgs &ca) {
   a.flag = c.flag;
   a.desc = c.desc;
   a.Fe = c.Fe;
+  a.fslot = c.fslot;
   a.emask = c.em[c.em_cur];
   a.eps_out = ca.eps_out;
   a.sig_out = ca.sig_out;
@@ -1600,10 +1602,10 @@ hipError_t launch_force_gather(Ctx &c, const double *f, double *F_out, double *r
   if (nblk == 0) return hipSuccess;
   if (c.dim == 2)
     hipLaunchKernelGGL((k_force_gather<2>), dim3(nblk), dim3(256), 0, c.stream, c.n_n,
-                       c.n2e_ptr, c.n2e, c.Fe, f, c.freem, F_out, r_out, partials);
+                       c.n2e_ptr, c.Fe, f, c.freem, F_out, r_out, partials);
   else
     hipLaunchKernelGGL((k_force_gather<3>), dim3(nblk), dim3(256), 0, c.stream, c.n_n,
-                       c.n2e_ptr, c.n2e, c.Fe, f, c.freem, F_out, r_out, partials);
+                       c.n2e_ptr, c.Fe, f, c.freem, F_out, r_out, partials);
   return hipGetLastError();
 }
 
