@@ -222,7 +222,7 @@ void free_ctx(Ctx *c) {
                   c->Ke, c->Ke32, c->Kt, c->epoch, c->n2e_ptr, c->fslot, c->ecol_perm,
                   c->d_colour_first_block, c->ep_s, c->beta_s, c->kappa_s, c->flag, c->desc,
                   c->Fe, c->em[0], c->em[1], c->plist, c->coff, c->ptotals, c->cmp_counts,
-                  c->cmp_counts2, c->cmp_counts3, c->cmp_offsets, c->F, c->r, c->partials,
+                  c->cmp_counts2, c->cmp_counts3, c->F, c->r, c->partials,
                   c->norms, c->pz, c->pp[0], c->pp[1], c->pq, c->px, c->dinv, c->sc,
                   c->iscratch, c->mlp_x, c->mlp_y, c->wu_pred, c->wu_warm};
   if (c->pcg_graph) (void)hipGraphExecDestroy(c->pcg_graph);
@@ -687,7 +687,6 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   SETUP_HIP(dalloc(&c->cmp_counts, c->cmp_cap));
   SETUP_HIP(dalloc(&c->cmp_counts2, c->cmp_cap));
   SETUP_HIP(dalloc(&c->cmp_counts3, c->cmp_cap));
-  SETUP_HIP(dalloc(&c->cmp_offsets, c->cmp_cap + 1));
   SETUP_HIP(dalloc(&c->F, n_dof));
   SETUP_HIP(dalloc(&c->r, n_dof));
   // reductions: 2 per 256 dofs (PCG vectors, force gather) or 1 per SpMV

@@ -179,8 +179,7 @@ struct Ctx {
   int32_t *iscratch = nullptr;  // [max(n_int, n_e)] ascending plastic lists
 
   // compaction scratch
-  int32_t *cmp_counts = nullptr, *cmp_counts2 = nullptr, *cmp_counts3 = nullptr,
-          *cmp_offsets = nullptr;
+  int32_t *cmp_counts = nullptr, *cmp_counts2 = nullptr, *cmp_counts3 = nullptr;
   int64_t cmp_cap = 0;  // blocks
 
   // vectors

@@ -1160,70 +1160,63 @@ __global__ __launch_bounds__(CMP_THREADS) void k_compact_count(const void *src,
   }
 }
 
-// Exclusive scan of the block counts (single workgroup), colour offsets and
-// totals: [0] selected items, [1] set bits, [2] items with src != 0.
-__global__ __launch_bounds__(1024) void k_compact_scan(const int32_t *counts,
-                                                       const int32_t *counts2,
-                                                       const int32_t *counts3, int nblk,
-                                                       int32_t *offsets,
-                                                       const int32_t *colour_first_block,
-                                                       int n_col, int32_t *colour_off,
-                                                       int32_t *totals) {
-  __shared__ int32_t s[1024];
-  __shared__ int32_t s2[1024];
-  __shared__ int32_t s3[1024];
-  const int tid = threadIdx.x;
-  const int per = (nblk + 1023) / 1024;
-  const int b0 = tid * per;
-  int32_t sum = 0, sum2 = 0, sum3 = 0;
-  for (int b = b0; b < b0 + per && b < nblk; ++b) {
-    sum += counts[b];
-    sum2 += counts2[b];
-    sum3 += counts3[b];
-  }
-  s[tid] = sum;
-  s2[tid] = sum2;
-  s3[tid] = sum3;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int32_t v = tid >= o ? s[tid - o] : 0;
-    const int32_t v2 = tid >= o ? s2[tid - o] : 0;
-    const int32_t v3 = tid >= o ? s3[tid - o] : 0;
-    __syncthreads();
-    s[tid] += v;
-    s2[tid] += v2;
-    s3[tid] += v3;
-    __syncthreads();
-  }
-  int32_t run = s[tid] - sum;  // exclusive prefix of this thread's range
-  for (int b = b0; b < b0 + per && b < nblk; ++b) {
-    offsets[b] = run;
-    run += counts[b];
-  }
-  __syncthreads();
-  if (tid == 0) {
-    totals[0] = s[1023];
-    totals[1] = s2[1023];
-    totals[2] = s3[1023];
-    offsets[nblk] = s[1023];
-  }
-  __syncthreads();
-  if (colour_off)
-    for (int c = tid; c <= n_col; c += 1024) {
-      const int fb = colour_first_block[c];
-      colour_off[c] = fb >= nblk ? s[1023] : offsets[fb];
-    }
-}
-
-__global__ __launch_bounds__(CMP_THREADS) void k_compact_scatter(const void *src,
-                                                                 const uint32_t *src2, int kind,
-                                                                 const int32_t *perm, int64_t n,
-                                                                 const int32_t *offsets,
-                                                                 int32_t *out) {
+// Scatter of the selected items.  Each block first sums the counts of the
+// blocks before it (its output offset); block 0 also writes the totals
+// [0] selected items, [1] set bits, [2] items with src != 0, and the output
+// offset of every colour segment.  Integer sums: exact in any order.
+__global__ __launch_bounds__(CMP_THREADS) void k_compact_scatter(
+    const void *src, const uint32_t *src2, int kind, const int32_t *perm, int64_t n,
+    const int32_t *counts, const int32_t *counts2, const int32_t *counts3, int nblk,
+    const int32_t *colour_first_block, int n_col, int32_t *colour_off, int32_t *totals,
+    int32_t *out) {
   __shared__ int32_t s_w[CMP_THREADS / 64];
+  __shared__ int32_t s_r[3][CMP_THREADS];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t base = (int64_t)blockIdx.x * CMP_CHUNK;
-  int32_t run = offsets[blockIdx.x];
+  // offset of this block; block 0: the three totals
+  {
+    int32_t a = 0, b2 = 0, b3 = 0;
+    const int lim = blockIdx.x == 0 ? nblk : (int)blockIdx.x;
+    for (int j = tid; j < lim; j += CMP_THREADS) {
+      a += counts[j];
+      if (blockIdx.x == 0) {
+        b2 += counts2[j];
+        b3 += counts3[j];
+      }
+    }
+    s_r[0][tid] = a;
+    s_r[1][tid] = b2;
+    s_r[2][tid] = b3;
+    __syncthreads();
+    for (int o = CMP_THREADS / 2; o > 0; o >>= 1) {
+      if (tid < o) {
+        s_r[0][tid] += s_r[0][tid + o];
+        s_r[1][tid] += s_r[1][tid + o];
+        s_r[2][tid] += s_r[2][tid + o];
+      }
+      __syncthreads();
+    }
+  }
+  int32_t run = blockIdx.x == 0 ? 0 : s_r[0][0];
+  if (blockIdx.x == 0) {
+    const int32_t total = s_r[0][0];
+    if (tid == 0) {
+      totals[0] = total;
+      totals[1] = s_r[1][0];
+      totals[2] = s_r[2][0];
+    }
+    if (colour_off)
+      for (int c = tid; c <= n_col; c += CMP_THREADS) {
+        const int fb = colour_first_block[c];
+        int32_t off = 0;
+        if (fb >= nblk) {
+          off = total;
+        } else {
+          for (int j = 0; j < fb; ++j) off += counts[j];
+        }
+        colour_off[c] = off;
+      }
+  }
   for (int k = 0; k < CMP_ITEMS; ++k) {
     const int64_t i = base + (int64_t)k * CMP_THREADS + tid;
     int64_t item = -1;
@@ -1623,12 +1616,10 @@ hipError_t launch_compact(Ctx &c, int kind, const void *src, const uint32_t *src
   if (nblk > 0)
     hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(CMP_THREADS), 0, c.stream, src, src2,
                        kind, perm, n, c.cmp_counts, c.cmp_counts2, c.cmp_counts3);
-  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, c.stream, c.cmp_counts,
-                     c.cmp_counts2, c.cmp_counts3, nblk, c.cmp_offsets, colour_first_block, n_col,
-                     colour_off, totals);
-  if (nblk > 0)
-    hipLaunchKernelGGL(k_compact_scatter, dim3(nblk), dim3(CMP_THREADS), 0, c.stream, src, src2,
-                       kind, perm, n, c.cmp_offsets, out);
+  // at least one block: block 0 writes the totals and colour offsets
+  hipLaunchKernelGGL(k_compact_scatter, dim3(nblk > 0 ? nblk : 1), dim3(CMP_THREADS), 0, c.stream,
+                     src, src2, kind, perm, n, c.cmp_counts, c.cmp_counts2, c.cmp_counts3, nblk,
+                     colour_first_block, n_col, colour_off, totals, out);
   return hipGetLastError();
 }
 
