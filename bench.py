@@ -22,7 +22,10 @@ Also measured (unless --no-newton), as extra objects of the same line:
     local products (FP32, BF16) on the Q2 / P2 blocks' 20-step paths;
   local_precision: incremental tangent error of the FP32 / BF16 local
     products against the FP64 path, and the assembly kernel's matrix-core
-    rate, on the Q2 / P2 blocks with half of the elements seeded plastic.
+    rate, on the Q2 / P2 blocks with half of the elements seeded plastic;
+  plastic_sweep: the same pass on the 64^3 Q1 cube with 0/25/50/100 % of the
+    elements seeded plastic, FP64 and FP32 tangent values, at u = 0 and at
+    the first Newton iterate of the load step t = 324.
 
 Prints one JSON line (rank 0, one GPU).
 """
@@ -255,6 +258,63 @@ def newton_report(cube_n, n_samples, block):
     return rep
 
 
+def time_pass(ctx, u, F, steps):
+    """Mean wall time (ms) of `steps` passes (constitutive + compaction +
+    assembly + force) after 2 warm-up passes."""
+    import torch
+    from paper_1805_04155_amd import _ep
+
+    def step():
+        _ep.ep_constitutive(ctx.h, u)
+        _ep.ep_assemble_tangent(ctx.h)
+        _ep.ep_internal_force(ctx.h, F)
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / steps
+
+
+def plastic_sweep(steps):
+    """Throughput on the 64^3 Q1 cube (von Mises) against the seeded plastic
+    fraction and the tangent value type, at u = 0 and at the first Newton
+    iterate of load step 6 (t = 324)."""
+    import torch
+    from paper_1805_04155_amd import _ep
+    from paper_1805_04155_amd import workloads as W
+    wl = W.workload_q1_cube(64)
+    mesh, mat = wl.mesh, wl.material
+    out = {"workload": "unit cube, 64^3 Q1 hexahedra (2097152 points), von Mises kinematic",
+           "unit": "M integration pts/s", "rows": []}
+    F = torch.empty(mesh.n_dof, dtype=torch.float64, device="cuda")
+    f6 = torch.as_tensor(wl.f(5), dtype=torch.float64, device="cuda")
+    for tang in ("fp64", "fp32"):
+        ctx = _ep.Context(mesh, wl.free, mat, options={
+            "tangent_prec": _ep.EP_FP64 if tang == "fp64" else _ep.EP_FP32})
+        for frac in (0.0, 0.25, 0.5, 1.0):
+            ep, beta, kappa, _ = W.seeded_state(wl, frac, seed=0)
+            ctx.set_state(ep, beta, None)
+            u = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
+            ms0 = time_pass(ctx, u, F, steps)
+            n_ip0, _ = _ep.ep_get_plastic(ctx.h)
+            _ep.ep_newton_step(ctx.h, f6, u)
+            ms1 = time_pass(ctx, u, F, steps)
+            n_ip1, _ = _ep.ep_get_plastic(ctx.h)
+            row = {"tangent": tang, "seeded_fraction": frac,
+                   "u0": {"ms": round(ms0, 4), "value": round(mesh.n_int / ms0 / 1e3, 1),
+                          "plastic_points": n_ip0},
+                   "first_iterate": {"ms": round(ms1, 4),
+                                     "value": round(mesh.n_int / ms1 / 1e3, 1),
+                                     "plastic_points": n_ip1}}
+            out["rows"].append(row)
+            log(f"sweep {row}")
+        ctx.close()
+    return out
+
+
 def local_precision_report(block):
     """Matrix-core local products on the blocks at a seeded state: tangent
     error against the FP64 path (relative Frobenius norm, and the largest
@@ -333,6 +393,8 @@ def main():
     ap.add_argument("--newton-cube-n", type=int, default=64)
     ap.add_argument("--newton-samples", type=float, default=20e6)
     ap.add_argument("--newton-block", default="32,16,16")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the plastic-fraction sweep on the Q1 cube")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hot path is built and timed on a single "
@@ -426,7 +488,9 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, ep, beta, kappa, u_np)
-    newton = local = None
+    newton = local = sweep = None
+    if not args.no_sweep:
+        sweep = plastic_sweep(max(5, args.steps // 2))
     if not args.no_newton:
         block = tuple(int(x) for x in args.newton_block.split(","))
         local = local_precision_report(block)
@@ -452,6 +516,7 @@ def main():
         "cpu_baseline": cpu,
         "newton": newton,
         "local_precision": local,
+        "plastic_sweep": sweep,
     }
     print(json.dumps(line), flush=True)
 

@@ -27,11 +27,15 @@ def _np(t):
 
 
 @pytest.mark.parametrize("case", ["q2_3d_dph", "p2_3d_dph"])
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16_f32values"])
 def test_incremental_tangent_matrix_cores(case, prec):
+    """bf16_f32values: BF16 local products with K stored in FP32."""
     mesh, free, mat, u, (ep, beta, kappa) = make_case(case)
-    ctx = _ep.Context(mesh, free, mat,
-                      options={"local_prec": _ep.EP_FP32 if prec == "fp32" else _ep.EP_BF16})
+    opts = {"local_prec": _ep.EP_FP32 if prec == "fp32" else _ep.EP_BF16}
+    if prec == "bf16_f32values":
+        opts["tangent_prec"] = _ep.EP_FP32
+    prec = prec.split("_")[0]
+    ctx = _ep.Context(mesh, free, mat, options=opts)
     try:
         ctx.set_state(ep, None, kappa)
         _, _, Ke = ctx.csr(0)
