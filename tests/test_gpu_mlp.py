@@ -250,6 +250,51 @@ def test_warm_start_parity():
         ctx.close()
 
 
+def test_warm_start_parity_drucker_prager():
+    """The learned step with Drucker-Prager hardening (27-node hexahedra):
+    predicted cone / apex tangents and network stresses, against the
+    oracle's warm start with the same network in FP64."""
+    wl = W.workload_q2_block(4, 2, 2, q_max=4000.0, steps=4)
+    mesh, mat = wl.mesh, wl.material
+    n = mesh.n_int
+    z6, kap0 = np.zeros((n, 6)), np.zeros(n)
+    u1, _, _, out1 = O.newton_solve(mesh, mat, wl.free, wl.f(1), np.zeros(mesh.n_dof), z6, z6,
+                                    kap0, tol=1e-12)
+    ep6, kappa = out1["ep"], out1["kappa"]
+    u2, *_ = O.newton_solve(mesh, mat, wl.free, wl.f(2), u1, ep6, z6, kappa, tol=1e-12)
+    f = wl.f(3)
+    extrap = 1.0
+    p = _params(31)
+    P = M.unpack(p.astype(np.float64))
+    P["b3"][6] = 0.3   # 396 of 432 points predicted plastic, |logit| > 0.015
+    p = M.pack(P).astype(np.float32)
+
+    def net(X):
+        return M.forward(p.astype(np.float64), X)[0]
+
+    u_o, info_o = M.warm_start(mesh, mat, wl.free, f, u2, u1, extrap, ep6, z6, kappa, net)
+    u_pred = u2 + extrap * (u2 - u1) * wl.free
+    logit = net(M.features(mesh, mat, u_pred, ep6, kappa))[:, 6]
+    assert np.abs(logit).min() > 1e-3
+    ctx = _ep.Context(mesh, wl.free, mat, options={"pcg_max_it": 20000})
+    mlp = _ep.Mlp(_ep.EP_FP32, 64)
+    try:
+        ctx.set_state(O.ip6_to_state(ep6, 3), None, kappa)
+        mlp.set_params(p)
+        uo = ctx.tensor(u2)
+        st, info = ctx.warm_start(mlp, ctx.tensor(f), uo, ctx.tensor(u1), extrap, 1e-13, uo)
+        assert st == _ep.EP_OK
+        assert info["n_plastic_pred"] == info_o["n_plastic_pred"] > 0
+        assert abs(info["res_rel_start"] - info_o["res_rel_start"]) <= 1e-9 * info_o["res_rel_start"]
+        assert abs(info["res_rel_pred"] - info_o["res_rel_pred"]) <= 1e-5 * info_o["res_rel_pred"]
+        assert abs(info["res_rel_warm"] - info_o["res_rel_warm"]) <= 1e-4 * info_o["res_rel_warm"]
+        assert info["accepted"] == info_o["accepted"]
+        assert np.abs(_np(uo) - u_o).max() <= 1e-4 * np.abs(u_o).max()
+    finally:
+        mlp.close()
+        ctx.close()
+
+
 def _cube_cyclic(n, steps):
     return W.workload_q1_cube_cyclic(n, steps)
 
