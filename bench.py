@@ -423,12 +423,26 @@ def main():
     u = ctx.tensor(u_np)
     F = torch.empty(mesh.n_dof, dtype=torch.float64, device="cuda")
 
+    copy_gbs = None
     if not args.no_calibration_copy:
-        # plain copy of a known size, for scaling hardware byte counters
+        # plain copy of a known size, for scaling hardware byte counters; then
+        # the measured copy rate (read + write bytes over time) as the
+        # practical HBM ceiling beside the published peak
         a = torch.empty(64 * 2 ** 20, dtype=torch.float64, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_ms = e0.elapsed_time(e1) / 20
+        copy_gbs = round(2 * a.numel() * 8 / (copy_ms / 1e3) / 1e9, 1)
+        log(f"copy of 512 MiB: {copy_ms:.4f} ms, {copy_gbs} GB/s read + write")
         del a, b
 
     def step():
@@ -480,7 +494,9 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "algorithmic_bytes_per_launch": int(d["bytes_per_step"] / n_launch),
                 "avg_launch_ms": round(d["ms_per_step"] / n_launch, 5),
-                "traffic": traffic}
+                "traffic": traffic,
+                "copy_GB_s": copy_gbs,
+                "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None}
 
     ctx.close()
     del ctx, F, u

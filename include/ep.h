@@ -74,6 +74,15 @@ typedef enum { EP_VM = 1, EP_DP = 2 } ep_model;
 
 typedef enum { EP_FP64 = 0, EP_FP32 = 1, EP_BF16 = 2 } ep_prec;
 
+/* How the Newton step applies the tangent (eq. K-split):
+ * ASSEMBLED: K_tangent is assembled into the CSR values and PCG multiplies
+ *            by it (ep_assemble_tangent);
+ * SPLIT:     nothing is assembled; PCG applies K_elast (CSR) plus, element
+ *            by element, B^T (D_tangent - D_elast) B over the elements with
+ *            plastic points (ep_apply_tangent), and its Jacobi diagonal is
+ *            diag K_elast plus the diagonals of those element terms. */
+typedef enum { EP_OPERATOR_ASSEMBLED = 0, EP_OPERATOR_SPLIT = 1 } ep_operator;
+
 typedef struct {
   int32_t dim;               /* 2 (plane strain) or 3                        */
   int32_t type;              /* ep_elem                                      */
@@ -107,6 +116,8 @@ typedef struct {
   int32_t pcg_check_every;   /* PCG iterations between host checks           */
   double newton_rtol;        /* |Q(f - F)| <= newton_rtol |Q f|              */
   double pcg_forcing_max;    /* PCG stops at min(this, res_rel) relative     */
+  int32_t operator_form;     /* ep_operator (default EP_OPERATOR_ASSEMBLED); SPLIT
+                                requires local_prec = EP_FP64                 */
 } ep_options;
 
 typedef struct {
@@ -193,7 +204,8 @@ ep_status ep_internal_force(ep_ctx *ctx, double *F);
  * displacement u[n_dof] (updated in place on free dofs; Dirichlet values of
  * u are kept).  Computes the residual r = Q(f - F(u)); if |r| <= newton_rtol
  * |Q f| it sets info->converged = 1 and leaves u unchanged; otherwise it
- * assembles K_tangent, solves K du = r on the free dofs by Jacobi-PCG to
+ * assembles K_tangent (operator_form ASSEMBLED; SPLIT assembles nothing),
+ * solves K du = r on the free dofs by Jacobi-PCG to
  * the relative tolerance min(pcg_forcing_max, res_rel) and adds du to u.
  * Writes info (host).  Synchronises the stream.  EP_ENOTCONV if PCG hits
  * its limit (u is still updated with the last iterate). */
@@ -225,16 +237,28 @@ ep_status ep_get_position_map(ep_ctx *ctx, int32_t *pos);
  * (x is used as given, also on Dirichlet dofs). */
 ep_status ep_spmv(ep_ctx *ctx, const double *x, double *y);
 
+/* y = Q (K_elast x + sum over the elements with plastic points of
+ * B_e^T (D_tangent - D_elast) B_e x_e) for the last ep_constitutive: the
+ * split form of K_tangent x (eq. K-split) without assembly, equal to
+ * ep_spmv after ep_assemble_tangent up to rounding.  The element terms are
+ * summed per node in a fixed order (deterministic).  x[n_dof], y[n_dof]
+ * device; x is used as given, also on Dirichlet dofs.
+ * Returns EP_ESTATE if ep_constitutive has not run since setup or commit. */
+ep_status ep_apply_tangent(ep_ctx *ctx, const double *x, double *y);
+
 /* Solves Q K_tangent Q x = Q b by Jacobi-PCG from x = 0 to
- * |r| <= rtol |Q b|.  its and relres are host outputs.  Synchronises. */
+ * |r| <= rtol |Q b|, with the assembled K_tangent or, for operator_form
+ * SPLIT, with the split form of ep_apply_tangent.  its and relres are host
+ * outputs.  Synchronises. */
 ep_status ep_pcg(ep_ctx *ctx, const double *b, double *x, double rtol, int32_t max_it,
                  int32_t *its, double *relres);
 
 /* Per-kernel timing with HIP events recorded on the context's stream
  * around every launch of the named kernels.  ep_profile_read returns the
  * summed duration (ms) and the launch count of kernel id k (0 constitutive,
- * 1 compaction, 2 unused, 3 colour assembly, 4 force gather, 5 SpMV,
- * 6 PCG vector update) and resets it.  Synchronises. */
+ * 1 compaction, 2 split-form element terms and their node sum inside PCG,
+ * 3 colour assembly, 4 force gather, 5 SpMV, 6 PCG vector update) and
+ * resets it.  Synchronises. */
 ep_status ep_profile(ep_ctx *ctx, int32_t enable);
 ep_status ep_profile_read(ep_ctx *ctx, int32_t k, double *ms, int64_t *count);
 

@@ -16,7 +16,8 @@ EP_OK, EP_EINVAL, EP_ENOMEM, EP_EDEVICE, EP_ENOTCONV, EP_ESTATE = 0, -1, -2, -3,
 EP_P1, EP_P2, EP_Q1, EP_Q2 = 1, 2, 3, 4
 EP_VM, EP_DP = 1, 2
 EP_FP64, EP_FP32, EP_BF16 = 0, 1, 2
-PROF = dict(constitutive=0, compaction=1, assembly=3, force=4, spmv=5, pcg_vec=6)
+EP_OPERATOR_ASSEMBLED, EP_OPERATOR_SPLIT = 0, 1
+PROF = dict(constitutive=0, compaction=1, split=2, assembly=3, force=4, spmv=5, pcg_vec=6)
 
 ETYPE = {"P1_2D": (2, EP_P1), "Q1_2D": (2, EP_Q1), "Q2_2D": (2, EP_Q2), "P1_3D": (3, EP_P1),
          "P2_3D": (3, EP_P2), "Q1_3D": (3, EP_Q1), "Q2_3D": (3, EP_Q2)}
@@ -46,7 +47,8 @@ class ep_material(C.Structure):
 class ep_options(C.Structure):
     _fields_ = [("tangent_prec", C.c_int32), ("local_prec", C.c_int32),
                 ("pcg_max_it", C.c_int32), ("pcg_check_every", C.c_int32),
-                ("newton_rtol", C.c_double), ("pcg_forcing_max", C.c_double)]
+                ("newton_rtol", C.c_double), ("pcg_forcing_max", C.c_double),
+                ("operator_form", C.c_int32)]
 
 
 class ep_sizes(C.Structure):
@@ -101,6 +103,7 @@ def lib():
             "ep_get_csr": [P, I32, P, P, P],
             "ep_get_position_map": [P, P],
             "ep_spmv": [P, P, P],
+            "ep_apply_tangent": [P, P, P],
             "ep_pcg": [P, P, P, D, I32, P, P],
             "ep_profile": [P, I32],
             "ep_profile_read": [P, I32, P, P],
@@ -132,7 +135,8 @@ def lib():
 EXPORTED = ["ep_setup", "ep_destroy", "ep_last_error", "ep_set_stream", "ep_get_sizes",
             "ep_set_state", "ep_get_state", "ep_geometry", "ep_strain", "ep_constitutive",
             "ep_assemble_tangent", "ep_internal_force", "ep_newton_step", "ep_commit_step",
-            "ep_get_plastic", "ep_get_csr", "ep_get_position_map", "ep_spmv", "ep_pcg",
+            "ep_get_plastic", "ep_get_csr", "ep_get_position_map", "ep_spmv",
+            "ep_apply_tangent", "ep_pcg",
             "ep_profile", "ep_profile_read", "ep_mlp_create", "ep_mlp_destroy",
             "ep_mlp_last_error", "ep_mlp_set_params", "ep_mlp_get_params", "ep_mlp_forward",
             "ep_mlp_loss_grad", "ep_mlp_adam_step", "ep_mlp_datagen", "ep_mlp_features",
@@ -179,7 +183,7 @@ def ep_setup(mesh, free, material, options=None, quadrature=None, stream=None):
     m = ep_mesh(dim, et, mesh.n_nodes, mesh.n_elems, coord.ctypes.data, elem.ctypes.data,
                 free.ctypes.data)
     mat = _material(material)
-    opt = ep_options(EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2)
+    opt = ep_options(EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2, EP_OPERATOR_ASSEMBLED)
     for k, v in (options or {}).items():
         setattr(opt, k, v)
     q = None
@@ -269,6 +273,10 @@ def ep_get_position_map(ctx, pos):
 
 def ep_spmv(ctx, x, y):
     _check(ctx, lib().ep_spmv(ctx, _ptr(x), _ptr(y)))
+
+
+def ep_apply_tangent(ctx, x, y):
+    _check(ctx, lib().ep_apply_tangent(ctx, _ptr(x), _ptr(y)))
 
 
 def ep_pcg(ctx, b, x, rtol, max_it):
@@ -395,6 +403,11 @@ class Context:
     def spmv(self, x):
         y = self._empty((self.sizes["n_dof"],))
         ep_spmv(self.h, x, y)
+        return y
+
+    def apply_tangent(self, x):
+        y = self._empty((self.sizes["n_dof"],))
+        ep_apply_tangent(self.h, x, y)
         return y
 
     def pcg(self, b, rtol, max_it=100000):

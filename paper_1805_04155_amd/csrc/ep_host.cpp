@@ -219,7 +219,7 @@ hipError_t upload(T *d, const std::vector<T> &h, hipStream_t s) {
 void free_ctx(Ctx *c) {
   if (!c) return;
   void *ptrs[] = {c->coord, c->elem, c->freem, c->ref, c->bptr, c->bcol, c->bdiag, c->bpos,
-                  c->Ke, c->Ke32, c->Kt, c->epoch, c->n2e_ptr, c->fslot, c->ecol_perm,
+                  c->Ke, c->Ke32, c->Kt, c->epoch, c->n2e_ptr, c->fslot, c->slot_elem, c->Fp, c->ecol_perm,
                   c->d_colour_first_block, c->ep_s, c->beta_s, c->kappa_s, c->flag, c->desc,
                   c->Fe, c->em[0], c->em[1], c->plist, c->coff, c->ptotals, c->cmp_counts,
                   c->cmp_counts2, c->cmp_counts3, c->F, c->r, c->partials,
@@ -477,8 +477,14 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
         if (en[i] == en[j]) return fail("ep_setup: repeated node in an element", EP_EINVAL);
   }
 
-  ep_options opt{EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2};
+  ep_options opt{EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2, EP_OPERATOR_ASSEMBLED};
   if (opt_in) opt = *opt_in;
+  if (opt.operator_form != EP_OPERATOR_ASSEMBLED && opt.operator_form != EP_OPERATOR_SPLIT)
+    return fail("ep_setup: operator_form must be EP_OPERATOR_ASSEMBLED or EP_OPERATOR_SPLIT",
+                EP_EINVAL);
+  if (opt.operator_form == EP_OPERATOR_SPLIT && opt.local_prec != EP_FP64)
+    return fail("ep_setup: the split operator form applies its element terms in FP64 "
+                "(local_prec must be EP_FP64)", EP_EINVAL);
   if (opt.tangent_prec != EP_FP64 && opt.tangent_prec != EP_FP32)
     return fail("ep_setup: tangent_prec must be EP_FP64 or EP_FP32", EP_EINVAL);
   if (opt.local_prec != EP_FP64 && !(opt.local_prec == EP_FP32 || opt.local_prec == EP_BF16))
@@ -540,7 +546,8 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
 
   const int32_t *E = mesh->elem;
   // node -> (element, local node), ascending element
-  std::vector<int32_t> n2e_ptr(n_n + 1, 0), n2e(n_e * n_p), fslot(n_e * n_p);
+  std::vector<int32_t> n2e_ptr(n_n + 1, 0), n2e(n_e * n_p), fslot(n_e * n_p),
+      slot_elem(n_e * n_p);
   for (int64_t i = 0; i < n_e * n_p; ++i) n2e_ptr[E[i] + 1]++;
   for (int64_t m = 0; m < n_n; ++m) n2e_ptr[m + 1] += n2e_ptr[m];
   {
@@ -550,6 +557,7 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
         const int32_t k = fill[E[e * n_p + p]]++;
         n2e[k] = (int32_t)(e * n_p + p);
         fslot[e * n_p + p] = k;  // element force vectors are stored node by node
+        slot_elem[k] = (int32_t)e;
       }
   }
   // node adjacency -> node-block CSR
@@ -668,6 +676,8 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   SETUP_HIP(dalloc(&c->epoch, nnzb));
   SETUP_HIP(dalloc(&c->n2e_ptr, n_n + 1));
   SETUP_HIP(dalloc(&c->fslot, n_e * n_p));
+  SETUP_HIP(dalloc(&c->slot_elem, n_e * n_p));
+  SETUP_HIP(dalloc(&c->Fp, n_e * n_p * dim));
   SETUP_HIP(dalloc(&c->ecol_perm, (int64_t)perm.size()));
   SETUP_HIP(dalloc(&c->d_colour_first_block, n_col + 1));
   SETUP_HIP(dalloc(&c->ep_s, c->n_sc * n_int));
@@ -715,6 +725,7 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   SETUP_HIP(upload(c->bpos, bpos, s));
   SETUP_HIP(upload(c->n2e_ptr, n2e_ptr, s));
   SETUP_HIP(upload(c->fslot, fslot, s));
+  SETUP_HIP(upload(c->slot_elem, slot_elem, s));
   SETUP_HIP(upload(c->ecol_perm, perm, s));
   SETUP_HIP(upload(c->d_colour_first_block, c->colour_first_block, s));
   SETUP_HIP(hipMemsetAsync(c->ep_s, 0, sizeof(double) * c->n_sc * n_int, s));
@@ -868,8 +879,10 @@ ep_status ep_newton_step(ep_ctx *ctx, const double *f, double *u, ep_newton_info
     info->converged = 1;
     return EP_OK;
   }
-  st = do_assemble(c);
-  if (st) return st;
+  if (c->opt.operator_form == EP_OPERATOR_ASSEMBLED) {
+    st = do_assemble(c);
+    if (st) return st;
+  }
   // forcing term min(max, |r|/|f|), but no tighter than needed to reach the
   // Newton tolerance in this step
   const double rtol = std::min(c->opt.pcg_forcing_max,
@@ -942,7 +955,19 @@ ep_status ep_spmv(ep_ctx *ctx, const double *x, double *y) {
   CHECK_CTX(ctx);
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   if (!x || !y) return EP_EINVAL;
-  HIPC(launch_spmv(*c, x, y, false, c->partials));
+  HIPC(launch_spmv(*c, x, y));
+  return EP_OK;
+}
+
+ep_status ep_apply_tangent(ep_ctx *ctx, const double *x, double *y) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!x || !y) return EP_EINVAL;
+  if (!c->have_const) {
+    c->err = "ep_apply_tangent: no constitutive evaluation since setup or commit";
+    return EP_ESTATE;
+  }
+  HIPC(launch_apply_split(*c, x, y));
   return EP_OK;
 }
 
@@ -951,6 +976,10 @@ ep_status ep_pcg(ep_ctx *ctx, const double *b, double *x, double rtol, int32_t m
   CHECK_CTX(ctx);
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   if (!b || !x || max_it <= 0) return EP_EINVAL;
+  if (c->opt.operator_form == EP_OPERATOR_SPLIT && !c->have_const) {
+    c->err = "ep_pcg: the split operator needs a constitutive evaluation since setup or commit";
+    return EP_ESTATE;
+  }
   int it = 0;
   double rel = 0;
   const ep_status st = do_pcg(c, b, x, rtol, max_it, &it, &rel);
@@ -1040,8 +1069,10 @@ ep_status ep_warm_start(ep_ctx *ctx, ep_mlp *mlp, const double *f, const double 
   }
   info->n_plastic_pred = tot[1];
   // one solve with the predicted tangent and residual
-  st = do_assemble(c);
-  if (st) return st;
+  if (c->opt.operator_form == EP_OPERATOR_ASSEMBLED) {
+    st = do_assemble(c);
+    if (st) return st;
+  }
   int its = 0;
   double rel = 0;
   const ep_status ps = do_pcg(c, c->r, c->px, pcg_rtol, c->opt.pcg_max_it, &its, &rel);

@@ -36,7 +36,7 @@ constexpr int CMP_ITEMS = 8;
 constexpr int CMP_CHUNK = CMP_THREADS * CMP_ITEMS;
 
 // Kernel ids for ep_profile.
-enum ProfId { PROF_CONST = 0, PROF_COMPACT, PROF_UNUSED2, PROF_ASSEMBLE, PROF_FORCE, PROF_SPMV,
+enum ProfId { PROF_CONST = 0, PROF_COMPACT, PROF_SPLIT, PROF_ASSEMBLE, PROF_FORCE, PROF_SPMV,
               PROF_PCGVEC, PROF_COUNT };
 
 struct Ctx;
@@ -78,7 +78,10 @@ hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t
 hipError_t launch_csr_expand(Ctx &c, int which, int32_t *row_ptr, int32_t *col_idx, double *val);
 hipError_t launch_pos_expand(Ctx &c, int32_t *pos);
 hipError_t launch_diag_inv(Ctx &c);
-hipError_t launch_spmv(Ctx &c, const double *x, double *y, bool fused_p, double *partials);
+hipError_t launch_spmv(Ctx &c, const double *x, double *y);
+// split form of the tangent: y = Q K_elast x + Q sum over plastic elements of
+// Delta K_e x_e (element by element, no assembly)
+hipError_t launch_apply_split(Ctx &c, const double *x, double *y);
 hipError_t launch_pcg_init(Ctx &c, const double *b, double *x);
 hipError_t launch_pcg_iteration(Ctx &c, double *x);
 hipError_t launch_axpy_free(Ctx &c, const double *du, double *u);
@@ -184,6 +187,10 @@ struct Ctx {
 
   // vectors
   double *F = nullptr, *r = nullptr;
+  // split form: element vectors of the plastic part (node-ordered slots) and
+  // the element of each slot
+  double *Fp = nullptr;
+  int32_t *slot_elem = nullptr;
   double *partials = nullptr;  // reduction scratch
   int64_t partials_cap = 0;
   double *norms = nullptr;     // [8] device

@@ -25,6 +25,29 @@ namespace ep {
 
 static inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// PCG scalars on the device
+enum { SC_RZ = 0, SC_PQ, SC_RR, SC_TOL, SC_DONE, SC_ITS, SC_ALPHA, SC_BETA, SC_RR0, SC_N };
+
+// Per-thread part of a one-block reduction of n partial results:
+// sum over b = t, t + nt, t + 2 nt, ... < n of p[b * stride] in increasing
+// b.  The loads of 16 strides are issued together (the reduction kernels run
+// as a single block, so their time is load latency); the additions keep the
+// stride order.
+__device__ inline double strided_sum(const double *p, int n, int stride, int t, int nt) {
+  constexpr int U = 16;
+  double v = 0.0;
+  int b = t;
+  for (; b + (U - 1) * nt < n; b += U * nt) {
+    double x[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) x[j] = p[(int64_t)(b + j * nt) * stride];
+#pragma unroll
+    for (int j = 0; j < U; ++j) v += x[j];
+  }
+  for (; b < n; b += nt) v += p[(int64_t)b * stride];
+  return v;
+}
+
 // ----------------------------------------------------------------------------
 // Geometry: J_ij = sum_p dphi_p/dxi_i x_{p,j} (eq. Jacobian); grad_x = J^{-1}
 // grad_xi (eq. Jacobian2).  Returns det J.
@@ -1096,9 +1119,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double *partials, int nblk
   __shared__ double s[256];
   const int tid = threadIdx.x;
   for (int c = 0; c < width; ++c) {
-    double v = 0.0;
-    for (int b = tid; b < nblk; b += 256) v += partials[(int64_t)b * width + c];
-    s[tid] = v;
+    s[tid] = strided_sum(partials + c, nblk, width, tid, 256);
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
       if (tid < h) s[tid] += s[tid + h];
@@ -1107,6 +1128,287 @@ __global__ __launch_bounds__(256) void k_reduce(const double *partials, int nblk
     if (tid == 0) out[c] = s[0];
     __syncthreads();
   }
+}
+
+// ----------------------------------------------------------------------------
+// Split form of the tangent, K_t = K_elast + sum over the plastic elements of
+// Delta K_e (eq. K_elast-split), with the plastic part applied element by
+// element instead of assembled.  For every element of the work list that has
+// plastic points now, with M_q = w_q (D_q - C) from the tangent descriptor:
+//   MODE 0: v_e = sum_q B_q^T M_q B_q x_e   (x gathered at the element nodes)
+//   MODE 1: v_e = diagonal of Delta K_e     (Jacobi preconditioner)
+// Sums over the plastic points run in point order.  The element vectors go
+// to the node-ordered slots used by the internal force, and k_split_gather
+// adds them per node, so no two threads write one value.
+// ----------------------------------------------------------------------------
+struct KS {
+  const double *coord;
+  const int32_t *elem;
+  const double *ref;
+  int64_t n_n, n_int;
+  const double *desc;
+  const uint32_t *emask;   // plastic points of each element, current
+  const int32_t *list;     // work list of the last compaction
+  const int32_t *list_n;   // device: its length
+  const int32_t *fslot;
+  const double *x;         // MODE 0
+  double *Fp;              // element vectors in node-ordered slots
+  const double *sc;        // PCG scalars (skip once converged) or nullptr
+  double G, K;
+};
+
+template <int ETID, int MODE>
+__global__ __launch_bounds__(CT) void k_split_apply(KS a) {
+  using T = Et<ETID>;
+  constexpr int D = T::D, NP = T::NP, NQ = T::NQ;
+  constexpr int EPB = CT / NQ;
+  constexpr int NS = D == 3 ? 6 : 3;
+  constexpr int NDESC = D == 3 ? 10 : 7;
+  constexpr int NMS = NS * (NS + 1) / 2;           // packed symmetric M
+  constexpr int NA = MODE == 0 ? D * D : NMS + D * D;
+  __shared__ double s_ref[NQ * NP * D];
+  __shared__ double s_wq[NQ];
+  __shared__ double s_x[EPB * NP * D];
+  __shared__ double s_u[MODE == 0 ? EPB * NP * D : 1];
+  __shared__ double s_A[EPB * NQ * NA];
+  __shared__ int s_e[EPB];
+  __shared__ uint32_t s_m[EPB];
+  if (a.sc && a.sc[SC_DONE] != 0.0) return;
+  const int tid = threadIdx.x;
+  const int64_t n_list = *a.list_n;
+  const int64_t k0 = (int64_t)blockIdx.x * EPB;
+  if (k0 >= n_list) return;  // uniform
+  for (int t = tid; t < NQ * NP * D; t += CT) s_ref[t] = a.ref[t];
+  for (int t = tid; t < NQ; t += CT) s_wq[t] = a.ref[NQ * NP * D + t];
+  for (int t = tid; t < EPB; t += CT) {
+    const int64_t k = k0 + t;
+    const int e = k < n_list ? a.list[k] : -1;
+    const uint32_t m = e >= 0 ? a.emask[e] : 0u;
+    s_e[t] = m ? e : -1;
+    s_m[t] = m;
+  }
+  __syncthreads();
+  for (int t = tid; t < EPB * NP; t += CT) {
+    const int e = s_e[t / NP];
+    if (e < 0) continue;
+    const int64_t node = a.elem[(int64_t)e * NP + t % NP];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      s_x[t * D + d] = a.coord[d * a.n_n + node];
+      if constexpr (MODE == 0) s_u[t * D + d] = a.x[D * node + d];
+    }
+  }
+  __syncthreads();
+  // per (element, plastic point)
+  {
+    const int el = tid / NQ, q = tid - (tid / NQ) * NQ;
+    const int e = tid < EPB * NQ ? s_e[el] : -1;
+    if (e >= 0 && ((s_m[el] >> q) & 1u)) {
+      const double *xs = s_x + el * NP * D, *dr = s_ref + q * NP * D;
+      double Ji[D][D];
+      const double det = jac_inv<D, NP>(xs, dr, Ji);
+      const double w = fabs(det) * s_wq[q];
+      double dsc[NDESC];
+      const int64_t ip = (int64_t)e * NQ + q;
+#pragma unroll
+      for (int c = 0; c < NDESC; ++c) dsc[c] = a.desc[c * a.n_int + ip];
+      double *A = s_A + tid * NA;
+      if constexpr (MODE == 0) {
+        // engineering Voigt strain of x_e, then sigma' = M eps with
+        // M = w (alpha DEV + beta n n^T + gamma (n 1^T + 1 n^T) + delta 1 1^T)
+        // applied term by term (the matrix of tangent_matrix, not formed)
+        double ev[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) ev[i] = 0.0;
+        const double *us = s_u + el * NP * D;
+#pragma unroll 3
+        for (int p = 0; p < NP; ++p) {
+          double g[D];
+          grad<D>(Ji, dr + p * D, g);
+          const double *up = us + p * D;
+          if constexpr (D == 3) {
+            ev[0] += g[0] * up[0];
+            ev[1] += g[1] * up[1];
+            ev[2] += g[2] * up[2];
+            ev[3] += g[1] * up[0] + g[0] * up[1];
+            ev[4] += g[2] * up[1] + g[1] * up[2];
+            ev[5] += g[2] * up[0] + g[0] * up[2];
+          } else {
+            ev[0] += g[0] * up[0];
+            ev[1] += g[1] * up[1];
+            ev[2] += g[1] * up[0] + g[0] * up[1];
+          }
+        }
+        constexpr int NN = D == 3 ? 3 : 2;  // normal components
+        double tr = 0.0, ne = 0.0;
+#pragma unroll
+        for (int i = 0; i < NN; ++i) tr += ev[i];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) ne += dsc[i] * ev[i];
+        const double al = dsc[NS], be = dsc[NS + 1], ga = dsc[NS + 2], de = dsc[NS + 3];
+        double sg[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          const bool nI = i < NN;
+          const double dev = nI ? ev[i] - tr / 3.0 : 0.5 * ev[i];
+          sg[i] = w * (al * dev + be * dsc[i] * ne + ga * (dsc[i] * tr + (nI ? ne : 0.0)) +
+                       (nI ? de * tr : 0.0));
+        }
+        // B_p^T sigma' = S g_p with S the symmetric tensor of sigma', and
+        // g_p = J^{-1} dphi_p, so one D x D matrix A = S J^{-1} per point
+        double sm[D][D];
+        if constexpr (D == 3) {
+          sm[0][0] = sg[0]; sm[1][1] = sg[1]; sm[2][2] = sg[2];
+          sm[0][1] = sm[1][0] = sg[3];
+          sm[1][2] = sm[2][1] = sg[4];
+          sm[0][2] = sm[2][0] = sg[5];
+        } else {
+          sm[0][0] = sg[0]; sm[1][1] = sg[1];
+          sm[0][1] = sm[1][0] = sg[2];
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int j = 0; j < D; ++j) {
+            double v = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) v += sm[i][k] * Ji[k][j];
+            A[i * D + j] = v;
+          }
+      } else {
+        double M[NS * NS];
+        tangent_matrix<D>(dsc, false, a.G, a.K, w, M);
+        int o = 0;
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+#pragma unroll
+          for (int j = i; j < NS; ++j) A[o++] = M[i * NS + j];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int j = 0; j < D; ++j) A[NMS + i * D + j] = Ji[i][j];
+      }
+    }
+  }
+  __syncthreads();
+  // per (element, node): sum over the plastic points in order
+  for (int t = tid; t < EPB * NP; t += CT) {
+    const int el = t / NP, p = t - (t / NP) * NP;
+    const int e = s_e[el];
+    if (e < 0) continue;
+    const uint32_t mask = s_m[el];
+    double f[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) f[i] = 0.0;
+    for (int qq = 0; qq < NQ; ++qq) {
+      if (!((mask >> qq) & 1u)) continue;
+      const double *A = s_A + (el * NQ + qq) * NA;
+      const double *dr = s_ref + (qq * NP + p) * D;
+      if constexpr (MODE == 0) {
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int j = 0; j < D; ++j) f[i] += A[i * D + j] * dr[j];
+      } else {
+        double Ji[D][D];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int j = 0; j < D; ++j) Ji[i][j] = A[NMS + i * D + j];
+        double g[D];
+        grad<D>(Ji, dr, g);
+        double Mf[NS][NS];
+        {
+          int o = 0;
+#pragma unroll
+          for (int i = 0; i < NS; ++i)
+#pragma unroll
+            for (int j = i; j < NS; ++j) {
+              Mf[i][j] = A[o];
+              Mf[j][i] = A[o];
+              ++o;
+            }
+        }
+        // column of B for displacement component i of node p
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          double b[NS];
+#pragma unroll
+          for (int k = 0; k < NS; ++k) b[k] = 0.0;
+          if constexpr (D == 3) {
+            if (i == 0) { b[0] = g[0]; b[3] = g[1]; b[5] = g[2]; }
+            if (i == 1) { b[1] = g[1]; b[3] = g[0]; b[4] = g[2]; }
+            if (i == 2) { b[2] = g[2]; b[4] = g[1]; b[5] = g[0]; }
+          } else {
+            if (i == 0) { b[0] = g[0]; b[2] = g[1]; }
+            if (i == 1) { b[1] = g[1]; b[2] = g[0]; }
+          }
+          double v = 0.0;
+#pragma unroll
+          for (int k = 0; k < NS; ++k) {
+            double mb = 0.0;
+#pragma unroll
+            for (int l = 0; l < NS; ++l) mb += Mf[k][l] * b[l];
+            v += b[k] * mb;
+          }
+          f[i] += v;
+        }
+      }
+    }
+    const int64_t slot = a.fslot[(int64_t)e * NP + p];
+#pragma unroll
+    for (int i = 0; i < D; ++i) a.Fp[slot * D + i] = f[i];
+  }
+}
+
+// Node sums of the split-form element vectors (elements plastic now only).
+//   MODE 0: y += Q v; optional per-block partial p.y (fixed tree) for PCG.
+//   MODE 1: dinv = Q / (diag K_elast + v).
+template <int D, int MODE>
+__global__ __launch_bounds__(256) void k_split_gather(int64_t n_n, const int32_t *n2e_ptr,
+                                                      const int32_t *slot_elem,
+                                                      const uint32_t *emask, const double *Fp,
+                                                      const uint8_t *freem, double *y,
+                                                      const double *p, double *partials,
+                                                      const double *sc, const int32_t *bdiag,
+                                                      const double *Ke, double *dinv) {
+  __shared__ double s_a[256];
+  if (sc && sc[SC_DONE] != 0.0) return;
+  const int tid = threadIdx.x;
+  const int64_t m = (int64_t)blockIdx.x * 256 + tid;
+  double dot = 0.0;
+  if (m < n_n) {
+    double s[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) s[i] = 0.0;
+    const int k1 = n2e_ptr[m + 1];
+    for (int64_t k = n2e_ptr[m]; k < k1; ++k) {
+      if (emask[slot_elem[k]] == 0u) continue;
+#pragma unroll
+      for (int i = 0; i < D; ++i) s[i] += Fp[k * D + i];
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const int64_t r = D * m + i;
+      const bool fr = freem[r] != 0;
+      if constexpr (MODE == 0) {
+        const double yv = y[r] + (fr ? s[i] : 0.0);
+        y[r] = yv;
+        if (p) dot += p[r] * yv;
+      } else {
+        const double d = Ke[((int64_t)bdiag[m] * D + i) * D + i] + s[i];
+        dinv[r] = fr ? 1.0 / d : 0.0;
+      }
+    }
+  }
+  if (MODE != 0 || !partials) return;
+  s_a[tid] = dot;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) s_a[tid] += s_a[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) partials[blockIdx.x] = s_a[0];
 }
 
 // ----------------------------------------------------------------------------
@@ -1296,26 +1598,23 @@ __global__ void k_diag_inv(int64_t n_n, const int32_t *bdiag, const VT *Kt, cons
   dinv[r] = freem[r] ? 1.0 / d : 0.0;
 }
 
-// PCG scalars on the device
-enum { SC_RZ = 0, SC_PQ, SC_RR, SC_TOL, SC_DONE, SC_ITS, SC_ALPHA, SC_BETA, SC_RR0, SC_N };
 
 // y = Q K x with G lanes per node row: the lanes of a group read consecutive
 // node blocks of the row (coalesced), each lane accumulates the dim rows of
 // the block row, and a butterfly over the G lanes (fixed order, identical
-// in every lane) reduces them.  Optional fused direction update
-// x = z + beta*p_old (p_new written for the own rows) and partial x.y.
+// in every lane) reduces them.  Optional per-block partial x.y (fixed
+// order); with sc, nothing is done once PCG has converged.
 template <int D, typename VT, int G>
 __global__ __launch_bounds__(256) void k_spmv(int64_t n_n, const int32_t *bptr,
                                               const int32_t *bcol, const VT *val,
                                               const double *x, const uint8_t *freem, double *y,
-                                              double *partials, const double *z,
-                                              const double *pold, double *pnew, const double *sc) {
+                                              double *partials, const double *sc,
+                                              const double *x1, const double *x2) {
   __shared__ double s[256 / G];
   if (sc && sc[SC_DONE] != 0.0) return;
   const int tid = threadIdx.x;
   const int g = tid % G;
   const int64_t m = ((int64_t)blockIdx.x * 256 + tid) / G;
-  const double beta = sc ? sc[SC_BETA] : 0.0;
   double acc[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) acc[i] = 0.0;
@@ -1324,8 +1623,17 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n_n, const int32_t *bptr,
     for (int b = bptr[m] + g; b < b1; b += G) {
       const int64_t c = bcol[b];
       double xv[D];
+      if constexpr (D == 3) {
+        // read through x1 = x + 1 and x2 = x + 2 so that the compiler keeps
+        // three aligned 8-byte loads (merged, they become a 16-byte load at a
+        // 24-byte stride, misaligned for every other node: measurably slower)
+        xv[0] = x[3 * c];
+        xv[1] = x1[3 * c];
+        xv[2] = x2[3 * c];
+      } else {
 #pragma unroll
-      for (int j = 0; j < D; ++j) xv[j] = z ? z[D * c + j] + beta * pold[D * c + j] : x[D * c + j];
+        for (int j = 0; j < D; ++j) xv[j] = x[D * c + j];
+      }
       const VT *v = val + (int64_t)b * D * D;
 #pragma unroll
       for (int i = 0; i < D; ++i)
@@ -1344,16 +1652,10 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n_n, const int32_t *bptr,
       const int64_t r = D * m + i;
       const double yv = freem[r] ? acc[i] : 0.0;
       y[r] = yv;
-      double xr;
-      if (z) {
-        xr = z[r] + beta * pold[r];
-        pnew[r] = xr;
-      } else {
-        xr = x[r];
-      }
-      dot += xr * yv;
+      dot += x[r] * yv;
     }
   }
+  if (!partials) return;  // uniform
   // block sum of the group leaders' dots, fixed order
   if (g == 0) s[tid / G] = dot;
   __syncthreads();
@@ -1369,9 +1671,7 @@ __global__ __launch_bounds__(256) void k_pcg_alpha(const double *partials, int n
   __shared__ double s[256];
   if (sc[SC_DONE] != 0.0) return;
   const int tid = threadIdx.x;
-  double v = 0.0;
-  for (int b = tid; b < nblk; b += 256) v += partials[b];
-  s[tid] = v;
+  s[tid] = strided_sum(partials, nblk, 1, tid, 256);
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
     if (tid < h) s[tid] += s[tid + h];
@@ -1381,6 +1681,15 @@ __global__ __launch_bounds__(256) void k_pcg_alpha(const double *partials, int n
     sc[SC_PQ] = s[0];
     sc[SC_ALPHA] = sc[SC_RZ] / s[0];
   }
+}
+
+// new search direction p = z + beta p_old
+__global__ __launch_bounds__(256) void k_pcg_direction(int64_t n, const double *z,
+                                                       const double *pold, double *pnew,
+                                                       const double *sc) {
+  if (sc[SC_DONE] != 0.0) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) pnew[i] = z[i] + sc[SC_BETA] * pold[i];
 }
 
 // x += alpha p, r -= alpha q, z = dinv r, partial (r.z, r.r)
@@ -1425,13 +1734,8 @@ __global__ __launch_bounds__(256) void k_pcg_beta(const double *partials, int nb
   __shared__ double sa[256], sb[256];
   if (!init && sc[SC_DONE] != 0.0) return;
   const int tid = threadIdx.x;
-  double a = 0.0, b = 0.0;
-  for (int k = tid; k < nblk; k += 256) {
-    a += partials[2 * k];
-    b += partials[2 * k + 1];
-  }
-  sa[tid] = a;
-  sb[tid] = b;
+  sa[tid] = strided_sum(partials, nblk, 2, tid, 256);
+  sb[tid] = strided_sum(partials + 1, nblk, 2, tid, 256);
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
     if (tid < h) {
@@ -1749,7 +2053,63 @@ static hipError_t pos_et(Ctx &c, int32_t *pos) {
 }
 hipError_t launch_pos_expand(Ctx &c, int32_t *pos) { DISPATCH_ET(pos_et, c, pos) }
 
+template <int ETID>
+static hipError_t split_apply_et(Ctx &c, int mode, const double *x, const double *sc) {
+  constexpr int EPB = CT / Et<ETID>::NQ;
+  KS a{};
+  a.coord = c.coord;
+  a.elem = c.elem;
+  a.ref = c.ref;
+  a.n_n = c.n_n;
+  a.n_int = c.n_int;
+  a.desc = c.desc;
+  a.emask = c.em[c.em_cur];
+  a.list = c.plist;
+  a.list_n = c.coff + c.n_col;
+  a.fslot = c.fslot;
+  a.x = x;
+  a.Fp = c.Fp;
+  a.sc = sc;
+  a.G = c.mat.G;
+  a.K = c.mat.K;
+  // one block per EPB list entries; blocks past the list length (known on
+  // the device only) return at once
+  const int grid = ceil_div(c.n_e, EPB);
+  if (grid == 0) return hipSuccess;
+  if (mode == 0)
+    hipLaunchKernelGGL((k_split_apply<ETID, 0>), dim3(grid), dim3(CT), 0, c.stream, a);
+  else
+    hipLaunchKernelGGL((k_split_apply<ETID, 1>), dim3(grid), dim3(CT), 0, c.stream, a);
+  return hipGetLastError();
+}
+hipError_t launch_split_apply(Ctx &c, int mode, const double *x, const double *sc) {
+  DISPATCH_ET(split_apply_et, c, mode, x, sc)
+}
+
+hipError_t launch_split_gather(Ctx &c, int mode, double *y, const double *p, double *partials,
+                               const double *sc, int *nblk) {
+  const int grid = ceil_div(c.n_n, 256);
+  *nblk = grid;
+  if (grid == 0) return hipSuccess;
+#define SG(D, M)                                                                             \
+  hipLaunchKernelGGL((k_split_gather<D, M>), dim3(grid), dim3(256), 0, c.stream, c.n_n,      \
+                     c.n2e_ptr, c.slot_elem, c.em[c.em_cur], c.Fp, c.freem, y, p, partials, \
+                     sc, c.bdiag, c.Ke, c.dinv)
+  if (c.dim == 2) {
+    if (mode == 0) SG(2, 0); else SG(2, 1);
+  } else {
+    if (mode == 0) SG(3, 0); else SG(3, 1);
+  }
+#undef SG
+  return hipGetLastError();
+}
+
 hipError_t launch_diag_inv(Ctx &c) {
+  if (c.opt.operator_form == EP_OPERATOR_SPLIT) {
+    int nblk = 0;
+    RT(launch_split_apply(c, 1, nullptr, nullptr));
+    return launch_split_gather(c, 1, nullptr, nullptr, nullptr, nullptr, &nblk);
+  }
   const int grid = ceil_div(c.n_dof, 256);
   const bool f32 = c.opt.tangent_prec == EP_FP32;
 #define DG(D, VT)                                                                               \
@@ -1771,15 +2131,15 @@ static int spmv_lanes(const Ctx &c) {
 }
 
 template <int D, typename VT>
-static hipError_t spmv_launch(Ctx &c, const double *x, double *y, double *partials, const double *z,
-                              const double *pold, double *pnew, const double *sc, int *nblk) {
+static hipError_t spmv_launch(Ctx &c, const void *vals, const double *x, double *y,
+                              double *partials, const double *sc, int *nblk) {
   const int G = spmv_lanes(c);
   const int grid = ceil_div(c.n_n * G, 256);
   *nblk = grid;
   if (grid == 0) return hipSuccess;
 #define SPG(GG)                                                                              \
   hipLaunchKernelGGL((k_spmv<D, VT, GG>), dim3(grid), dim3(256), 0, c.stream, c.n_n, c.bptr, \
-                     c.bcol, (const VT *)c.Kt, x, c.freem, y, partials, z, pold, pnew, sc)
+                     c.bcol, (const VT *)vals, x, c.freem, y, partials, sc, x + 1, x + 2)
   switch (G) {
     case 4: SPG(4); break;
     case 8: SPG(8); break;
@@ -1790,19 +2150,29 @@ static hipError_t spmv_launch(Ctx &c, const double *x, double *y, double *partia
   return hipGetLastError();
 }
 
-static hipError_t spmv_any(Ctx &c, const double *x, double *y, double *partials, const double *z,
-                           const double *pold, double *pnew, const double *sc, int *nblk) {
+// values: the assembled tangent, or K_elast for the split form (stored in
+// the tangent's precision)
+static hipError_t spmv_any(Ctx &c, bool elastic, const double *x, double *y, double *partials,
+                           const double *sc, int *nblk) {
   const bool f32 = c.opt.tangent_prec == EP_FP32;
+  const void *vals = !elastic ? c.Kt : (f32 ? (const void *)c.Ke32 : (const void *)c.Ke);
   if (c.dim == 2)
-    return f32 ? spmv_launch<2, float>(c, x, y, partials, z, pold, pnew, sc, nblk)
-               : spmv_launch<2, double>(c, x, y, partials, z, pold, pnew, sc, nblk);
-  return f32 ? spmv_launch<3, float>(c, x, y, partials, z, pold, pnew, sc, nblk)
-             : spmv_launch<3, double>(c, x, y, partials, z, pold, pnew, sc, nblk);
+    return f32 ? spmv_launch<2, float>(c, vals, x, y, partials, sc, nblk)
+               : spmv_launch<2, double>(c, vals, x, y, partials, sc, nblk);
+  return f32 ? spmv_launch<3, float>(c, vals, x, y, partials, sc, nblk)
+             : spmv_launch<3, double>(c, vals, x, y, partials, sc, nblk);
 }
 
-hipError_t launch_spmv(Ctx &c, const double *x, double *y, bool, double *partials) {
+hipError_t launch_spmv(Ctx &c, const double *x, double *y) {
   int nblk = 0;
-  return spmv_any(c, x, y, partials, nullptr, nullptr, nullptr, nullptr, &nblk);
+  return spmv_any(c, false, x, y, nullptr, nullptr, &nblk);
+}
+
+hipError_t launch_apply_split(Ctx &c, const double *x, double *y) {
+  int nblk = 0;
+  RT(spmv_any(c, true, x, y, nullptr, nullptr, &nblk));
+  RT(launch_split_apply(c, 0, x, nullptr));
+  return launch_split_gather(c, 0, y, nullptr, nullptr, nullptr, &nblk);
 }
 
 hipError_t launch_pcg_init(Ctx &c, const double *b, double *x) {
@@ -1821,8 +2191,21 @@ hipError_t launch_pcg_iteration(Ctx &c, double *x) {
   double *pold = c.pp[c.pcur], *pnew = c.pp[1 - c.pcur];
   int tok = c.prof_begin(PROF_SPMV);
   int nblk = 0;
-  RT(spmv_any(c, nullptr, c.pq, c.partials, c.pz, pold, pnew, c.sc, &nblk));
+  const bool split = c.opt.operator_form == EP_OPERATOR_SPLIT;
+  // p = z + beta p_old as a vector pass, so that the product gathers one
+  // vector (beta = 0 at the first iteration)
+  hipLaunchKernelGGL(k_pcg_direction, dim3(grid), dim3(256), 0, c.stream, c.n_dof, c.pz, pold,
+                     pnew, c.sc);
+  RT(hipGetLastError());
+  RT(spmv_any(c, split, pnew, c.pq, split ? nullptr : c.partials, c.sc, &nblk));
   c.prof_end(tok);
+  if (split) {
+    // q = Q K_elast p + Q sum_e Delta K_e p_e, then the partial p.q
+    tok = c.prof_begin(PROF_SPLIT);
+    RT(launch_split_apply(c, 0, pnew, c.sc));
+    RT(launch_split_gather(c, 0, c.pq, pnew, c.partials, c.sc, &nblk));
+    c.prof_end(tok);
+  }
   hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(256), 0, c.stream, c.partials, nblk, c.sc);
   RT(hipGetLastError());
   tok = c.prof_begin(PROF_PCGVEC);

@@ -77,7 +77,7 @@ def _setup_error(mesh, free, mat, options=None):
 
 
 @pytest.mark.parametrize("what", ["node_range", "repeated_node", "nu", "yield", "local_prec",
-                                  "tangent_prec"])
+                                  "tangent_prec", "operator_form", "split_local_prec"])
 def test_setup_rejects_invalid_input(lib, what):
     """Invalid meshes, materials and options are refused at setup with
     EP_EINVAL and a message, before any device work (runs without a GPU)."""
@@ -101,6 +101,12 @@ def test_setup_rejects_invalid_input(lib, what):
         mat = W.Material("DP", E=1000.0, nu=0.3, eta=0.0, c=1.0)
     elif what == "local_prec":
         opts = {"local_prec": _ep.EP_BF16}   # matrix-core products: Q2-27 / P2 only
+    elif what == "operator_form":
+        opts = {"operator_form": 5}
+    elif what == "split_local_prec":
+        mesh = W.mesh_q2_3d(2, 2, 2, 1.0, 1.0, 1.0)
+        free = np.ones(mesh.n_dof, np.uint8)
+        opts = {"operator_form": _ep.EP_OPERATOR_SPLIT, "local_prec": _ep.EP_BF16}
     else:
         opts = {"tangent_prec": _ep.EP_BF16}
     err = _setup_error(mesh, free, mat, opts)

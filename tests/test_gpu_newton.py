@@ -226,3 +226,30 @@ def test_pcg_graph_replay_matches_eager():
                 assert np.array_equal(xg, xe), (mode, i)
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("name", ["p1_square", "q2_slope", "q2_block"])
+def test_split_operator_load_paths(name):
+    """Newton with the split operator (K_elast product plus the plastic
+    element terms applied element by element, nothing assembled) reaches the
+    oracle's solution on whole small load paths, with the iteration counts
+    of the assembled operator (same preconditioner, same operator up to
+    rounding)."""
+    if name == "p1_square":
+        wl, steps, tol = W.workload_p1_square(), range(10), 1e-9
+    elif name == "q2_slope":
+        wl, steps, tol = W.workload_q2_slope(16, 8, gamma_max=60.0, steps=6), range(6), 1e-8
+    else:
+        wl, steps, tol = W.workload_q2_block(4, 2, 2, q_max=4000.0, steps=4), range(4), 1e-8
+    uo, so = oracle_path(wl, steps, tol=1e-12 if name == "q2_slope" else 1e-13)
+    ctx_s, us, recs_s, _ = gpu_path(wl, steps, {"operator_form": _ep.EP_OPERATOR_SPLIT})
+    ctx_a, ua, recs_a, _ = gpu_path(wl, steps)
+    try:
+        assert so[-1][3] > 0
+        for k in steps:
+            assert _rel(us[k], uo[k]) < tol, k
+            assert recs_s[k]["n_plastic_ip"] == so[k][3], k
+            assert abs(recs_s[k]["newton_its"] - recs_a[k]["newton_its"]) <= 1, k
+    finally:
+        ctx_s.close()
+        ctx_a.close()

@@ -191,3 +191,60 @@ def test_determinism(case):
         outs.append((_np(val), _np(F)))
     assert np.array_equal(outs[0][0], outs[1][0])
     assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_split_apply_matches_oracle(case):
+    """The split form K_elast x + sum over plastic elements of Delta K_e x_e,
+    applied element by element without assembly (eq. K-split), equals the
+    oracle's assembled K_t x, for two different plastic sets.  The split
+    cancels up to |K_elast| |x|, which sets the scale."""
+    _, _, Ke = case.ctx.csr(0)
+    rp, ci = case.pattern
+    n = case.mesh.n_dof
+    Kabs = O.csr_to_scipy(rp, ci, np.abs(_np(Ke)), n)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(n)
+    for s in (1.0, 0.3):
+        u = case.u * s
+        case.ctx.constitutive(case.ctx.tensor(u), sig=False, D=False, flag=False)
+        y = _np(case.ctx.apply_tangent(case.ctx.tensor(x)))
+        ref = case.oracle_const(u)
+        assert np.count_nonzero(ref["flag"]) > 0
+        _, _, Kt = O.assemble(case.mesh, case.dphi, case.w, ref["D"], rp, ci)
+        yo = (O.csr_to_scipy(rp, ci, Kt, n) @ x) * case.free
+        close(y, yo, scale=(Kabs @ np.abs(x)).max())
+
+
+def test_split_apply_deterministic_and_equals_assembled(case):
+    """Two split applications are bit-identical; after an assembly the split
+    form and the assembled product agree to rounding."""
+    case.ctx.constitutive(case.du(), sig=False, D=False, flag=False)
+    rng = np.random.default_rng(8)
+    x = case.ctx.tensor(rng.standard_normal(case.mesh.n_dof))
+    y1 = _np(case.ctx.apply_tangent(x))
+    y2 = _np(case.ctx.apply_tangent(x))
+    assert np.array_equal(y1, y2)
+    case.ctx.assemble_tangent()
+    ya = _np(case.ctx.spmv(x))
+    _, _, Ke = case.ctx.csr(0)
+    rp, ci = case.pattern
+    Kabs = O.csr_to_scipy(rp, ci, np.abs(_np(Ke)), case.mesh.n_dof)
+    close(y1, ya, scale=(Kabs @ np.abs(_np(x))).max())
+
+
+def test_split_apply_elastic_state_is_k_elast():
+    """With no plastic point the split form is exactly the K_elast product."""
+    mesh, free, mat, u, _ = make_case("q1_3d_vm")
+    ctx = _ep.Context(mesh, free, mat)
+    try:
+        ctx.constitutive(ctx.tensor(np.zeros(mesh.n_dof)), sig=False, D=False, flag=False)
+        ip, el = ctx.plastic()
+        assert ip.numel() == 0
+        rng = np.random.default_rng(9)
+        x = rng.standard_normal(mesh.n_dof)
+        y = _np(ctx.apply_tangent(ctx.tensor(x)))
+        rp, ci, Ke = (_np(t) for t in ctx.csr(0))
+        ref = (O.csr_to_scipy(rp, ci, Ke, mesh.n_dof) @ x) * free
+        close(y, ref)
+    finally:
+        ctx.close()
