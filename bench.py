@@ -214,6 +214,7 @@ def newton_report(cube_n, n_samples, block):
     variants["plain_fp64"], u_ref = run_path(wl, st0, {}, keep_u=True)
     log(f"cube plain_fp64: {variants['plain_fp64']}")
     runs = [("fp32_tangent", {"tangent_prec": _ep.EP_FP32}, None, False),
+            ("split_operator", {"operator_form": _ep.EP_OPERATOR_SPLIT}, None, False),
             ("secant_predictor", {}, None, True),
             ("learned_fp32", {}, nets["fp32"], True),
             ("learned_bf16", {}, nets["bf16"], True),
@@ -247,6 +248,10 @@ def newton_report(cube_n, n_samples, block):
             r["du_rel_vs_plain"] = _du(uu, u_ref)
             variants[f"local_{lp}"] = r
             log(f"{name} local_{lp}: {r}")
+        r, uu = run_path(wl, st0, {"operator_form": _ep.EP_OPERATOR_SPLIT}, keep_u=True)
+        r["du_rel_vs_plain"] = _du(uu, u_ref)
+        variants["split_operator"] = r
+        log(f"{name} split_operator: {r}")
         base = variants["plain_fp64"]["seconds"]
         for v in variants.values():
             v["speedup_vs_plain"] = round(base / v["seconds"], 3)
