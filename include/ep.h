@@ -60,8 +60,10 @@ typedef enum {
  * tensor-product Lagrange with the paper's 20 hexahedron nodes first, then
  * the face centres (-xi3,+xi3,-xi2,+xi1,+xi2,-xi1) and the centre; the
  * 9-node quadrilateral lists vertices counter-clockwise, edge midpoints
- * (bottom, right, top, left) and the centre. */
-typedef enum { EP_P1 = 1, EP_P2 = 2, EP_Q1 = 3, EP_Q2 = 4 } ep_elem;
+ * (bottom, right, top, left) and the centre.  EP_Q2S: the serendipity
+ * elements of the Appendix's Q2 definition, the 8-node quadrilateral (3x3)
+ * and the 20-node hexahedron (3x3x3), nodes as the first 8 / 20 of EP_Q2. */
+typedef enum { EP_P1 = 1, EP_P2 = 2, EP_Q1 = 3, EP_Q2 = 4, EP_Q2S = 5 } ep_elem;
 
 /* EP_VM: von Mises with linear kinematic hardening (Section 2.2; a = 0 is
  *        perfect plasticity).  State: plastic strain, back stress.

@@ -35,7 +35,8 @@
 /* ------------------------------------------------------------------------ */
 enum {
   OR_P1_2D = 1, OR_Q1_2D = 2, OR_Q2_2D = 3,
-  OR_P1_3D = 4, OR_P2_3D = 5, OR_Q1_3D = 6, OR_Q2_3D = 7
+  OR_P1_3D = 4, OR_P2_3D = 5, OR_Q1_3D = 6, OR_Q2_3D = 7,
+  OR_Q2S_2D = 8, OR_Q2S_3D = 9  /* serendipity: 8-node quadrilateral, 20-node hexahedron */
 };
 
 int or_elem_info(int et, int *dim, int *n_p, int *n_q) {
@@ -47,6 +48,8 @@ int or_elem_info(int et, int *dim, int *n_p, int *n_q) {
     case OR_P2_3D: *dim = 3; *n_p = 10; *n_q = 11; return 0;
     case OR_Q1_3D: *dim = 3; *n_p = 8;  *n_q = 8;  return 0;
     case OR_Q2_3D: *dim = 3; *n_p = 27; *n_q = 27; return 0;
+    case OR_Q2S_2D: *dim = 2; *n_p = 8;  *n_q = 9;  return 0;
+    case OR_Q2S_3D: *dim = 3; *n_p = 20; *n_q = 27; return 0;
   }
   return -1;
 }
@@ -134,6 +137,64 @@ void or_basis(int et, const double *xi, double *phi, double *dphi) {
         dphi[3 * p + 0] = 0.125 * a * fb * fc;
         dphi[3 * p + 1] = 0.125 * fa * b * fc;
         dphi[3 * p + 2] = 0.125 * fa * fb * c;
+      }
+      return;
+    case OR_Q2S_2D:
+      /* 8-node serendipity quadrilateral (the 2D counterpart of the
+         Appendix's 20-node element): vertices 1/4 (1+a x)(1+b y)(a x+b y-1),
+         edge midpoints 1/2 (1-x^2)(1+b y) or 1/2 (1+a x)(1-y^2) */
+      for (p = 0; p < 8; ++p) {
+        int a = QUAD9[p][0], b = QUAD9[p][1];
+        double x = xi[0], y = xi[1];
+        if (a != 0 && b != 0) {
+          double fa = 1 + a * x, fb = 1 + b * y, t = a * x + b * y - 1;
+          phi[p] = 0.25 * fa * fb * t;
+          dphi[2 * p + 0] = 0.25 * (a * fb * t + fa * fb * a);
+          dphi[2 * p + 1] = 0.25 * (fa * b * t + fa * fb * b);
+        } else if (a == 0) {
+          phi[p] = 0.5 * (1 - x * x) * (1 + b * y);
+          dphi[2 * p + 0] = 0.5 * (-2 * x) * (1 + b * y);
+          dphi[2 * p + 1] = 0.5 * (1 - x * x) * b;
+        } else {
+          phi[p] = 0.5 * (1 + a * x) * (1 - y * y);
+          dphi[2 * p + 0] = 0.5 * a * (1 - y * y);
+          dphi[2 * p + 1] = 0.5 * (1 + a * x) * (-2 * y);
+        }
+      }
+      return;
+    case OR_Q2S_3D:
+      /* 20-node serendipity hexahedron of the Appendix: vertices
+         1/8 (1+a x1)(1+b x2)(1+c x3)(a x1+b x2+c x3-2), edge midpoints
+         1/4 (1-x_k^2) times the two linear factors of the other axes */
+      for (p = 0; p < 20; ++p) {
+        int a = HEX27[p][0], b = HEX27[p][1], c = HEX27[p][2];
+        double x = xi[0], y = xi[1], z = xi[2];
+        if (a != 0 && b != 0 && c != 0) {
+          double fa = 1 + a * x, fb = 1 + b * y, fc = 1 + c * z;
+          double t = a * x + b * y + c * z - 2;
+          phi[p] = 0.125 * fa * fb * fc * t;
+          dphi[3 * p + 0] = 0.125 * (a * fb * fc * t + fa * fb * fc * a);
+          dphi[3 * p + 1] = 0.125 * (fa * b * fc * t + fa * fb * fc * b);
+          dphi[3 * p + 2] = 0.125 * (fa * fb * c * t + fa * fb * fc * c);
+        } else if (a == 0) {
+          double fb = 1 + b * y, fc = 1 + c * z;
+          phi[p] = 0.25 * (1 - x * x) * fb * fc;
+          dphi[3 * p + 0] = 0.25 * (-2 * x) * fb * fc;
+          dphi[3 * p + 1] = 0.25 * (1 - x * x) * b * fc;
+          dphi[3 * p + 2] = 0.25 * (1 - x * x) * fb * c;
+        } else if (b == 0) {
+          double fa = 1 + a * x, fc = 1 + c * z;
+          phi[p] = 0.25 * fa * (1 - y * y) * fc;
+          dphi[3 * p + 0] = 0.25 * a * (1 - y * y) * fc;
+          dphi[3 * p + 1] = 0.25 * fa * (-2 * y) * fc;
+          dphi[3 * p + 2] = 0.25 * fa * (1 - y * y) * c;
+        } else {
+          double fa = 1 + a * x, fb = 1 + b * y;
+          phi[p] = 0.25 * fa * fb * (1 - z * z);
+          dphi[3 * p + 0] = 0.25 * a * fb * (1 - z * z);
+          dphi[3 * p + 1] = 0.25 * fa * b * (1 - z * z);
+          dphi[3 * p + 2] = 0.25 * fa * fb * (-2 * z);
+        }
       }
       return;
     case OR_Q2_3D:

@@ -19,7 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ep_oracle.c")
 LIB = os.path.join(HERE, "libep_oracle.so")
 
-ETYPE = {"P1_2D": 1, "Q1_2D": 2, "Q2_2D": 3, "P1_3D": 4, "P2_3D": 5, "Q1_3D": 6, "Q2_3D": 7}
+ETYPE = {"P1_2D": 1, "Q1_2D": 2, "Q2_2D": 3, "P1_3D": 4, "P2_3D": 5, "Q1_3D": 6, "Q2_3D": 7,
+         "Q2S_2D": 8, "Q2S_3D": 9}
 PLANE = [0, 1, 3]
 
 

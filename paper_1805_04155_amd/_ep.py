@@ -13,14 +13,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libep.so")
 
 EP_OK, EP_EINVAL, EP_ENOMEM, EP_EDEVICE, EP_ENOTCONV, EP_ESTATE = 0, -1, -2, -3, -4, -5
-EP_P1, EP_P2, EP_Q1, EP_Q2 = 1, 2, 3, 4
+EP_P1, EP_P2, EP_Q1, EP_Q2, EP_Q2S = 1, 2, 3, 4, 5
 EP_VM, EP_DP = 1, 2
 EP_FP64, EP_FP32, EP_BF16 = 0, 1, 2
 EP_OPERATOR_ASSEMBLED, EP_OPERATOR_SPLIT = 0, 1
 PROF = dict(constitutive=0, compaction=1, split=2, assembly=3, force=4, spmv=5, pcg_vec=6)
 
 ETYPE = {"P1_2D": (2, EP_P1), "Q1_2D": (2, EP_Q1), "Q2_2D": (2, EP_Q2), "P1_3D": (3, EP_P1),
-         "P2_3D": (3, EP_P2), "Q1_3D": (3, EP_Q1), "Q2_3D": (3, EP_Q2)}
+         "P2_3D": (3, EP_P2), "Q1_3D": (3, EP_Q1), "Q2_3D": (3, EP_Q2), "Q2S_2D": (2, EP_Q2S),
+         "Q2S_3D": (3, EP_Q2S)}
 
 
 class EpError(RuntimeError):

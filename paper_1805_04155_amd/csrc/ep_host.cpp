@@ -83,6 +83,8 @@ bool elem_def(int dim, int type, ElemDef &d) {
   else if (dim == 3 && type == EP_P2) d = {ET_P2_3D, 3, 10, 11};
   else if (dim == 3 && type == EP_Q1) d = {ET_Q1_3D, 3, 8, 8};
   else if (dim == 3 && type == EP_Q2) d = {ET_Q2_3D, 3, 27, 27};
+  else if (dim == 2 && type == EP_Q2S) d = {ET_Q2S_2D, 2, 8, 9};
+  else if (dim == 3 && type == EP_Q2S) d = {ET_Q2S_3D, 3, 20, 27};
   else return false;
   return true;
 }
@@ -134,6 +136,64 @@ void ref_gradients(int id, const double *xi, double *g) {
       for (int k = 0; k < 6; ++k) {
         const int a = kTetEdge[k][0], b = kTetEdge[k][1];
         for (int i = 0; i < 3; ++i) g[3 * (4 + k) + i] = 4.0 * (dl[a][i] * lam[b] + lam[a] * dl[b][i]);
+      }
+      return;
+    }
+    case ET_Q2S_2D:
+    case ET_Q2S_3D: {
+      // Serendipity element (Appendix): an edge-midpoint function is the
+      // quadratic bubble 1 - t^2 along its edge times the linear factors
+      // (1 + s x) of the other axes; a vertex function is the multilinear
+      // vertex function minus half of the three (2D: two) edge functions
+      // of the edges meeting at the vertex.
+      const int dim = id == ET_Q2S_2D ? 2 : 3;
+      const int n_p = dim == 2 ? 8 : 20, n_v = dim == 2 ? 4 : 8;
+      auto node = [&](int p, int a) {
+        return dim == 2 ? kQuad9[p][a] : kHex27[p][a];
+      };
+      // value and gradient of the edge function of node p
+      auto edge = [&](int p, double &v, double *dv) {
+        double f[3], df[3];
+        for (int a = 0; a < dim; ++a) {
+          const int s = node(p, a);
+          if (s == 0) { f[a] = 1.0 - xi[a] * xi[a]; df[a] = -2.0 * xi[a]; }
+          else { f[a] = 0.5 * (1.0 + s * xi[a]); df[a] = 0.5 * s; }
+        }
+        v = 1.0;
+        for (int a = 0; a < dim; ++a) v *= f[a];
+        for (int i = 0; i < dim; ++i) {
+          double t = df[i];
+          for (int a = 0; a < dim; ++a)
+            if (a != i) t *= f[a];
+          dv[i] = t;
+        }
+      };
+      for (int p = n_v; p < n_p; ++p) {
+        double v, dv[3];
+        edge(p, v, dv);
+        for (int i = 0; i < dim; ++i) g[p * dim + i] = dv[i];
+      }
+      for (int p = 0; p < n_v; ++p) {
+        double f[3], df[3];
+        for (int a = 0; a < dim; ++a) {
+          f[a] = 0.5 * (1.0 + node(p, a) * xi[a]);
+          df[a] = 0.5 * node(p, a);
+        }
+        for (int i = 0; i < dim; ++i) {
+          double t = df[i];
+          for (int a = 0; a < dim; ++a)
+            if (a != i) t *= f[a];
+          g[p * dim + i] = t;
+        }
+        // edges at vertex p: the midpoints that differ from it in one axis
+        for (int q = n_v; q < n_p; ++q) {
+          int diff = 0;
+          for (int a = 0; a < dim; ++a) diff += node(q, a) != node(p, a) ? 1 : 0;
+          if (diff != 1) continue;
+          double v, dv[3];
+          edge(q, v, dv);
+          for (int i = 0; i < dim; ++i) g[p * dim + i] -= 0.5 * dv[i];
+        }
       }
       return;
     }
@@ -489,9 +549,10 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
     return fail("ep_setup: tangent_prec must be EP_FP64 or EP_FP32", EP_EINVAL);
   if (opt.local_prec != EP_FP64 && !(opt.local_prec == EP_FP32 || opt.local_prec == EP_BF16))
     return fail("ep_setup: local_prec must be EP_FP64, EP_FP32 or EP_BF16", EP_EINVAL);
-  if (opt.local_prec != EP_FP64 && !(ed.id == ET_Q2_3D || ed.id == ET_P2_3D))
+  if (opt.local_prec != EP_FP64 &&
+      !(ed.id == ET_Q2_3D || ed.id == ET_Q2S_3D || ed.id == ET_P2_3D))
     return fail("ep_setup: matrix-core local products (EP_FP32 / EP_BF16) are built for the "
-                "27-node hexahedron and the 10-node tetrahedron only", EP_EINVAL);
+                "27- and 20-node hexahedra and the 10-node tetrahedron only", EP_EINVAL);
   if (opt.pcg_max_it <= 0) opt.pcg_max_it = 20000;
   if (opt.pcg_check_every <= 0) opt.pcg_check_every = 50;
 

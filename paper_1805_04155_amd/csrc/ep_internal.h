@@ -13,7 +13,8 @@
 namespace ep {
 
 // Element kinds the kernels are specialised on.
-enum EtId { ET_P1_2D = 0, ET_Q1_2D, ET_Q2_2D, ET_P1_3D, ET_P2_3D, ET_Q1_3D, ET_Q2_3D, ET_COUNT };
+enum EtId { ET_P1_2D = 0, ET_Q1_2D, ET_Q2_2D, ET_P1_3D, ET_P2_3D, ET_Q1_3D, ET_Q2_3D, ET_Q2S_2D,
+            ET_Q2S_3D, ET_COUNT };
 
 template <int ID> struct Et;
 template <> struct Et<ET_P1_2D> { static constexpr int D = 2, NP = 3, NQ = 1; };
@@ -23,6 +24,8 @@ template <> struct Et<ET_P1_3D> { static constexpr int D = 3, NP = 4, NQ = 1; };
 template <> struct Et<ET_P2_3D> { static constexpr int D = 3, NP = 10, NQ = 11; };
 template <> struct Et<ET_Q1_3D> { static constexpr int D = 3, NP = 8, NQ = 8; };
 template <> struct Et<ET_Q2_3D> { static constexpr int D = 3, NP = 27, NQ = 27; };
+template <> struct Et<ET_Q2S_2D> { static constexpr int D = 2, NP = 8, NQ = 9; };
+template <> struct Et<ET_Q2S_3D> { static constexpr int D = 3, NP = 20, NQ = 27; };
 
 // Material constants used on the device.
 struct MatC {

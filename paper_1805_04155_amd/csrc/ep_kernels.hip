@@ -436,7 +436,8 @@ struct AsmCfg {
   // scatter it row by row in column order: on structured meshes an element's
   // blocks in a row form runs of consecutive nodes, so consecutive lanes write
   // consecutive blocks (simplices have no such runs)
-  static constexpr bool SORTED = ETID == ET_Q1_2D || ETID == ET_Q2_2D || ETID == ET_Q1_3D;
+  static constexpr bool SORTED =
+      ETID == ET_Q1_2D || ETID == ET_Q2_2D || ETID == ET_Q2S_2D || ETID == ET_Q1_3D;
   static constexpr int NSLOT = SORTED ? (T::NP * T::NP + BS - 1) / BS : 1;
 };
 
@@ -1877,6 +1878,8 @@ static hipError_t constitutive_et(Ctx &c, const ConstArgs &ca) {
     case ET_P2_3D: return FN<ET_P2_3D>(__VA_ARGS__);           \
     case ET_Q1_3D: return FN<ET_Q1_3D>(__VA_ARGS__);           \
     case ET_Q2_3D: return FN<ET_Q2_3D>(__VA_ARGS__);           \
+    case ET_Q2S_2D: return FN<ET_Q2S_2D>(__VA_ARGS__);         \
+    case ET_Q2S_3D: return FN<ET_Q2S_3D>(__VA_ARGS__);         \
   }                                                            \
   return hipErrorInvalidValue;
 
@@ -1987,7 +1990,7 @@ static hipError_t colour_et(Ctx &c, int colour, int epoch) {
   const int gcap = 48 * c.n_cu;
   const int gpipe = grid < gcap ? grid : gcap;
   const bool f32 = c.opt.tangent_prec == EP_FP32;
-  if constexpr (ETID == ET_Q2_3D || ETID == ET_P2_3D) {
+  if constexpr (ETID == ET_Q2_3D || ETID == ET_Q2S_3D || ETID == ET_P2_3D) {
     if (c.opt.local_prec == EP_BF16 || c.opt.local_prec == EP_FP32) {
       const bool bf = c.opt.local_prec == EP_BF16;
 #define MF(VT, BF) \

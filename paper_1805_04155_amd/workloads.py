@@ -61,6 +61,8 @@ ELEMENT_INFO = {
     "P2_3D": (3, 10, 11),
     "Q1_3D": (3, 8, 8),
     "Q2_3D": (3, 27, 27),
+    "Q2S_2D": (2, 8, 9),     # serendipity (the paper's Q2): 3x3 Gauss points
+    "Q2S_3D": (3, 20, 27),   # serendipity 20-node hexahedron: 3x3x3
 }
 
 
@@ -170,6 +172,28 @@ def mesh_q2_3d(nx, ny, nz, lx, ly, lz) -> Mesh:
     return Mesh("Q2_3D", coord, np.stack(cols, axis=1))
 
 
+def _compact(etype, coord, elem):
+    """Drop the nodes no element uses; the kept nodes keep their order."""
+    used = np.zeros(coord.shape[1], dtype=bool)
+    used[elem.ravel()] = True
+    new_id = np.cumsum(used) - 1
+    return Mesh(etype, coord[:, used], new_id[elem].astype(np.int32))
+
+
+def mesh_q2s_2d(nx, ny, lx, ly) -> Mesh:
+    """8-node serendipity quadrilaterals: the 9-node mesh without the
+    element centres."""
+    m = mesh_q2_2d(nx, ny, lx, ly)
+    return _compact("Q2S_2D", m.coord, m.elem[:, :8])
+
+
+def mesh_q2s_3d(nx, ny, nz, lx, ly, lz) -> Mesh:
+    """20-node serendipity hexahedra (the paper's Q2 element, Appendix): the
+    27-node mesh without the face and element centres."""
+    m = mesh_q2_3d(nx, ny, nz, lx, ly, lz)
+    return _compact("Q2S_3D", m.coord, m.elem[:, :20])
+
+
 def _kuhn_tets():
     """Six tetrahedra of the unit cube along the diagonal v000 -> v111, each
     positively oriented (vertex lists in unit-cube corner coordinates)."""
@@ -210,6 +234,40 @@ def mesh_tet_3d(nx, ny, nz, lx, ly, lz, order) -> Mesh:
     n_p = 10 if order == 2 else 4
     elem = np.stack(out, axis=1).reshape(-1, n_p)
     return Mesh("P2_3D" if order == 2 else "P1_3D", coord, elem)
+
+
+# --------------------------------------------------------------------------
+# The paper's L-shaped domain (Section 8.1, the figure of the elastic
+# problem): [0,10]^2 without [0,5)x[0,5), extruded over [0,1] in 3D.  Level l
+# has element size h = 2^-l (10*2^l elements per box side in plane, 2^l
+# through the thickness), which reproduces the matrix sizes of the paper's
+# Tables 1 and 2.
+# --------------------------------------------------------------------------
+
+LSHAPE_GENERATORS = {
+    "P1_2D": lambda n, m: mesh_p1_2d(n, n, 10.0, 10.0),
+    "Q1_2D": lambda n, m: mesh_q1_2d(n, n, 10.0, 10.0),
+    "Q2_2D": lambda n, m: mesh_q2_2d(n, n, 10.0, 10.0),
+    "Q2S_2D": lambda n, m: mesh_q2s_2d(n, n, 10.0, 10.0),
+    "P1_3D": lambda n, m: mesh_tet_3d(n, n, m, 10.0, 10.0, 1.0, order=1),
+    "P2_3D": lambda n, m: mesh_tet_3d(n, n, m, 10.0, 10.0, 1.0, order=2),
+    "Q1_3D": lambda n, m: mesh_q1_3d(n, n, m, 10.0, 10.0, 1.0),
+    "Q2_3D": lambda n, m: mesh_q2_3d(n, n, m, 10.0, 10.0, 1.0),
+    "Q2S_3D": lambda n, m: mesh_q2s_3d(n, n, m, 10.0, 10.0, 1.0),
+}
+
+
+def mesh_lshape(etype, level) -> Mesh:
+    """Structured mesh of the L-shaped domain: the box mesh with the
+    elements whose vertex centroid lies in [0,5)x[0,5) removed, unused nodes
+    dropped."""
+    n, m = 10 * 2 ** level, 2 ** level
+    box = LSHAPE_GENERATORS[etype](n, m)
+    nv = {"P1_2D": 3, "P1_3D": 4, "P2_3D": 4, "Q1_2D": 4, "Q2_2D": 4,
+          "Q2S_2D": 4, "Q1_3D": 8, "Q2_3D": 8, "Q2S_3D": 8}[etype]
+    cen = box.coord[:, box.elem[:, :nv]].mean(axis=2)  # (dim, n_e)
+    keep = ~((cen[0] < 5.0) & (cen[1] < 5.0))
+    return _compact(etype, box.coord, box.elem[keep])
 
 
 # --------------------------------------------------------------------------

@@ -18,6 +18,8 @@ CASES = {
     "q1_3d_vm": (lambda: W.mesh_q1_3d(11, 9, 8, 1.1, 0.9, 0.8), W.VM_MATERIAL),
     "q1_3d_dp": (lambda: W.mesh_q1_3d(9, 7, 6, 0.9, 0.7, 0.6), DP3),
     "q2_3d_dph": (lambda: W.mesh_q2_3d(5, 4, 3, 1.0, 0.8, 0.6), DPH),
+    "q2s_2d_vm": (lambda: W.mesh_q2s_2d(23, 17, 3.0, 2.0), W.VM_MATERIAL),
+    "q2s_3d_dph": (lambda: W.mesh_q2s_3d(6, 4, 3, 1.0, 0.7, 0.5), DPH),
 }
 
 

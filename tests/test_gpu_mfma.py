@@ -26,7 +26,7 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("case", ["q2_3d_dph", "p2_3d_dph"])
+@pytest.mark.parametrize("case", ["q2_3d_dph", "q2s_3d_dph", "p2_3d_dph"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16_f32values"])
 def test_incremental_tangent_matrix_cores(case, prec):
     """bf16_f32values: BF16 local products with K stored in FP32."""

@@ -12,10 +12,10 @@ from paper_1805_04155_amd import workloads as W
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 REF_VOLUME = {"P1_2D": 0.5, "Q1_2D": 4.0, "Q2_2D": 4.0, "P1_3D": 1 / 6,
-              "P2_3D": 1 / 6, "Q1_3D": 8.0, "Q2_3D": 8.0}
+              "P2_3D": 1 / 6, "Q1_3D": 8.0, "Q2_3D": 8.0, "Q2S_2D": 4.0, "Q2S_3D": 8.0}
 # polynomial degree integrated exactly by each rule
 EXACT_DEGREE = {"P1_2D": 1, "Q1_2D": 3, "Q2_2D": 5, "P1_3D": 1, "P2_3D": 4,
-                "Q1_3D": 3, "Q2_3D": 5}
+                "Q1_3D": 3, "Q2_3D": 5, "Q2S_2D": 5, "Q2S_3D": 5}
 
 
 def _exact_monomial(etype, powers):
@@ -68,6 +68,12 @@ def _golden_nodes():
 
 
 def _node_coords(etype):
+    if etype == "Q2S_3D":
+        g = _golden_nodes()
+        return np.array([g["Q1_3D"][k] for k in range(1, 9)] +
+                        [g["Q2_3D"][k] for k in range(9, 21)])
+    if etype == "Q2S_2D":
+        return W.QUAD9_LOCAL[:8].astype(float)
     if etype == "Q2_3D":
         return W.HEX27_LOCAL.astype(float)
     if etype == "Q1_3D":
@@ -135,6 +141,60 @@ def test_basis_reproduces_polynomials(etype):
         assert abs(phi @ vals - f(x)) < 1e-13
 
 
+@pytest.mark.parametrize("etype", ["Q2S_2D", "Q2S_3D"])
+def test_serendipity_space(etype):
+    """The serendipity basis reproduces every complete quadratic and the
+    cubic terms of its space (x^2 y, x y^2; in 3D also x y z and the
+    x_i^2 x_j products), but not the biquadratic x^2 y^2 (that is the
+    9- / 27-node space): interpolation at the nodes is exact for the first,
+    not for the second."""
+    nodes = _node_coords(etype)
+    dim = nodes.shape[1]
+    rng = np.random.default_rng(6)
+    c = rng.standard_normal(20)
+    if dim == 2:
+        def f(x):
+            a, b = x
+            return (c[0] + c[1] * a + c[2] * b + c[3] * a * a + c[4] * a * b + c[5] * b * b
+                    + c[6] * a * a * b + c[7] * a * b * b)
+
+        def g(x):
+            return x[0] ** 2 * x[1] ** 2
+    else:
+        def f(x):
+            a, b, z = x
+            return (c[0] + c[1] * a + c[2] * b + c[3] * z + c[4] * a * a + c[5] * b * b
+                    + c[6] * z * z + c[7] * a * b + c[8] * b * z + c[9] * a * z + c[10] * a * b * z
+                    + c[11] * a * a * b + c[12] * a * a * z + c[13] * b * b * a
+                    + c[14] * b * b * z + c[15] * z * z * a + c[16] * z * z * b)
+
+        def g(x):
+            return x[0] ** 2 * x[1] ** 2
+    vals = np.array([f(n) for n in nodes])
+    gv = np.array([g(n) for n in nodes])
+    miss = 0.0
+    for _ in range(5):
+        x = rng.uniform(-1, 1, dim)
+        phi, _ = O.basis(etype, x)
+        assert abs(phi @ vals - f(x)) < 1e-13
+        miss = max(miss, abs(phi @ gv - g(x)))
+    assert miss > 1e-3
+
+
+def test_serendipity_face_integrals():
+    """Integrals of the 8-node serendipity functions over the reference
+    square: -1/3 for a vertex, 4/3 for an edge midpoint (closed form); the
+    consistent load of a uniform traction on such a face is -A/12 per
+    vertex and A/3 per midpoint."""
+    xi, w = O.quadrature("Q2S_2D")
+    tot = np.zeros(8)
+    for q in range(len(w)):
+        phi, _ = O.basis("Q2S_2D", xi[q])
+        tot += w[q] * phi
+    assert np.max(np.abs(tot[:4] + 1 / 3)) < 1e-14
+    assert np.max(np.abs(tot[4:] - 4 / 3)) < 1e-14
+
+
 def test_p2_reproduces_quadratics():
     nodes = _node_coords("P2_3D")
 
@@ -157,6 +217,8 @@ MESHES = {
     "P2_3D": lambda: W.mesh_tet_3d(2, 2, 1, 1.0, 1.0, 0.5, order=2),
     "Q1_3D": lambda: W.mesh_q1_3d(2, 2, 1, 1.0, 1.0, 0.5),
     "Q2_3D": lambda: W.mesh_q2_3d(2, 2, 1, 1.0, 1.0, 0.5),
+    "Q2S_2D": lambda: W.mesh_q2s_2d(3, 2, 1.5, 1.0),
+    "Q2S_3D": lambda: W.mesh_q2s_3d(2, 2, 1, 1.0, 1.0, 0.5),
 }
 
 
@@ -215,3 +277,37 @@ def test_structured_p1_counts():
     """Element / node / integration-point counts of the P1 square workload."""
     wl = W.workload_p1_square()
     assert (wl.mesh.n_elems, wl.mesh.n_nodes, wl.mesh.n_int) == (2048, 1089, 2048)
+
+
+def _lshape_table():
+    rows = []
+    for line in open(os.path.join(GOLD, "lshape_sizes.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        d, lev, el, n = line.split()
+        rows.append((int(d), int(lev), el, int(n)))
+    return rows
+
+
+LSHAPE_ETYPE = {(2, "P1"): "P1_2D", (2, "Q1"): "Q1_2D", (2, "Q2"): "Q2S_2D",
+                (3, "P1"): "P1_3D", (3, "P2"): "P2_3D", (3, "Q1"): "Q1_3D", (3, "Q2"): "Q2S_3D"}
+
+
+@pytest.mark.parametrize("row", [r for r in _lshape_table() if (r[0] == 2 and r[1] <= 5) or
+                                 (r[0] == 3 and r[1] <= 2)], ids=str)
+def test_lshape_mesh_sizes_match_paper_tables(row):
+    """The L-shaped domain generator reproduces the matrix sizes printed in
+    the paper's Tables 1 and 2 (levels small enough to build in a test)."""
+    dim, level, el, n = row
+    mesh = W.mesh_lshape(LSHAPE_ETYPE[(dim, el)], level)
+    assert mesh.n_dof == n
+    # the domain: area 75 (2D) or volume 75 (3D), covered exactly once
+    dphi, w = O.geometry(mesh)
+    assert abs(w.sum() - 75.0) < 1e-9
+
+
+def test_lshape_vm_mesh_is_the_papers():
+    """The von Mises experiment of Section 8.2 runs on the level-2 3D mesh of
+    20-node hexahedra with 23,929 nodes."""
+    mesh = W.mesh_lshape("Q2S_3D", 2)
+    assert mesh.n_nodes == 23929
