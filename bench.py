@@ -283,6 +283,66 @@ def time_pass(ctx, u, F, steps):
     return 1e3 * (time.perf_counter() - t0) / steps
 
 
+def lshape_report(level, steps):
+    """The paper's von Mises example (Section 8.2) on the L-shaped domain of
+    20-node serendipity hexahedra: tangent-assembly time of every Newton
+    iteration against its number of plastic points, a least-squares line
+    through them, and the K_elast assembly time for comparison; plus the
+    hysteresis data (load factor, work f_max^T u) of the load path."""
+    import numpy as np
+    import torch
+    from paper_1805_04155_amd import _ep
+    from paper_1805_04155_amd import workloads as W
+    wl = W.workload_lshape_vm(level, steps)
+    mesh = wl.mesh
+    ctx = _ep.Context(mesh, wl.free, wl.material, options={"newton_rtol": 1e-10})
+    u = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
+    _ep.ep_profile(ctx.h, 1)
+    for _ in range(5):
+        _ep.ep_assemble_elastic(ctx.h)
+    el_ms = _ep.ep_profile_read(ctx.h, "elastic")[0] / 5
+    _ep.ep_profile_read(ctx.h, "assembly")
+    fmax = torch.tensor(200.0 * wl.f_unit, dtype=torch.float64, device="cuda")
+    pts, hyst, its = [], [], 0
+    t0 = time.perf_counter()
+    for k in range(len(wl.load_factors)):
+        f = ctx.tensor(wl.f(k))
+        for _ in range(50):
+            st, info = ctx.newton_step(f, u)
+            ms = _ep.ep_profile_read(ctx.h, "assembly")[0]
+            if info["converged"]:
+                break
+            its += 1
+            pts.append((info["n_plastic_ip"], ms))
+        ctx.commit_step(u)
+        hyst.append((round(float(wl.load_factors[k] / 200.0), 4),
+                     round(float(torch.dot(fmax, u).item()), 6)))
+    t = time.perf_counter() - t0
+    _ep.ep_profile(ctx.h, 0)
+    ctx.close()
+    n = np.array([p[0] for p in pts], dtype=np.float64)
+    ms = np.array([p[1] for p in pts])
+    A = np.vstack([np.ones_like(n), n]).T
+    (a0, a1), *_ = np.linalg.lstsq(A, ms, rcond=None)
+    pred = a0 + a1 * n
+    r2 = 1.0 - ((ms - pred) ** 2).sum() / max(((ms - ms.mean()) ** 2).sum(), 1e-30)
+    full = a0 + a1 * mesh.n_int
+    out = {"workload": f"L-shaped domain, level {level}: {mesh.n_elems} 20-node serendipity "
+                       f"hexahedra, {mesh.n_nodes} nodes, {mesh.n_int} points; von Mises "
+                       f"kinematic, cyclic top traction 200 zeta(t), {steps} steps",
+           "newton_iterations": its, "path_seconds_profiled": round(t, 3),
+           "elastic_assembly_ms": round(el_ms, 4),
+           "tangent_assembly_ms_vs_plastic_points": [[int(a), round(b, 4)] for a, b in pts],
+           "fit_ms": {"intercept": round(float(a0), 5), "per_1000_points": round(float(a1) * 1e3, 6),
+                      "r2": round(float(r2), 4)},
+           "extrapolated_all_plastic_ms": round(float(full), 4),
+           "ratio_all_plastic_to_elastic": round(float(full / el_ms), 3) if el_ms > 0 else None,
+           "hysteresis_zeta_work": hyst}
+    log(f"lshape: {len(pts)} assemblies, fit {out['fit_ms']}, elastic {el_ms:.4f} ms, "
+        f"extrapolated {full:.4f} ms")
+    return out
+
+
 def plastic_sweep(steps):
     """Throughput on the 64^3 Q1 cube (von Mises) against the seeded plastic
     fraction and the tangent value type, at u = 0 and at the first Newton
@@ -400,6 +460,10 @@ def main():
     ap.add_argument("--newton-block", default="32,16,16")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the plastic-fraction sweep on the Q1 cube")
+    ap.add_argument("--no-lshape", action="store_true",
+                    help="skip the L-shape von Mises example (assembly time vs plastic points)")
+    ap.add_argument("--lshape-level", type=int, default=2)
+    ap.add_argument("--lshape-steps", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hot path is built and timed on a single "
@@ -509,9 +573,11 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, ep, beta, kappa, u_np)
-    newton = local = sweep = None
+    newton = local = sweep = lshape = None
     if not args.no_sweep:
         sweep = plastic_sweep(max(5, args.steps // 2))
+    if not args.no_lshape:
+        lshape = lshape_report(args.lshape_level, args.lshape_steps)
     if not args.no_newton:
         block = tuple(int(x) for x in args.newton_block.split(","))
         local = local_precision_report(block)
@@ -538,6 +604,7 @@ def main():
         "newton": newton,
         "local_precision": local,
         "plastic_sweep": sweep,
+        "lshape_vm": lshape,
     }
     print(json.dumps(line), flush=True)
 

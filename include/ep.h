@@ -198,6 +198,13 @@ ep_status ep_constitutive(ep_ctx *ctx, const double *u, double *sig, double *D,
  * Returns EP_ESTATE if ep_constitutive has not run since setup or commit. */
 ep_status ep_assemble_tangent(ep_ctx *ctx);
 
+/* Recomputes K_elast = B^T D_elast B (eq. K_elast-split, the setup step)
+ * from scratch, colour round by colour round, and resets K_tangent to it
+ * (the next ep_assemble_tangent adds the element terms of the elements
+ * plastic at that time only).  Timed under profile id 7, so that the cost
+ * of the incremental tangent can be set against it (Section 8.2). */
+ep_status ep_assemble_elastic(ep_ctx *ctx);
+
 /* F = B^T (WEIGHT .* S) (Section 7) for the last ep_constitutive,
  * F[n_dof].  Deterministic node gather of the element vectors. */
 ep_status ep_internal_force(ep_ctx *ctx, double *F);
@@ -259,8 +266,8 @@ ep_status ep_pcg(ep_ctx *ctx, const double *b, double *x, double rtol, int32_t m
  * around every launch of the named kernels.  ep_profile_read returns the
  * summed duration (ms) and the launch count of kernel id k (0 constitutive,
  * 1 compaction, 2 split-form element terms and their node sum inside PCG,
- * 3 colour assembly, 4 force gather, 5 SpMV, 6 PCG vector update) and
- * resets it.  Synchronises. */
+ * 3 colour assembly, 4 force gather, 5 SpMV, 6 PCG vector update,
+ * 7 K_elast assembly of ep_assemble_elastic) and resets it.  Synchronises. */
 ep_status ep_profile(ep_ctx *ctx, int32_t enable);
 ep_status ep_profile_read(ep_ctx *ctx, int32_t k, double *ms, int64_t *count);
 

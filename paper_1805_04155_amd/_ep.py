@@ -17,7 +17,8 @@ EP_P1, EP_P2, EP_Q1, EP_Q2, EP_Q2S = 1, 2, 3, 4, 5
 EP_VM, EP_DP = 1, 2
 EP_FP64, EP_FP32, EP_BF16 = 0, 1, 2
 EP_OPERATOR_ASSEMBLED, EP_OPERATOR_SPLIT = 0, 1
-PROF = dict(constitutive=0, compaction=1, split=2, assembly=3, force=4, spmv=5, pcg_vec=6)
+PROF = dict(constitutive=0, compaction=1, split=2, assembly=3, force=4, spmv=5, pcg_vec=6,
+            elastic=7)
 
 ETYPE = {"P1_2D": (2, EP_P1), "Q1_2D": (2, EP_Q1), "Q2_2D": (2, EP_Q2), "P1_3D": (3, EP_P1),
          "P2_3D": (3, EP_P2), "Q1_3D": (3, EP_Q1), "Q2_3D": (3, EP_Q2), "Q2S_2D": (2, EP_Q2S),
@@ -97,6 +98,7 @@ def lib():
             "ep_strain": [P, P, P],
             "ep_constitutive": [P, P, P, P, P],
             "ep_assemble_tangent": [P],
+            "ep_assemble_elastic": [P],
             "ep_internal_force": [P, P],
             "ep_newton_step": [P, P, P, P],
             "ep_commit_step": [P, P],
@@ -135,7 +137,8 @@ def lib():
 
 EXPORTED = ["ep_setup", "ep_destroy", "ep_last_error", "ep_set_stream", "ep_get_sizes",
             "ep_set_state", "ep_get_state", "ep_geometry", "ep_strain", "ep_constitutive",
-            "ep_assemble_tangent", "ep_internal_force", "ep_newton_step", "ep_commit_step",
+            "ep_assemble_tangent", "ep_assemble_elastic", "ep_internal_force", "ep_newton_step",
+            "ep_commit_step",
             "ep_get_plastic", "ep_get_csr", "ep_get_position_map", "ep_spmv",
             "ep_apply_tangent", "ep_pcg",
             "ep_profile", "ep_profile_read", "ep_mlp_create", "ep_mlp_destroy",
@@ -239,6 +242,10 @@ def ep_constitutive(ctx, u, sig=None, D=None, flag=None):
 
 def ep_assemble_tangent(ctx):
     _check(ctx, lib().ep_assemble_tangent(ctx))
+
+
+def ep_assemble_elastic(ctx):
+    _check(ctx, lib().ep_assemble_elastic(ctx))
 
 
 def ep_internal_force(ctx, F):

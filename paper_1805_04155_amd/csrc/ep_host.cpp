@@ -1020,6 +1020,20 @@ ep_status ep_spmv(ep_ctx *ctx, const double *x, double *y) {
   return EP_OK;
 }
 
+ep_status ep_assemble_elastic(ep_ctx *ctx) {
+  CHECK_CTX(ctx);
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  const int64_t n = c->nnzb * c->dim * c->dim;
+  HIPC(hipMemsetAsync(c->Ke, 0, sizeof(double) * std::max<int64_t>(1, n), c->stream));
+  const int tok = c->prof_begin(PROF_ELASTIC);
+  HIPC(launch_elastic_assembly(*c));
+  c->prof_end(tok);
+  if (c->opt.tangent_prec == EP_FP32) HIPC(launch_to_float(c->Ke, c->Ke32, n, c->stream));
+  HIPC(launch_copy_ke_to_kt(*c));
+  c->em_asm = -1;  // K_tangent = K_elast: no element terms to restore
+  return EP_OK;
+}
+
 ep_status ep_apply_tangent(ep_ctx *ctx, const double *x, double *y) {
   CHECK_CTX(ctx);
   Ctx *c = reinterpret_cast<Ctx *>(ctx);

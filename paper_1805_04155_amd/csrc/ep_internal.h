@@ -40,7 +40,7 @@ constexpr int CMP_CHUNK = CMP_THREADS * CMP_ITEMS;
 
 // Kernel ids for ep_profile.
 enum ProfId { PROF_CONST = 0, PROF_COMPACT, PROF_SPLIT, PROF_ASSEMBLE, PROF_FORCE, PROF_SPMV,
-              PROF_PCGVEC, PROF_COUNT };
+              PROF_PCGVEC, PROF_ELASTIC, PROF_COUNT };
 
 struct Ctx;
 

@@ -329,6 +329,33 @@ def nodal_load_structured_face(mesh: Mesh, grid_shape, order, axis, value,
     return f.reshape(-1)
 
 
+def nodal_load_serendipity_face(mesh: Mesh, axis, value, direction, magnitude):
+    """Uniform traction on an axis-aligned boundary plane of a serendipity
+    mesh: an 8-node quadrilateral edge of length L gives L/6 to each vertex
+    and 2L/3 to the midpoint; a 20-node hexahedron face of area A gives
+    -A/12 to each vertex and A/3 to each edge midpoint (the integrals of the
+    8-node face functions)."""
+    dim = mesh.dim
+    nv, nface = (4, 3) if dim == 2 else (8, 8)
+    on = np.abs(mesh.coord[axis] - value) < 1e-12
+    on_e = on[mesh.elem]                          # (n_e, n_p)
+    faces = np.nonzero(on_e.sum(axis=1) == nface)[0]
+    f = np.zeros((mesh.n_nodes, dim))
+    others = [a for a in range(dim) if a != axis]
+    for e in faces:
+        nodes = mesh.elem[e]
+        sel = np.nonzero(on_e[e])[0]
+        x = mesh.coord[:, nodes[sel]]
+        size = np.prod([x[a].max() - x[a].min() for a in others])
+        for loc in sel:
+            if dim == 2:
+                wgt = size / 6.0 if loc < nv else 2.0 * size / 3.0
+            else:
+                wgt = -size / 12.0 if loc < nv else size / 3.0
+            f[nodes[loc], direction] += magnitude * wgt
+    return f.reshape(-1)
+
+
 def nodal_load_p1_edge_2d(mesh: Mesh, axis, value, direction, magnitude):
     """Uniform traction on a straight boundary line of a P1 triangle mesh:
     each boundary edge of length L gives L/2 to each end node."""
@@ -504,6 +531,19 @@ def workload_q1_cube_cyclic(n=64, steps=30) -> Workload:
     wl = workload_q1_cube(n)
     return Workload("q1_cube_vm_cyclic", wl.mesh, wl.material, wl.free, wl.f_unit,
                     cyclic_factors(steps, 540.0))
+
+
+def workload_lshape_vm(level=2, steps=40) -> Workload:
+    """The paper's von Mises example (Section 8.2): the L-shaped domain of
+    20-node serendipity hexahedra (level 2: 23,929 nodes), von Mises with
+    linear kinematic hardening (E = 206900, nu = 0.29, a = 10000,
+    Y = 450 sqrt(2/3)), symmetry conditions on x1 = 0 and x2 = 0 (and
+    u3 = 0 on x3 = 0), traction zeta(t) * 200 on the top x2 = 10 in +x2
+    along the cyclic history at t_k = 4k/steps."""
+    mesh = mesh_lshape("Q2S_3D", level)
+    free = free_mask(mesh, [(0, 0.0, [0]), (1, 0.0, [1]), (2, 0.0, [2])])
+    f = nodal_load_serendipity_face(mesh, 1, 10.0, 1, 1.0)
+    return Workload("lshape_vm_cyclic", mesh, VM_MATERIAL, free, f, cyclic_factors(steps, 200.0))
 
 
 def _block_bcs(mesh):

@@ -253,3 +253,49 @@ def test_split_operator_load_paths(name):
     finally:
         ctx_s.close()
         ctx_a.close()
+
+
+def test_lshape_vm_cyclic_path_small():
+    """The paper's von Mises example (Section 8.2) on the coarsest L-shape
+    mesh of 20-node serendipity hexahedra: the whole cyclic load path
+    (loading, unloading, reverse loading) on the GPU equals the oracle's."""
+    # t_k = 4k/7: loading, unloading and reverse loading without the
+    # zero-load instants t = 2 and t = 4 (the oracle's relative residual
+    # needs a nonzero load); the seventh step (t = 4) is left out
+    wl = W.workload_lshape_vm(level=0, steps=7)
+    steps = range(6)
+    # the FP64 residual floor of this problem is ~2e-13
+    uo, so = oracle_path(wl, steps, tol=1e-12)
+    ctx, ug, recs, st = gpu_path(wl, steps)
+    try:
+        assert max(s[3] for s in so) > 0
+        for k in steps:
+            assert _rel(ug[k], uo[k]) < 1e-9, k
+            assert recs[k]["n_plastic_ip"] == so[k][3], k
+        ref = O.ip6_to_state(so[-1][0], 3)
+        assert np.abs(st[0] - ref).max() < 1e-9 * np.abs(ref).max()
+    finally:
+        ctx.close()
+
+
+def test_assemble_elastic_resets_tangent():
+    """ep_assemble_elastic recomputes K_elast bit for bit and leaves
+    K_tangent = K_elast; the next tangent assembly equals the one before."""
+    wl = W.workload_lshape_vm(level=0, steps=8)
+    ctx = _ep.Context(wl.mesh, wl.free, wl.material)
+    try:
+        _, _, Ke0 = ctx.csr(0)
+        Ke0 = _np(Ke0)
+        u = ctx.tensor(W.random_displacement(wl.mesh, 3, 2e-3, wl.free))
+        ctx.constitutive(u, sig=False, D=False, flag=False)
+        ip, _ = ctx.plastic()
+        assert ip.numel() > 0
+        ctx.assemble_tangent()
+        Kt1 = _np(ctx.csr(1)[2])
+        _ep.ep_assemble_elastic(ctx.h)
+        assert np.array_equal(_np(ctx.csr(0)[2]), Ke0)
+        assert np.array_equal(_np(ctx.csr(1)[2]), Ke0)
+        ctx.assemble_tangent()
+        assert np.array_equal(_np(ctx.csr(1)[2]), Kt1)
+    finally:
+        ctx.close()
