@@ -343,6 +343,39 @@ def lshape_report(level, steps):
     return out
 
 
+def footing_report(n, ud_max, du_max, max_steps):
+    """The strip-footing example (Section 8.3), 9-node quadrilaterals on an
+    n x n grid: displacement-controlled path with the paper's doubling of
+    the increment, the normalised footing pressure p/c0 along it."""
+    import torch
+    from paper_1805_04155_amd import _ep, solver
+    from paper_1805_04155_amd import workloads as W
+    wl = W.workload_strip_footing(n, "Q2_2D")
+    ctx = _ep.Context(wl.mesh, wl.free, wl.material, options={"newton_rtol": 1e-10})
+    u = torch.zeros(wl.mesh.n_dof, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = solver.displacement_path(ctx, wl, u, ud_max=ud_max, du0=1e-3, du_max=du_max,
+                                    max_steps=max_steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ctx.close()
+    c0 = 450.0
+    out = {"workload": f"plane strain [0,10]^2, {n}x{n} 9-node quadrilaterals "
+                       f"({wl.mesh.n_dof} dofs), Drucker-Prager perfect E=1e7 nu=0.48 c0=450 "
+                       "phi=pi/9, footing 0<=x1<=1 pushed down by u_D",
+           "seconds": round(t, 3), "steps": len(recs),
+           "newton_its": sum(r["newton_its"] for r in recs),
+           "pcg_its": sum(r["pcg_its"] for r in recs),
+           "final_u_D": recs[-1]["u_D"] if recs else 0.0,
+           "final_pressure_over_c0": round(recs[-1]["pressure"] / c0, 4) if recs else None,
+           "path_u_D_p_over_c0_plastic": [[round(r["u_D"], 6), round(r["pressure"] / c0, 4),
+                                          r["n_plastic_ip"]] for r in recs]}
+    log(f"footing: {out['steps']} steps to u_D = {out['final_u_D']}, p/c0 = "
+        f"{out['final_pressure_over_c0']}, {t:.1f} s")
+    return out
+
+
 def plastic_sweep(steps):
     """Throughput on the 64^3 Q1 cube (von Mises) against the seeded plastic
     fraction and the tangent value type, at u = 0 and at the first Newton
@@ -463,6 +496,9 @@ def main():
     ap.add_argument("--no-lshape", action="store_true",
                     help="skip the L-shape von Mises example (assembly time vs plastic points)")
     ap.add_argument("--lshape-level", type=int, default=2)
+    ap.add_argument("--no-footing", action="store_true",
+                    help="skip the strip-footing example (displacement control)")
+    ap.add_argument("--footing-n", type=int, default=64)
     ap.add_argument("--lshape-steps", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -573,11 +609,13 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, ep, beta, kappa, u_np)
-    newton = local = sweep = lshape = None
+    newton = local = sweep = lshape = footing = None
     if not args.no_sweep:
         sweep = plastic_sweep(max(5, args.steps // 2))
     if not args.no_lshape:
         lshape = lshape_report(args.lshape_level, args.lshape_steps)
+    if not args.no_footing:
+        footing = footing_report(args.footing_n, 0.1, 0.016, 40)
     if not args.no_newton:
         block = tuple(int(x) for x in args.newton_block.split(","))
         local = local_precision_report(block)
@@ -605,6 +643,7 @@ def main():
         "local_precision": local,
         "plastic_sweep": sweep,
         "lshape_vm": lshape,
+        "strip_footing": footing,
     }
     print(json.dumps(line), flush=True)
 

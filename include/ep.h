@@ -130,7 +130,10 @@ typedef struct {
 } ep_sizes;
 
 typedef struct {
-  double res_rel;            /* |Q(f - F(u))| / |Q f| at the u passed in     */
+  double res_rel;            /* |Q(f - F(u))| / |Q f| at the u passed in;
+                                with Q f = 0 (pure displacement control)
+                                relative to the reactions |(I - Q) F(u)|,
+                                absolute if both vanish                       */
   double res_norm, f_norm;
   double pcg_relres;         /* final relative PCG residual (if solved)      */
   int32_t pcg_its;

@@ -226,7 +226,9 @@ def csr_to_scipy(row_ptr, col_idx, val, n):
 def newton_solve(mesh, material, free, f, u0, ep6, beta6, kappa, *, tol=1e-10,
                  max_it=50, linear="direct", dphi=None, w=None, pattern_=None,
                  history=None, raise_on_limit=True):
-    """Solve one load step: find u with |Q(f - F(u))| <= tol |Q f|.
+    """Solve one load step: find u with |Q(f - F(u))| <= tol |Q f| (with
+    Q f = 0, under pure displacement control, relative to the reactions
+    |(I - Q) F(u)| instead).
 
     The first iterate is u0 (the previous step's displacement on free dofs;
     Dirichlet values are already in u0).  The linear solve is either a sparse
@@ -249,7 +251,8 @@ def newton_solve(mesh, material, free, f, u0, ep6, beta6, kappa, *, tol=1e-10,
         out = constitutive(material, eps, ep6, beta6, kappa)
         F = internal_force(mesh, dphi, w, out["sig"])
         r = (f - F) * free
-        rel = np.linalg.norm(r) / fq
+        scale = fq if fq > 0 else np.linalg.norm(F[~q])
+        rel = np.linalg.norm(r) / scale if scale > 0 else np.linalg.norm(r)
         res.append(rel)
         if history is not None:
             history.append(dict(rel=rel, n_plastic=int((out["flag"] != 0).sum())))

@@ -391,14 +391,23 @@ ep_status do_assemble(Ctx *c) {
   return EP_OK;
 }
 
-// residual r = Q(f - F), norms -> c->norms[0] = |r|^2, [1] = |Qf|^2
+// residual r = Q(f - F), norms -> c->norms[0] = |r|^2, [1] = |Qf|^2,
+// [2] = |(I - Q) F|^2 (reactions at the Dirichlet dofs)
 ep_status do_residual(Ctx *c, const double *f, double *F_out) {
   const int nblk = (int)((c->n_n + 255) / 256);
   const int tok = c->prof_begin(PROF_FORCE);
   HIPC(launch_force_gather(*c, f, F_out, c->r, c->partials, nblk));
   c->prof_end(tok);
-  HIPC(launch_reduce(*c, c->partials, nblk, 2, c->norms));
+  HIPC(launch_reduce(*c, c->partials, nblk, 3, c->norms));
   return EP_OK;
+}
+
+// |Q(f - F)| relative to |Q f|; under pure displacement control (Q f = 0)
+// relative to the reactions |(I - Q) F|; absolute if both vanish
+double relative_residual(const double *norms_h) {
+  const double rn = std::sqrt(norms_h[0]), fn = std::sqrt(norms_h[1]);
+  const double scale = fn > 0 ? fn : std::sqrt(norms_h[2]);
+  return scale > 0 ? rn / scale : rn;
 }
 
 // n PCG iterations.  Even chunks without profiling replay a HIP graph of
@@ -474,10 +483,9 @@ ep_status exact_residual(Ctx *c, const double *f, const double *u, double *res_r
   if (st) return st;
   st = do_residual(c, f, nullptr);
   if (st) return st;
-  HIPC(hipMemcpyAsync(c->norms_h, c->norms, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPC(hipMemcpyAsync(c->norms_h, c->norms, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPC(hipStreamSynchronize(c->stream));
-  const double rn = std::sqrt(c->norms_h[0]), fn = std::sqrt(c->norms_h[1]);
-  *res_rel = fn > 0 ? rn / fn : rn;
+  *res_rel = relative_residual(c->norms_h);
   return EP_OK;
 }
 
@@ -927,13 +935,13 @@ ep_status ep_newton_step(ep_ctx *ctx, const double *f, double *u, ep_newton_info
   if (st) return st;
   st = do_residual(c, f, nullptr);
   if (st) return st;
-  HIPC(hipMemcpyAsync(c->norms_h, c->norms, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPC(hipMemcpyAsync(c->norms_h, c->norms, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   int32_t tot[3];
   HIPC(hipMemcpyAsync(tot, c->ptotals, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIPC(hipStreamSynchronize(c->stream));
   info->res_norm = std::sqrt(c->norms_h[0]);
   info->f_norm = std::sqrt(c->norms_h[1]);
-  info->res_rel = info->f_norm > 0 ? info->res_norm / info->f_norm : info->res_norm;
+  info->res_rel = relative_residual(c->norms_h);
   info->n_plastic_elem = tot[2];
   info->n_plastic_ip = tot[1];
   if (info->res_rel <= c->opt.newton_rtol) {
@@ -1135,12 +1143,11 @@ ep_status ep_warm_start(ep_ctx *ctx, ep_mlp *mlp, const double *f, const double 
   st = do_residual(c, f, nullptr);
   if (st) return st;
   int32_t tot[3];
-  HIPC(hipMemcpyAsync(c->norms_h, c->norms, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPC(hipMemcpyAsync(c->norms_h, c->norms, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPC(hipMemcpyAsync(tot, c->ptotals, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIPC(hipStreamSynchronize(c->stream));
   {
-    const double rn = std::sqrt(c->norms_h[0]), fn = std::sqrt(c->norms_h[1]);
-    info->res_rel_pred = fn > 0 ? rn / fn : rn;
+    info->res_rel_pred = relative_residual(c->norms_h);
   }
   info->n_plastic_pred = tot[1];
   // one solve with the predicted tangent and residual

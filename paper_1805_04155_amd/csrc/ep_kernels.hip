@@ -1065,7 +1065,7 @@ __global__ __launch_bounds__(256) void k_assemble_mfma(KA a) {
 
 // ----------------------------------------------------------------------------
 // Deterministic node gather of the element force vectors, residual and
-// partial norms.
+// partial norms |r|^2, |Q f|^2 and |(I - Q) F|^2 (reactions).
 // ----------------------------------------------------------------------------
 template <int D>
 __global__ __launch_bounds__(256) void k_force_gather(int64_t n_n, const int32_t *n2e_ptr,
@@ -1073,10 +1073,10 @@ __global__ __launch_bounds__(256) void k_force_gather(int64_t n_n, const int32_t
                                                       const double *f, const uint8_t *freem,
                                                       double *F_out, double *r_out,
                                                       double *partials) {
-  __shared__ double s_a[256], s_b[256];
+  __shared__ double s_a[256], s_b[256], s_c[256];
   const int tid = threadIdx.x;
   const int64_t m = (int64_t)blockIdx.x * 256 + tid;
-  double rr = 0.0, ff = 0.0;
+  double rr = 0.0, ff = 0.0, rc = 0.0;
   if (m < n_n) {
     double s[D];
 #pragma unroll
@@ -1096,21 +1096,25 @@ __global__ __launch_bounds__(256) void k_force_gather(int64_t n_n, const int32_t
       if (r_out) r_out[dof] = r;
       rr += r * r;
       ff += fv * fv;
+      if (!fr) rc += s[i] * s[i];  // reaction at a Dirichlet dof
     }
   }
   s_a[tid] = rr;
   s_b[tid] = ff;
+  s_c[tid] = rc;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if (tid < s) {
       s_a[tid] += s_a[tid + s];
       s_b[tid] += s_b[tid + s];
+      s_c[tid] += s_c[tid + s];
     }
     __syncthreads();
   }
   if (tid == 0) {
-    partials[2 * blockIdx.x] = s_a[0];
-    partials[2 * blockIdx.x + 1] = s_b[0];
+    partials[3 * blockIdx.x] = s_a[0];
+    partials[3 * blockIdx.x + 1] = s_b[0];
+    partials[3 * blockIdx.x + 2] = s_c[0];
   }
 }
 

@@ -476,6 +476,7 @@ class Workload:
     f_unit: np.ndarray            # load vector for unit load factor
     load_factors: np.ndarray      # one factor per load step
     note: str = ""
+    u_dir_unit: np.ndarray = None  # displacement control: prescribed u per unit u_D
 
     def f(self, k):
         return self.load_factors[k] * self.f_unit
@@ -544,6 +545,41 @@ def workload_lshape_vm(level=2, steps=40) -> Workload:
     free = free_mask(mesh, [(0, 0.0, [0]), (1, 0.0, [1]), (2, 0.0, [2])])
     f = nodal_load_serendipity_face(mesh, 1, 10.0, 1, 1.0)
     return Workload("lshape_vm_cyclic", mesh, VM_MATERIAL, free, f, cyclic_factors(steps, 200.0))
+
+
+def dp_strip_footing_material(phi=math.pi / 9, c0=450.0, E=1e7, nu=0.48, plane=True):
+    """Drucker-Prager parameters of the strip-footing example (Section 8.3):
+    eta and c from the friction angle phi and the cohesion c0, the plane
+    strain fit or the 3D fit of the paper's formulas."""
+    if plane:
+        t = math.tan(phi)
+        d = math.sqrt(9.0 + 12.0 * t * t)
+        eta, c = 3.0 * t / d, c0 * 3.0 / d
+    else:
+        s, co = math.sin(phi), math.cos(phi)
+        d = math.sqrt(3.0) * (3.0 + s)
+        eta, c = 6.0 * s / d, c0 * 6.0 * co / d
+    return Material("DP", E=E, nu=nu, eta=eta, c=c, a=0.0)
+
+
+def workload_strip_footing(n=32, etype="Q2_2D", phi=math.pi / 9, c0=450.0) -> Workload:
+    """The strip-footing example of Section 8.3 in plane strain: the square
+    [0,10]^2 on n x n elements, zero normal displacement on the left, right
+    and bottom sides, the footing 0 <= x1 <= 1 on the top pushed down by the
+    prescribed vertical displacement u_D (no forces), Drucker-Prager perfect
+    plasticity E = 1e7, nu = 0.48, c0 = 450, phi = pi/9."""
+    make = {"Q2_2D": mesh_q2_2d, "Q2S_2D": mesh_q2s_2d, "Q1_2D": mesh_q1_2d,
+            "P1_2D": mesh_p1_2d}[etype]
+    mesh = make(n, n, 10.0, 10.0)
+    free = free_mask(mesh, [(0, 0.0, [0]), (0, 10.0, [0]), (1, 0.0, [1])])
+    x = mesh.coord
+    foot = np.nonzero((np.abs(x[1] - 10.0) < 1e-12) & (x[0] <= 1.0 + 1e-12))[0]
+    free[2 * foot + 1] = 0
+    ud = np.zeros(mesh.n_dof)
+    ud[2 * foot + 1] = -1.0
+    return Workload("strip_footing_dp", mesh, dp_strip_footing_material(phi, c0), free,
+                    np.zeros(mesh.n_dof), np.zeros(0), note=f"footing nodes {len(foot)}",
+                    u_dir_unit=ud)
 
 
 def _block_bcs(mesh):

@@ -299,3 +299,72 @@ def test_assemble_elastic_resets_tangent():
         assert np.array_equal(_np(ctx.csr(1)[2]), Kt1)
     finally:
         ctx.close()
+
+
+def test_strip_footing_displacement_control():
+    """The strip-footing example (Section 8.3) on a coarse 9-node mesh:
+    five steps of the prescribed footing displacement (no forces; the
+    residual is measured against the reactions) through the onset of
+    plastic flow, GPU driver against the oracle's Newton with the same
+    increments: displacements, footing pressures and plastic sets."""
+    wl = W.workload_strip_footing(8, "Q2_2D")
+    mesh, mat = wl.mesh, wl.material
+    n = mesh.n_int
+    ep6, beta6, kappa = np.zeros((n, 6)), np.zeros((n, 6)), np.zeros(n)
+    dphi, w = O.geometry(mesh)
+    pat = O.pattern(mesh)
+    dirn = wl.u_dir_unit
+    m = dirn != 0
+    uo = np.zeros(mesh.n_dof)
+    ref = []
+    for k in range(1, 6):
+        uo[m] = dirn[m] * 1e-3 * k
+        uo, it, res, out = O.newton_solve(mesh, mat, wl.free, np.zeros(mesh.n_dof), uo, ep6,
+                                          beta6, kappa, tol=1e-11, dphi=dphi, w=w, pattern_=pat)
+        ep6, beta6, kappa = out["ep"], out["beta"], out["kappa"]
+        F = O.internal_force(mesh, dphi, w, out["sig"])
+        ref.append((uo.copy(), float(F @ dirn), int(np.count_nonzero(out["flag"]))))
+    ctx = _ep.Context(mesh, wl.free, mat, options={"newton_rtol": 1e-11})
+    try:
+        u = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
+        us = []
+        recs = solver.displacement_path(ctx, wl, u, ud_max=5e-3, du0=1e-3, dp_rel=0.0,
+                                        max_steps=5, callback=lambda k, r: us.append(_np(u).copy()))
+        assert len(recs) == 5
+        assert ref[-1][2] > 0
+        for k in range(5):
+            assert abs(recs[k]["u_D"] - 1e-3 * (k + 1)) < 1e-15
+            assert _rel(us[k], ref[k][0]) < 1e-9, k
+            assert abs(recs[k]["pressure"] - ref[k][1]) < 1e-9 * abs(ref[k][1]), k
+            assert recs[k]["n_plastic_ip"] == ref[k][2], k
+    finally:
+        ctx.close()
+
+
+def test_strip_footing_limit_load_prandtl():
+    """Physics pin of the whole displacement-controlled path: the limit
+    pressure of a smooth strip footing on a weightless Drucker-Prager
+    (plane-strain Mohr-Coulomb fit) half-space approaches Prandtl's closed
+    form c0 N_c, N_c = (e^{pi tan phi} tan^2(pi/4 + phi/2) - 1) cot phi
+    (14.835 for phi = pi/9).  On a 32x32 mesh the 9-node elements come
+    within 6 %, while the 4-node elements lock and overestimate it by more
+    than 25 % (the paper's observation for P1 / Q1 against P2 / Q2)."""
+    phi = math.pi / 9
+    nc = (math.exp(math.pi * math.tan(phi)) * math.tan(math.pi / 4 + phi / 2) ** 2 - 1) / math.tan(phi)
+    out = {}
+    for et in ("Q2_2D", "Q1_2D"):
+        wl = W.workload_strip_footing(32, et)
+        ctx = _ep.Context(wl.mesh, wl.free, wl.material, options={"newton_rtol": 1e-10})
+        try:
+            u = torch.zeros(wl.mesh.n_dof, dtype=torch.float64, device="cuda")
+            recs = solver.displacement_path(ctx, wl, u, ud_max=0.05, du0=1e-3, du_max=0.016,
+                                            max_steps=40)
+            assert abs(recs[-1]["u_D"] - 0.05) < 1e-12
+            p = [r["pressure"] / 450.0 for r in recs]
+            # the pressure saturates: the last steps change it by < 0.5 %
+            assert abs(p[-1] - p[-3]) < 0.005 * p[-1]
+            out[et] = p[-1]
+        finally:
+            ctx.close()
+    assert abs(out["Q2_2D"] - nc) < 0.06 * nc, out
+    assert out["Q1_2D"] > 1.25 * nc, out
