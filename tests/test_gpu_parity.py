@@ -248,3 +248,33 @@ def test_split_apply_elastic_state_is_k_elast():
         close(y, ref)
     finally:
         ctx.close()
+
+
+def test_split_apply_fp32_storage():
+    """Split form with K_elast stored in FP32 (tangent_prec FP32): the
+    element terms stay FP64, so the product matches the oracle's K_t x to
+    the FP32 rounding of K_elast."""
+    mesh, free, mat, u, (ep, beta, kappa) = make_case("q2_2d_dp")
+    ctx = _ep.Context(mesh, free, mat, options={"tangent_prec": _ep.EP_FP32,
+                                                "operator_form": _ep.EP_OPERATOR_SPLIT})
+    try:
+        ctx.set_state(ep, None, kappa)
+        ctx.constitutive(ctx.tensor(u), sig=False, D=False, flag=False)
+        rng = np.random.default_rng(11)
+        x = rng.standard_normal(mesh.n_dof)
+        y = _np(ctx.apply_tangent(ctx.tensor(x)))
+        dphi, w = O.geometry(mesh)
+        rp, ci = O.pattern(mesh)
+        eps = O.strain(mesh, dphi, u)
+        ref = O.constitutive(mat, eps, O.state_to_ip6(ep, 2), None, kappa)
+        assert np.count_nonzero(ref["flag"]) > 0
+        _, _, Kt = O.assemble(mesh, dphi, w, ref["D"], rp, ci)
+        n0 = mesh.n_int
+        D0 = O.constitutive(mat, np.zeros((n0, 6)), np.zeros((n0, 6)))["D"]
+        _, _, Ke = O.assemble(mesh, dphi, w, D0, rp, ci)
+        yo = (O.csr_to_scipy(rp, ci, Kt, mesh.n_dof) @ x) * free
+        scale = (O.csr_to_scipy(rp, ci, np.abs(Ke), mesh.n_dof) @ np.abs(x)).max()
+        close(y, yo, tol=1e-6, scale=scale)
+        assert np.abs(y - yo).max() > 1e-12 * scale  # the FP32 values are really used
+    finally:
+        ctx.close()
