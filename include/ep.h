@@ -9,8 +9,11 @@
  *   - the return map T_k and consistent tangent T_k^o (Sections 2.2, 2.3),
  *   - the compaction of the plastic integration points,
  *   - the tangent K = K_elast + B^T (D_tangent - D_elast) B (eq. K-split),
+ *     assembled, or applied element by element in its split form,
  *   - the internal force F = B^T (WEIGHT .* S) (Section 7),
  *   - a linear solve for the Newton correction (here Jacobi-PCG).
+ * Load paths (force- or displacement-controlled, Section 8) are driven by
+ * the caller: one ep_newton_step per iteration, ep_commit_step per step.
  *
  * Conventions
  *   - Pointers are DEVICE pointers unless the comment says host.  Device

@@ -11,8 +11,10 @@ Conventions (shared input format):
   * coord : float64 array (dim, n_nodes), Cartesian node coordinates.
   * elem  : int32 array (n_elems, n_p), 0-based node ids per element, in the
             local node order of the reference element (paper Appendix for P1,
-            P2 tetrahedra and Q1 hexahedra; tensor Lagrange orders for the
-            9-node quadrilateral and the 27-node hexahedron, listed below).
+            P2 tetrahedra, Q1 hexahedra and the 20-node serendipity
+            hexahedron; tensor Lagrange orders for the 9-node quadrilateral
+            and the 27-node hexahedron, listed below; the serendipity
+            elements use the first 8 / 20 of those nodes).
   * dof numbering is interleaved: dof = dim * node + component (the paper's
             column-major U(:) of a dim x n_n array, Section 5).
   * free  : uint8 array (dim * n_nodes), 1 = free, 0 = Dirichlet.
