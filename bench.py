@@ -85,8 +85,8 @@ def kernel_bytes(mesh, mat, counts, tangent_bytes):
         + 8 * ndesc * pi,
         # colour-major order and two masks read, list written
         "compaction": counts["n_perm"] * 4 + 8 * n_e + 4 * listed,
-        # node offsets, element force vectors (node order), f, free mask, F/r
-        "force": 4 * (n_n + 1) + 8 * D * NP * n_e + n_dof * (8 + 1 + 8),
+        # node offsets, element force vectors (node order), free mask, F
+        "force": 4 * (n_n + 1) + 8 * D * NP * n_e + n_dof * (8 + 1),
     }
 
 

@@ -392,13 +392,14 @@ ep_status do_assemble(Ctx *c) {
 }
 
 // residual r = Q(f - F), norms -> c->norms[0] = |r|^2, [1] = |Qf|^2,
-// [2] = |(I - Q) F|^2 (reactions at the Dirichlet dofs)
-ep_status do_residual(Ctx *c, const double *f, double *F_out) {
+// [2] = |(I - Q) F|^2 (reactions at the Dirichlet dofs); residual = false:
+// F only (into F_out)
+ep_status do_residual(Ctx *c, const double *f, double *F_out, bool residual = true) {
   const int nblk = (int)((c->n_n + 255) / 256);
   const int tok = c->prof_begin(PROF_FORCE);
-  HIPC(launch_force_gather(*c, f, F_out, c->r, c->partials, nblk));
+  HIPC(launch_force_gather(*c, f, F_out, residual ? c->r : nullptr, c->partials, nblk));
   c->prof_end(tok);
-  HIPC(launch_reduce(*c, c->partials, nblk, 3, c->norms));
+  if (residual) HIPC(launch_reduce(*c, c->partials, nblk, 3, c->norms));
   return EP_OK;
 }
 
@@ -923,7 +924,7 @@ ep_status ep_internal_force(ep_ctx *ctx, double *F) {
     c->err = "ep_internal_force: no constitutive evaluation since setup or commit";
     return EP_ESTATE;
   }
-  return do_residual(c, nullptr, F);
+  return do_residual(c, nullptr, F, false);
 }
 
 ep_status ep_newton_step(ep_ctx *ctx, const double *f, double *u, ep_newton_info *info) {

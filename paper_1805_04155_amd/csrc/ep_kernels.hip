@@ -1421,31 +1421,70 @@ __global__ __launch_bounds__(256) void k_split_gather(int64_t n_n, const int32_t
 // through a permutation, -1 = padding) with predicate (src | src2) != 0; kind
 // 0: uint8 source, kind 1: uint32 source (bitmask), src2 uint32 or null.
 // ----------------------------------------------------------------------------
-__device__ inline uint32_t cmp_value(const void *src, int kind, int64_t item) {
-  if (item < 0) return 0u;
-  return kind == 0 ? (uint32_t)((const uint8_t *)src)[item] : ((const uint32_t *)src)[item];
+// The CMP_ITEMS items of this thread (item k at base + k*CMP_THREADS + tid,
+// through perm when given; -1 past n or for padding) and their predicate
+// words (src: uint8 for KIND 0, uint32 for KIND 1; src2 uint32 or null).
+// Every load is unconditional (out-of-range lanes read element 0, which
+// every source array has, and discard it), and the index loads are issued
+// before the value loads that depend on them: a thread waits for two memory
+// round trips, not 2*CMP_ITEMS.
+template <int KIND>
+__device__ inline void cmp_load(const void *src, const uint32_t *src2, const int32_t *perm,
+                                int64_t n, int64_t base, int tid, int64_t *item, uint32_t *v,
+                                uint32_t *v2) {
+  int64_t idx[CMP_ITEMS];
+#pragma unroll
+  for (int k = 0; k < CMP_ITEMS; ++k) {
+    const int64_t i = base + (int64_t)k * CMP_THREADS + tid;
+    idx[k] = i < n ? i : -1;
+  }
+  if (perm) {
+    int32_t pv[CMP_ITEMS];
+#pragma unroll
+    for (int k = 0; k < CMP_ITEMS; ++k) pv[k] = perm[idx[k] >= 0 ? idx[k] : 0];
+#pragma unroll
+    for (int k = 0; k < CMP_ITEMS; ++k) item[k] = idx[k] >= 0 ? (int64_t)pv[k] : -1;
+  } else {
+#pragma unroll
+    for (int k = 0; k < CMP_ITEMS; ++k) item[k] = idx[k];
+  }
+  uint32_t raw[CMP_ITEMS];
+#pragma unroll
+  for (int k = 0; k < CMP_ITEMS; ++k) {
+    const int64_t j = item[k] >= 0 ? item[k] : 0;
+    raw[k] = KIND == 0 ? (uint32_t)((const uint8_t *)src)[j] : ((const uint32_t *)src)[j];
+  }
+#pragma unroll
+  for (int k = 0; k < CMP_ITEMS; ++k) v[k] = item[k] >= 0 ? raw[k] : 0u;
+  if (src2) {
+#pragma unroll
+    for (int k = 0; k < CMP_ITEMS; ++k) raw[k] = src2[item[k] >= 0 ? item[k] : 0];
+#pragma unroll
+    for (int k = 0; k < CMP_ITEMS; ++k) v2[k] = item[k] >= 0 ? raw[k] : 0u;
+  } else {
+#pragma unroll
+    for (int k = 0; k < CMP_ITEMS; ++k) v2[k] = 0u;
+  }
 }
 
+template <int KIND>
 __global__ __launch_bounds__(CMP_THREADS) void k_compact_count(const void *src,
-                                                               const uint32_t *src2, int kind,
+                                                               const uint32_t *src2,
                                                                const int32_t *perm, int64_t n,
                                                                int32_t *counts, int32_t *counts2,
                                                                int32_t *counts3) {
   __shared__ int32_t s_c[CMP_THREADS / 64], s_b[CMP_THREADS / 64], s_z[CMP_THREADS / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t base = (int64_t)blockIdx.x * CMP_CHUNK;
+  int64_t item[CMP_ITEMS];
+  uint32_t v[CMP_ITEMS], v2[CMP_ITEMS];
+  cmp_load<KIND>(src, src2, perm, n, base, tid, item, v, v2);
   int32_t cnt = 0, bits = 0, nz = 0;
+#pragma unroll
   for (int k = 0; k < CMP_ITEMS; ++k) {
-    const int64_t i = base + (int64_t)k * CMP_THREADS + tid;
-    uint32_t v = 0u, v2 = 0u;
-    if (i < n) {
-      const int64_t item = perm ? (int64_t)perm[i] : i;
-      v = cmp_value(src, kind, item);
-      if (src2 && item >= 0) v2 = src2[item];
-    }
-    cnt += __popcll(__ballot((v | v2) != 0u));
-    nz += __popcll(__ballot(v != 0u));
-    bits += __popc(v);
+    cnt += __popcll(__ballot((v[k] | v2[k]) != 0u));
+    nz += __popcll(__ballot(v[k] != 0u));
+    bits += __popc(v[k]);
   }
   for (int o = 32; o > 0; o >>= 1) bits += __shfl_down(bits, o, 64);
   if (lane == 0) {
@@ -1471,8 +1510,9 @@ __global__ __launch_bounds__(CMP_THREADS) void k_compact_count(const void *src,
 // blocks before it (its output offset); block 0 also writes the totals
 // [0] selected items, [1] set bits, [2] items with src != 0, and the output
 // offset of every colour segment.  Integer sums: exact in any order.
+template <int KIND>
 __global__ __launch_bounds__(CMP_THREADS) void k_compact_scatter(
-    const void *src, const uint32_t *src2, int kind, const int32_t *perm, int64_t n,
+    const void *src, const uint32_t *src2, const int32_t *perm, int64_t n,
     const int32_t *counts, const int32_t *counts2, const int32_t *counts3, int nblk,
     const int32_t *colour_first_block, int n_col, int32_t *colour_off, int32_t *totals,
     int32_t *out) {
@@ -1480,6 +1520,10 @@ __global__ __launch_bounds__(CMP_THREADS) void k_compact_scatter(
   __shared__ int32_t s_r[3][CMP_THREADS];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t base = (int64_t)blockIdx.x * CMP_CHUNK;
+  // this thread's items first (their loads overlap the offset reduction)
+  int64_t item[CMP_ITEMS];
+  uint32_t vv[CMP_ITEMS], vv2[CMP_ITEMS];
+  cmp_load<KIND>(src, src2, perm, n, base, tid, item, vv, vv2);
   // offset of this block; block 0: the three totals
   {
     int32_t a = 0, b2 = 0, b3 = 0;
@@ -1524,15 +1568,9 @@ __global__ __launch_bounds__(CMP_THREADS) void k_compact_scatter(
         colour_off[c] = off;
       }
   }
+#pragma unroll
   for (int k = 0; k < CMP_ITEMS; ++k) {
-    const int64_t i = base + (int64_t)k * CMP_THREADS + tid;
-    int64_t item = -1;
-    uint32_t v = 0u;
-    if (i < n) {
-      item = perm ? (int64_t)perm[i] : i;
-      v = cmp_value(src, kind, item);
-      if (src2 && item >= 0) v |= src2[item];
-    }
+    const uint32_t v = vv[k] | vv2[k];
     const uint64_t b = __ballot(v != 0u);
     const int rank = __popcll(b & ((1ull << lane) - 1ull));
     if (lane == 0) s_w[wv] = __popcll(b);
@@ -1542,7 +1580,7 @@ __global__ __launch_bounds__(CMP_THREADS) void k_compact_scatter(
       if (w < wv) before += s_w[w];
       tot += s_w[w];
     }
-    if (v != 0u) out[run + before + rank] = (int32_t)item;
+    if (v != 0u) out[run + before + rank] = (int32_t)item[k];
     run += tot;
     __syncthreads();
   }
@@ -1924,13 +1962,20 @@ hipError_t launch_compact(Ctx &c, int kind, const void *src, const uint32_t *src
                           int32_t *totals) {
   const int nblk = ceil_div(n, CMP_CHUNK);
   if (nblk > c.cmp_cap) return hipErrorInvalidValue;
-  if (nblk > 0)
-    hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(CMP_THREADS), 0, c.stream, src, src2,
-                       kind, perm, n, c.cmp_counts, c.cmp_counts2, c.cmp_counts3);
-  // at least one block: block 0 writes the totals and colour offsets
-  hipLaunchKernelGGL(k_compact_scatter, dim3(nblk > 0 ? nblk : 1), dim3(CMP_THREADS), 0, c.stream,
-                     src, src2, kind, perm, n, c.cmp_counts, c.cmp_counts2, c.cmp_counts3, nblk,
-                     colour_first_block, n_col, colour_off, totals, out);
+#define CMP_LAUNCH(K)                                                                         \
+  if (nblk > 0)                                                                               \
+    hipLaunchKernelGGL((k_compact_count<K>), dim3(nblk), dim3(CMP_THREADS), 0, c.stream, src,  \
+                       src2, perm, n, c.cmp_counts, c.cmp_counts2, c.cmp_counts3);             \
+  /* at least one block: block 0 writes the totals and colour offsets */                      \
+  hipLaunchKernelGGL((k_compact_scatter<K>), dim3(nblk > 0 ? nblk : 1), dim3(CMP_THREADS), 0, \
+                     c.stream, src, src2, perm, n, c.cmp_counts, c.cmp_counts2, c.cmp_counts3, \
+                     nblk, colour_first_block, n_col, colour_off, totals, out)
+  if (kind == 0) {
+    CMP_LAUNCH(0);
+  } else {
+    CMP_LAUNCH(1);
+  }
+#undef CMP_LAUNCH
   return hipGetLastError();
 }
 
