@@ -1078,25 +1078,45 @@ __global__ __launch_bounds__(256) void k_force_gather(int64_t n_n, const int32_t
   const int64_t m = (int64_t)blockIdx.x * 256 + tid;
   double rr = 0.0, ff = 0.0, rc = 0.0;
   if (m < n_n) {
+    // the free mask and the load do not depend on the slots: issue them
+    // with the slot range, then the slots four at a time (unconditional
+    // loads from a clamped index, predicated additions in slot order)
+    const int k0 = n2e_ptr[m], k1 = n2e_ptr[m + 1];
+    bool fr[D];
+    double fl[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      fr[i] = freem[D * m + i] != 0;
+      fl[i] = f ? f[D * m + i] : 0.0;
+    }
     double s[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) s[i] = 0.0;
-    const int k1 = n2e_ptr[m + 1];
-    for (int64_t k = n2e_ptr[m]; k < k1; ++k) {
+    for (int k = k0; k < k1; k += 4) {
+      double v[4][D];
 #pragma unroll
-      for (int i = 0; i < D; ++i) s[i] += Fe[k * D + i];
+      for (int j = 0; j < 4; ++j) {
+        const int64_t kk = k + j < k1 ? k + j : k0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) v[j][i] = Fe[kk * D + i];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (k + j < k1) {
+#pragma unroll
+          for (int i = 0; i < D; ++i) s[i] += v[j][i];
+        }
     }
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       const int64_t dof = D * m + i;
       if (F_out) F_out[dof] = s[i];
-      const bool fr = freem[dof] != 0;
-      const double fv = (f && fr) ? f[dof] : 0.0;
-      const double r = fr ? fv - s[i] : 0.0;
+      const double fv = fr[i] ? fl[i] : 0.0;
+      const double r = fr[i] ? fv - s[i] : 0.0;
       if (r_out) r_out[dof] = r;
       rr += r * r;
       ff += fv * fv;
-      if (!fr) rc += s[i] * s[i];  // reaction at a Dirichlet dof
+      if (!fr[i]) rc += s[i] * s[i];  // reaction at a Dirichlet dof
     }
   }
   s_a[tid] = rr;
@@ -1386,11 +1406,31 @@ __global__ __launch_bounds__(256) void k_split_gather(int64_t n_n, const int32_t
     double s[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) s[i] = 0.0;
-    const int k1 = n2e_ptr[m + 1];
-    for (int64_t k = n2e_ptr[m]; k < k1; ++k) {
-      if (emask[slot_elem[k]] == 0u) continue;
+    // four slots at a time: element ids, their masks, then the vectors
+    // (unconditional loads from clamped indices, predicated additions in
+    // slot order)
+    const int k0 = n2e_ptr[m], k1 = n2e_ptr[m + 1];
+    for (int k = k0; k < k1; k += 4) {
+      int64_t kk[4];
+      int el[4];
+      uint32_t em[4];
+      double v[4][D];
 #pragma unroll
-      for (int i = 0; i < D; ++i) s[i] += Fp[k * D + i];
+      for (int j = 0; j < 4; ++j) kk[j] = k + j < k1 ? k + j : k0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) el[j] = slot_elem[kk[j]];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) em[j] = emask[el[j]];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < D; ++i) v[j][i] = Fp[kk[j] * D + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (k + j < k1 && em[j] != 0u) {
+#pragma unroll
+          for (int i = 0; i < D; ++i) s[i] += v[j][i];
+        }
     }
 #pragma unroll
     for (int i = 0; i < D; ++i) {
