@@ -279,7 +279,7 @@ hipError_t upload(T *d, const std::vector<T> &h, hipStream_t s) {
 void free_ctx(Ctx *c) {
   if (!c) return;
   void *ptrs[] = {c->coord, c->elem, c->freem, c->ref, c->bptr, c->bcol, c->bdiag, c->bpos,
-                  c->Ke, c->Ke32, c->Kt, c->epoch, c->n2e_ptr, c->fslot, c->slot_elem, c->Fp, c->ecol_perm,
+                  c->Ke, c->Ke32, c->Kt, c->epoch, c->bposs, c->n2e_ptr, c->fslot, c->slot_elem, c->Fp, c->ecol_perm,
                   c->d_colour_first_block, c->ep_s, c->beta_s, c->kappa_s, c->flag, c->desc,
                   c->Fe, c->em[0], c->em[1], c->plist, c->coff, c->ptotals, c->cmp_counts,
                   c->cmp_counts2, c->cmp_counts3, c->F, c->r, c->partials,
@@ -683,6 +683,25 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
         }
       }
   });
+  // position map with each row's columns in ascending global node order
+  // (the sorted scatter of quadrilaterals and 8-node hexahedra)
+  const bool sorted_scatter = ed.id == ET_Q1_2D || ed.id == ET_Q2_2D || ed.id == ET_Q2S_2D ||
+                              ed.id == ET_Q1_3D;
+  std::vector<int32_t> bposs;
+  if (sorted_scatter) {
+    bposs.resize((size_t)n_e * n_p * n_p);
+    parallel_for(n_e, [&](int64_t a, int64_t b) {
+      std::vector<int> ord(n_p);
+      for (int64_t e = a; e < b; ++e) {
+        std::iota(ord.begin(), ord.end(), 0);
+        std::sort(ord.begin(), ord.end(),
+                  [&](int x, int y) { return E[e * n_p + x] < E[e * n_p + y]; });
+        for (int p = 0; p < n_p; ++p)
+          for (int r = 0; r < n_p; ++r)
+            bposs[(e * n_p + p) * n_p + r] = bpos[(e * n_p + p) * n_p + ord[r]];
+      }
+    });
+  }
   // greedy colouring: elements of one colour share no node
   std::vector<int32_t> colour(n_e, -1);
   int n_col = 0;
@@ -736,6 +755,7 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   SETUP_HIP(dalloc(&c->bcol, nnzb));
   SETUP_HIP(dalloc(&c->bdiag, n_n));
   SETUP_HIP(dalloc(&c->bpos, n_e * n_p * n_p));
+  if (sorted_scatter) SETUP_HIP(dalloc(&c->bposs, n_e * n_p * n_p));
   SETUP_HIP(dalloc(&c->Ke, nnzb * dim * dim));
   if (opt.tangent_prec == EP_FP32) {
     SETUP_HIP(dalloc(&c->Ke32, nnzb * dim * dim));
@@ -793,6 +813,7 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   SETUP_HIP(upload(c->bcol, bcol, s));
   SETUP_HIP(upload(c->bdiag, bdiag, s));
   SETUP_HIP(upload(c->bpos, bpos, s));
+  if (sorted_scatter) SETUP_HIP(upload(c->bposs, bposs, s));
   SETUP_HIP(upload(c->n2e_ptr, n2e_ptr, s));
   SETUP_HIP(upload(c->fslot, fslot, s));
   SETUP_HIP(upload(c->slot_elem, slot_elem, s));

@@ -143,6 +143,9 @@ struct Ctx {
   int32_t *bcol = nullptr;     // [nnzb]
   int32_t *bdiag = nullptr;    // [n_n] block index of (m, m)
   int32_t *bpos = nullptr;     // [n_e][n_p][n_p] block index of (node p, node p')
+  // the same with the columns in ascending global node order (quadrilaterals
+  // and 8-node hexahedra: the sorted scatter), else unused
+  int32_t *bposs = nullptr;
   double *Ke = nullptr;        // [nnzb][dim][dim]
   float *Ke32 = nullptr;
   void *Kt = nullptr;          // double or float, [nnzb][dim][dim]

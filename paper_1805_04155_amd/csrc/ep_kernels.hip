@@ -413,6 +413,7 @@ struct KA {
   int colour;
   int64_t k0, k1;      // host segment bounds when off == nullptr
   const int32_t *bpos;
+  const int32_t *bposs;  // position map in ascending-node column order (sorted scatter)
   const double *Ke;
   const float *Ke32;
   void *Kt;
@@ -553,14 +554,26 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
   // software pipeline over the elements of this block: the list entry, mask
   // and node ids of the next element are loaded while the current one is
   // processed
+  // (sorted scatter: also the block positions of the next element, so that
+  // the freshness stamps can be read as soon as an element starts)
+  constexpr int NIP = SORTED ? NSLOT : 1;
   int64_t k = k0 + blockIdx.x;
   int e_n = k < k1 ? a.list[k] : -1;
   uint32_t m_n = (e_n >= 0 && !a.elastic) ? a.emask[e_n] : 0xffffffffu;
   int node_n = (e_n >= 0 && tid < NP) ? a.elem[(int64_t)e_n * NP + tid] : 0;
+  int32_t ip_n[NIP];
+#pragma unroll
+  for (int sl = 0; sl < NIP; ++sl) {
+    const int t = tid + sl * BS;
+    ip_n[sl] = (SORTED && e_n >= 0 && t < NB2) ? a.bposs[(int64_t)e_n * NB2 + t] : 0;
+  }
   for (; k < k1; k += gridDim.x) {
     const int e = e_n;
     const uint32_t mask = m_n & qmask;
     const int node_cur = node_n;
+    int32_t ip_cur[NIP];
+#pragma unroll
+    for (int sl = 0; sl < NIP; ++sl) ip_cur[sl] = ip_n[sl];
     {
       const int64_t kn = k + gridDim.x;
       e_n = kn < k1 ? a.list[kn] : -1;
@@ -568,6 +581,11 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
     if (e < 0) {  // padding of the colour-major order (uniform)
       m_n = (e_n >= 0 && !a.elastic) ? a.emask[e_n] : 0xffffffffu;
       node_n = (e_n >= 0 && tid < NP) ? a.elem[(int64_t)e_n * NP + tid] : 0;
+#pragma unroll
+      for (int sl = 0; sl < NIP; ++sl) {
+        const int t = tid + sl * BS;
+        ip_n[sl] = (SORTED && e_n >= 0 && t < NB2) ? a.bposs[(int64_t)e_n * NB2 + t] : 0;
+      }
       continue;
     }
     const int nq = __popc(mask);
@@ -576,6 +594,14 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
     int64_t i1[SORTED ? NSLOT : NBT], i2[SORTED ? 1 : NBT];
     bool f1[SORTED ? NSLOT : NBT], f2[SORTED ? 1 : NBT];
     if constexpr (SORTED) {
+      // slot t = p * NP + r: block (p, r-th node by global id), position
+      // prefetched; its stamp is read at once
+#pragma unroll
+      for (int sl = 0; sl < NSLOT; ++sl) {
+        const bool on = tid + sl * BS < NB2;
+        i1[sl] = on ? (int64_t)ip_cur[sl] : 0;
+        f1[sl] = (!a.elastic && on) ? (a.epoch[i1[sl]] != a.cur) : false;
+      }
       __syncthreads();  // LDS of the previous element is no longer read
       if (tid < NP) s_node[tid] = node_cur;
       __syncthreads();
@@ -587,18 +613,6 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
         s_ord[r] = tid;
       }
       __syncthreads();
-#pragma unroll
-      for (int sl = 0; sl < NSLOT; ++sl) {
-        const int t = tid + sl * BS;
-        const bool on = t < NB2;
-        const int p = on ? t / NP : 0, pc = on ? s_ord[t - (t / NP) * NP] : 0;
-        i1[sl] = on ? (int64_t)a.bpos[(int64_t)e * NB2 + p * NP + pc] : 0;
-      }
-#pragma unroll
-      for (int sl = 0; sl < NSLOT; ++sl) {
-        const bool on = tid + sl * BS < NB2;
-        f1[sl] = (!a.elastic && on) ? (a.epoch[i1[sl]] != a.cur) : false;
-      }
     } else {
 #pragma unroll
       for (int j = 0; j < NBT; ++j) {
@@ -731,6 +745,11 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
     }
     m_n = (e_n >= 0 && !a.elastic) ? a.emask[e_n] : 0xffffffffu;
     node_n = (e_n >= 0 && tid < NP) ? a.elem[(int64_t)e_n * NP + tid] : 0;
+#pragma unroll
+    for (int sl = 0; sl < NIP; ++sl) {
+      const int t = tid + sl * BS;
+      ip_n[sl] = (SORTED && e_n >= 0 && t < NB2) ? a.bposs[(int64_t)e_n * NB2 + t] : 0;
+    }
     // base values (K_elast for blocks not yet written in this assembly, else
     // K_tangent) plus the element's contribution
     if constexpr (SORTED) {
@@ -2034,6 +2053,7 @@ static hipError_t elastic_et(Ctx &c) {
     a.k0 = (int64_t)c.colour_first_block[col] * CMP_CHUNK;
     a.k1 = a.k0 + c.colour_size[col];
     a.bpos = c.bpos;
+    a.bposs = c.bposs;
     a.Kt = c.Ke;
     a.elastic = 1;
     a.G = c.mat.G;
@@ -2063,6 +2083,7 @@ static hipError_t colour_et(Ctx &c, int colour, int epoch) {
   a.off = c.coff;
   a.colour = colour;
   a.bpos = c.bpos;
+  a.bposs = c.bposs;
   a.Ke = c.Ke;
   a.Ke32 = c.Ke32;
   a.Kt = c.Kt;
