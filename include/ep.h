@@ -268,13 +268,19 @@ ep_status ep_apply_tangent(ep_ctx *ctx, const double *x, double *y);
 ep_status ep_pcg(ep_ctx *ctx, const double *b, double *x, double rtol, int32_t max_it,
                  int32_t *its, double *relres);
 
-/* Per-kernel timing with HIP events recorded on the context's stream
- * around every launch of the named kernels.  ep_profile_read returns the
- * summed duration (ms) and the launch count of kernel id k (0 constitutive,
- * 1 compaction, 2 split-form element terms and their node sum inside PCG,
- * 3 colour assembly, 4 force gather, 5 SpMV, 6 PCG vector update,
- * 7 K_elast assembly of ep_assemble_elastic) and resets it.  Synchronises. */
-ep_status ep_profile(ep_ctx *ctx, int32_t enable);
+/* Per-kernel timing with HIP events on the context's stream: the events
+ * travel with the kernel dispatches (start of the first kernel, end of the
+ * last kernel of each timed call), so no marker command separates the
+ * kernels.  mask selects the kernel ids to time (bit k for id k; 0 = off,
+ * EP_PROFILE_ALL = every id): 0 constitutive, 1 compaction, 2 split-form
+ * element terms and their node sum inside PCG, 3 colour assembly (one
+ * count per colour launch), 4 force gather, 5 SpMV, 6 PCG vector update,
+ * 7 K_elast assembly of ep_assemble_elastic.  While any id is timed, PCG
+ * launches its kernels one by one instead of replaying a graph.
+ * ep_profile_read returns the summed duration (ms) and the count of kernel
+ * id k and resets both.  Both calls synchronise. */
+#define EP_PROFILE_ALL 0xff
+ep_status ep_profile(ep_ctx *ctx, int32_t mask);
 ep_status ep_profile_read(ep_ctx *ctx, int32_t k, double *ms, int64_t *count);
 
 /* ------------------------------------------------------------------------

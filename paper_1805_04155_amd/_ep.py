@@ -295,8 +295,16 @@ def ep_pcg(ctx, b, x, rtol, max_it):
     return st, its.value, rel.value
 
 
-def ep_profile(ctx, enable):
-    _check(ctx, lib().ep_profile(ctx, int(enable)))
+EP_PROFILE_ALL = 0xFF
+
+
+def ep_profile(ctx, enable, kernels=None):
+    """Turns kernel timing on (every kernel id, or only the names in
+    `kernels`, keys of PROF) or off."""
+    mask = 0
+    if enable:
+        mask = EP_PROFILE_ALL if kernels is None else sum(1 << PROF[k] for k in set(kernels))
+    _check(ctx, lib().ep_profile(ctx, mask))
 
 
 def ep_profile_read(ctx, k):

@@ -305,7 +305,7 @@ void free_ctx(Ctx *c) {
 // profiling
 // ---------------------------------------------------------------------------
 int Ctx::prof_begin(int id) {
-  if (!prof) return -1;
+  if (!((prof_mask >> id) & 1u)) return -1;
   hipEvent_t a, b;
   if (event_pool.size() >= 2) {
     a = event_pool.back();
@@ -313,17 +313,26 @@ int Ctx::prof_begin(int id) {
     b = event_pool.back();
     event_pool.pop_back();
   } else {
-    if (hipEventCreate(&a) != hipSuccess) return -1;
-    if (hipEventCreate(&b) != hipSuccess) return -1;
+    // no system-scope fence: the times are read after a stream
+    // synchronisation, which makes every result visible anyway
+    if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess) return -1;
+    if (hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess) return -1;
   }
-  (void)hipEventRecord(a, stream);
   pending.push_back({id, a, b});
+  launch_start = a;
+  launch_stop = b;
   return (int)pending.size() - 1;
 }
 
 void Ctx::prof_end(int token) {
   if (token < 0) return;
-  (void)hipEventRecord(pending[token].b, stream);
+  if (launch_start) {
+    // no kernel was launched in the section: nothing to time
+    event_pool.push_back(pending[token].a);
+    event_pool.push_back(pending[token].b);
+    pending.erase(pending.begin() + token);
+  }
+  launch_start = launch_stop = nullptr;
 }
 
 void Ctx::prof_collect() {
@@ -416,7 +425,7 @@ double relative_residual(const double *norms_h) {
 // iterations alternate two search-direction buffers, so an even chunk ends
 // where it started); otherwise the kernels are launched one by one.
 ep_status pcg_chunk(Ctx *c, double *x, int n) {
-  if (c->prof || n < 2 || n % 2 != 0) {
+  if (c->prof_mask || n < 2 || n % 2 != 0) {
     for (int k = 0; k < n; ++k) HIPC(launch_pcg_iteration(*c, x));
     return EP_OK;
   }
@@ -1093,11 +1102,11 @@ ep_status ep_pcg(ep_ctx *ctx, const double *b, double *x, double rtol, int32_t m
   return st;
 }
 
-ep_status ep_profile(ep_ctx *ctx, int32_t enable) {
+ep_status ep_profile(ep_ctx *ctx, int32_t mask) {
   CHECK_CTX(ctx);
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   c->prof_collect();
-  c->prof = enable != 0;
+  c->prof_mask = (uint32_t)mask & EP_PROFILE_ALL;
   return EP_OK;
 }
 

@@ -2,6 +2,7 @@
 // HIP kernels.  Not part of the C ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -220,16 +221,32 @@ struct Ctx {
   double *wu_pred = nullptr, *wu_warm = nullptr;  // [n_dof]
   double E = 0.0;
 
-  // profiling
-  bool prof = false;
+  // profiling: a profiled section hands its two events to the kernel
+  // launches inside it (EP_LAUNCH); the first launch records the start
+  // time, every launch the stop time
+  uint32_t prof_mask = 0;  // bit k: time kernel id k
   struct Pending { int id; hipEvent_t a, b; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;
+  hipEvent_t launch_start = nullptr, launch_stop = nullptr;
   double prof_ms[PROF_COUNT] = {0};
   int64_t prof_n[PROF_COUNT] = {0};
   int prof_begin(int id);
   void prof_end(int token);
   void prof_collect();
+  hipEvent_t take_start() {
+    hipEvent_t e = launch_start;
+    launch_start = nullptr;
+    return e;
+  }
 };
+
+// Kernel launch on the context's stream (hipLaunchKernelGGL's arguments with
+// the context in place of the stream).  Inside a profiled section the
+// section's events travel with the dispatch itself, so timing adds no marker
+// command between kernels.
+#define EP_LAUNCH(K, G, B, SHM, C, ...)                                                   \
+  hipExtLaunchKernelGGL(K, G, B, SHM, (C).stream, (C).take_start(), (C).launch_stop, 0, \
+                        __VA_ARGS__)
 
 }  // namespace ep

@@ -1956,7 +1956,7 @@ static hipError_t constitutive_et(Ctx &c, const ConstArgs &ca) {
   const int grid = ceil_div(c.n_e, EPB);
   if (grid == 0) return hipSuccess;
 #define CONST_LAUNCH(MODEL, LM) \
-  hipLaunchKernelGGL((k_constitutive<ETID, MODEL, LM>), dim3(grid), dim3(CT), 0, c.stream, a)
+  EP_LAUNCH((k_constitutive<ETID, MODEL, LM>), dim3(grid), dim3(CT), 0, c, a)
   if (c.mat.model == EP_VM) {
     if (ca.learned == 1) CONST_LAUNCH(EP_VM, 1);
     else if (ca.learned == 2) CONST_LAUNCH(EP_VM, 2);
@@ -1990,8 +1990,8 @@ template <int ETID>
 static hipError_t geometry_et(Ctx &c, double *dphi, double *w, int32_t *bad) {
   const int64_t n = c.n_int;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_geometry<ETID>), dim3(ceil_div(n, 128)), dim3(128), 0, c.stream, c.coord,
-                     c.elem, c.ref, c.n_n, c.n_e, dphi, w, bad);
+  EP_LAUNCH((k_geometry<ETID>), dim3(ceil_div(n, 128)), dim3(128), 0, c, c.coord,
+            c.elem, c.ref, c.n_n, c.n_e, dphi, w, bad);
   return hipGetLastError();
 }
 hipError_t launch_geometry(Ctx &c, double *dphi, double *w, int32_t *bad) {
@@ -2002,16 +2002,16 @@ hipError_t launch_force_gather(Ctx &c, const double *f, double *F_out, double *r
                                double *partials, int nblk) {
   if (nblk == 0) return hipSuccess;
   if (c.dim == 2)
-    hipLaunchKernelGGL((k_force_gather<2>), dim3(nblk), dim3(256), 0, c.stream, c.n_n,
-                       c.n2e_ptr, c.Fe, f, c.freem, F_out, r_out, partials);
+    EP_LAUNCH((k_force_gather<2>), dim3(nblk), dim3(256), 0, c, c.n_n,
+              c.n2e_ptr, c.Fe, f, c.freem, F_out, r_out, partials);
   else
-    hipLaunchKernelGGL((k_force_gather<3>), dim3(nblk), dim3(256), 0, c.stream, c.n_n,
-                       c.n2e_ptr, c.Fe, f, c.freem, F_out, r_out, partials);
+    EP_LAUNCH((k_force_gather<3>), dim3(nblk), dim3(256), 0, c, c.n_n,
+              c.n2e_ptr, c.Fe, f, c.freem, F_out, r_out, partials);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce(Ctx &c, const double *partials, int nblk, int width, double *out) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, c.stream, partials, nblk, width, out);
+  EP_LAUNCH(k_reduce, dim3(1), dim3(256), 0, c, partials, nblk, width, out);
   return hipGetLastError();
 }
 
@@ -2021,14 +2021,14 @@ hipError_t launch_compact(Ctx &c, int kind, const void *src, const uint32_t *src
                           int32_t *totals) {
   const int nblk = ceil_div(n, CMP_CHUNK);
   if (nblk > c.cmp_cap) return hipErrorInvalidValue;
-#define CMP_LAUNCH(K)                                                                         \
-  if (nblk > 0)                                                                               \
-    hipLaunchKernelGGL((k_compact_count<K>), dim3(nblk), dim3(CMP_THREADS), 0, c.stream, src,  \
-                       src2, perm, n, c.cmp_counts, c.cmp_counts2, c.cmp_counts3);             \
-  /* at least one block: block 0 writes the totals and colour offsets */                      \
-  hipLaunchKernelGGL((k_compact_scatter<K>), dim3(nblk > 0 ? nblk : 1), dim3(CMP_THREADS), 0, \
-                     c.stream, src, src2, perm, n, c.cmp_counts, c.cmp_counts2, c.cmp_counts3, \
-                     nblk, colour_first_block, n_col, colour_off, totals, out)
+#define CMP_LAUNCH(K)                                                                      \
+  if (nblk > 0)                                                                            \
+    EP_LAUNCH((k_compact_count<K>), dim3(nblk), dim3(CMP_THREADS), 0, c, src, src2, perm, n, \
+              c.cmp_counts, c.cmp_counts2, c.cmp_counts3);                                 \
+  /* at least one block: block 0 writes the totals and colour offsets */                   \
+  EP_LAUNCH((k_compact_scatter<K>), dim3(nblk > 0 ? nblk : 1), dim3(CMP_THREADS), 0, c, src, \
+            src2, perm, n, c.cmp_counts, c.cmp_counts2, c.cmp_counts3, nblk,                \
+            colour_first_block, n_col, colour_off, totals, out)
   if (kind == 0) {
     CMP_LAUNCH(0);
   } else {
@@ -2061,7 +2061,7 @@ static hipError_t elastic_et(Ctx &c) {
     const int64_t cnt = a.k1 - a.k0;
     if (cnt == 0) continue;
     const int grid = (int)(cnt < 65536 ? cnt : 65536);
-    hipLaunchKernelGGL((k_assemble<ETID, double>), dim3(grid), dim3(Cfg::BS), 0, c.stream, a);
+    EP_LAUNCH((k_assemble<ETID, double>), dim3(grid), dim3(Cfg::BS), 0, c, a);
     RT(hipGetLastError());
   }
   return hipSuccess;
@@ -2104,7 +2104,7 @@ static hipError_t colour_et(Ctx &c, int colour, int epoch) {
     if (c.opt.local_prec == EP_BF16 || c.opt.local_prec == EP_FP32) {
       const bool bf = c.opt.local_prec == EP_BF16;
 #define MF(VT, BF) \
-  hipLaunchKernelGGL((k_assemble_mfma<ETID, VT, BF>), dim3(grid), dim3(256), 0, c.stream, a)
+  EP_LAUNCH((k_assemble_mfma<ETID, VT, BF>), dim3(grid), dim3(256), 0, c, a)
       if (f32) {
         if (bf) MF(float, true); else MF(float, false);
       } else {
@@ -2115,9 +2115,9 @@ static hipError_t colour_et(Ctx &c, int colour, int epoch) {
     }
   }
   if (f32)
-    hipLaunchKernelGGL((k_assemble<ETID, float>), dim3(gpipe), dim3(Cfg::BS), 0, c.stream, a);
+    EP_LAUNCH((k_assemble<ETID, float>), dim3(gpipe), dim3(Cfg::BS), 0, c, a);
   else
-    hipLaunchKernelGGL((k_assemble<ETID, double>), dim3(gpipe), dim3(Cfg::BS), 0, c.stream, a);
+    EP_LAUNCH((k_assemble<ETID, double>), dim3(gpipe), dim3(Cfg::BS), 0, c, a);
   return hipGetLastError();
 }
 hipError_t launch_colour_assembly(Ctx &c, int colour, int epoch) {
@@ -2144,8 +2144,8 @@ hipError_t launch_csr_expand(Ctx &c, int which, int32_t *row_ptr, int32_t *col_i
   const bool f32 = which == 1 && c.opt.tangent_prec == EP_FP32;
   const void *v = which == 1 ? c.Kt : (const void *)c.Ke;
 #define CSRX(D, VT)                                                                          \
-  hipLaunchKernelGGL((k_csr_expand<D, VT>), dim3(grid), dim3(256), 0, c.stream, c.n_n, c.nnzb, \
-                     c.bptr, c.bcol, (const VT *)v, row_ptr, col_idx, val)
+  EP_LAUNCH((k_csr_expand<D, VT>), dim3(grid), dim3(256), 0, c, c.n_n, c.nnzb, \
+            c.bptr, c.bcol, (const VT *)v, row_ptr, col_idx, val)
   if (c.dim == 2) {
     if (f32) CSRX(2, float); else CSRX(2, double);
   } else {
@@ -2160,8 +2160,8 @@ static hipError_t pos_et(Ctx &c, int32_t *pos) {
   using T = Et<ETID>;
   const int64_t n = c.n_e * T::NP * T::NP;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_pos_expand<ETID>), dim3(ceil_div(n, 256)), dim3(256), 0, c.stream, c.n_e,
-                     c.elem, c.bptr, c.bpos, pos);
+  EP_LAUNCH((k_pos_expand<ETID>), dim3(ceil_div(n, 256)), dim3(256), 0, c, c.n_e,
+            c.elem, c.bptr, c.bpos, pos);
   return hipGetLastError();
 }
 hipError_t launch_pos_expand(Ctx &c, int32_t *pos) { DISPATCH_ET(pos_et, c, pos) }
@@ -2190,9 +2190,9 @@ static hipError_t split_apply_et(Ctx &c, int mode, const double *x, const double
   const int grid = ceil_div(c.n_e, EPB);
   if (grid == 0) return hipSuccess;
   if (mode == 0)
-    hipLaunchKernelGGL((k_split_apply<ETID, 0>), dim3(grid), dim3(CT), 0, c.stream, a);
+    EP_LAUNCH((k_split_apply<ETID, 0>), dim3(grid), dim3(CT), 0, c, a);
   else
-    hipLaunchKernelGGL((k_split_apply<ETID, 1>), dim3(grid), dim3(CT), 0, c.stream, a);
+    EP_LAUNCH((k_split_apply<ETID, 1>), dim3(grid), dim3(CT), 0, c, a);
   return hipGetLastError();
 }
 hipError_t launch_split_apply(Ctx &c, int mode, const double *x, const double *sc) {
@@ -2205,9 +2205,9 @@ hipError_t launch_split_gather(Ctx &c, int mode, double *y, const double *p, dou
   *nblk = grid;
   if (grid == 0) return hipSuccess;
 #define SG(D, M)                                                                             \
-  hipLaunchKernelGGL((k_split_gather<D, M>), dim3(grid), dim3(256), 0, c.stream, c.n_n,      \
-                     c.n2e_ptr, c.slot_elem, c.em[c.em_cur], c.Fp, c.freem, y, p, partials, \
-                     sc, c.bdiag, c.Ke, c.dinv)
+  EP_LAUNCH((k_split_gather<D, M>), dim3(grid), dim3(256), 0, c, c.n_n,      \
+            c.n2e_ptr, c.slot_elem, c.em[c.em_cur], c.Fp, c.freem, y, p, partials, \
+            sc, c.bdiag, c.Ke, c.dinv)
   if (c.dim == 2) {
     if (mode == 0) SG(2, 0); else SG(2, 1);
   } else {
@@ -2226,8 +2226,8 @@ hipError_t launch_diag_inv(Ctx &c) {
   const int grid = ceil_div(c.n_dof, 256);
   const bool f32 = c.opt.tangent_prec == EP_FP32;
 #define DG(D, VT)                                                                               \
-  hipLaunchKernelGGL((k_diag_inv<D, VT>), dim3(grid), dim3(256), 0, c.stream, c.n_n, c.bdiag, \
-                     (const VT *)c.Kt, c.freem, c.dinv)
+  EP_LAUNCH((k_diag_inv<D, VT>), dim3(grid), dim3(256), 0, c, c.n_n, c.bdiag, \
+            (const VT *)c.Kt, c.freem, c.dinv)
   if (c.dim == 2) {
     if (f32) DG(2, float); else DG(2, double);
   } else {
@@ -2251,8 +2251,8 @@ static hipError_t spmv_launch(Ctx &c, const void *vals, const double *x, double 
   *nblk = grid;
   if (grid == 0) return hipSuccess;
 #define SPG(GG)                                                                              \
-  hipLaunchKernelGGL((k_spmv<D, VT, GG>), dim3(grid), dim3(256), 0, c.stream, c.n_n, c.bptr, \
-                     c.bcol, (const VT *)vals, x, c.freem, y, partials, sc, x + 1, x + 2)
+  EP_LAUNCH((k_spmv<D, VT, GG>), dim3(grid), dim3(256), 0, c, c.n_n, c.bptr, \
+            c.bcol, (const VT *)vals, x, c.freem, y, partials, sc, x + 1, x + 2)
   switch (G) {
     case 4: SPG(4); break;
     case 8: SPG(8); break;
@@ -2291,8 +2291,8 @@ hipError_t launch_apply_split(Ctx &c, const double *x, double *y) {
 hipError_t launch_pcg_init(Ctx &c, const double *b, double *x) {
   const int grid = ceil_div(c.n_dof, 256);
   c.pcur = 0;
-  hipLaunchKernelGGL(k_pcg_init, dim3(grid), dim3(256), 0, c.stream, c.n_dof, b, c.freem, x, c.r,
-                     c.pz, c.pp[0], c.dinv, c.partials);
+  EP_LAUNCH(k_pcg_init, dim3(grid), dim3(256), 0, c, c.n_dof, b, c.freem, x, c.r,
+            c.pz, c.pp[0], c.dinv, c.partials);
   RT(hipGetLastError());
   return hipSuccess;
 }
@@ -2307,8 +2307,8 @@ hipError_t launch_pcg_iteration(Ctx &c, double *x) {
   const bool split = c.opt.operator_form == EP_OPERATOR_SPLIT;
   // p = z + beta p_old as a vector pass, so that the product gathers one
   // vector (beta = 0 at the first iteration)
-  hipLaunchKernelGGL(k_pcg_direction, dim3(grid), dim3(256), 0, c.stream, c.n_dof, c.pz, pold,
-                     pnew, c.sc);
+  EP_LAUNCH(k_pcg_direction, dim3(grid), dim3(256), 0, c, c.n_dof, c.pz, pold,
+            pnew, c.sc);
   RT(hipGetLastError());
   RT(spmv_any(c, split, pnew, c.pq, split ? nullptr : c.partials, c.sc, &nblk));
   c.prof_end(tok);
@@ -2319,14 +2319,14 @@ hipError_t launch_pcg_iteration(Ctx &c, double *x) {
     RT(launch_split_gather(c, 0, c.pq, pnew, c.partials, c.sc, &nblk));
     c.prof_end(tok);
   }
-  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(256), 0, c.stream, c.partials, nblk, c.sc);
+  EP_LAUNCH(k_pcg_alpha, dim3(1), dim3(256), 0, c, c.partials, nblk, c.sc);
   RT(hipGetLastError());
   tok = c.prof_begin(PROF_PCGVEC);
-  hipLaunchKernelGGL(k_pcg_update, dim3(grid), dim3(256), 0, c.stream, c.n_dof, x, pnew, c.r,
-                     c.pq, c.pz, c.dinv, c.sc, c.partials);
+  EP_LAUNCH(k_pcg_update, dim3(grid), dim3(256), 0, c, c.n_dof, x, pnew, c.r,
+            c.pq, c.pz, c.dinv, c.sc, c.partials);
   c.prof_end(tok);
   RT(hipGetLastError());
-  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(256), 0, c.stream, c.partials, grid, c.sc, 0, 0.0);
+  EP_LAUNCH(k_pcg_beta, dim3(1), dim3(256), 0, c, c.partials, grid, c.sc, 0, 0.0);
   RT(hipGetLastError());
   c.pcur = 1 - c.pcur;
   return hipSuccess;
@@ -2334,21 +2334,21 @@ hipError_t launch_pcg_iteration(Ctx &c, double *x) {
 
 hipError_t launch_pcg_beta_init(Ctx &c, double rtol) {
   const int grid = ceil_div(c.n_dof, 256);
-  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(256), 0, c.stream, c.partials, grid, c.sc, 1, rtol);
+  EP_LAUNCH(k_pcg_beta, dim3(1), dim3(256), 0, c, c.partials, grid, c.sc, 1, rtol);
   return hipGetLastError();
 }
 
 hipError_t launch_axpy_free(Ctx &c, const double *du, double *u) {
   if (c.n_dof == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_axpy_free, dim3(ceil_div(c.n_dof, 256)), dim3(256), 0, c.stream, c.n_dof,
-                     du, c.freem, u);
+  EP_LAUNCH(k_axpy_free, dim3(ceil_div(c.n_dof, 256)), dim3(256), 0, c, c.n_dof,
+            du, c.freem, u);
   return hipGetLastError();
 }
 
 hipError_t launch_extrapolate(Ctx &c, const double *u, const double *u2, double t, double *out) {
   if (c.n_dof == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_extrapolate, dim3(ceil_div(c.n_dof, 256)), dim3(256), 0, c.stream, c.n_dof,
-                     u, u2, t, c.freem, out);
+  EP_LAUNCH(k_extrapolate, dim3(ceil_div(c.n_dof, 256)), dim3(256), 0, c, c.n_dof,
+            u, u2, t, c.freem, out);
   return hipGetLastError();
 }
 
