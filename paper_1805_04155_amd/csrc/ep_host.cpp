@@ -318,7 +318,7 @@ int Ctx::prof_begin(int id) {
     if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess) return -1;
     if (hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess) return -1;
   }
-  pending.push_back({id, a, b});
+  pending.push_back({id, a, b, 1});
   launch_start = a;
   launch_stop = b;
   return (int)pending.size() - 1;
@@ -342,7 +342,7 @@ void Ctx::prof_collect() {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, pd.a, pd.b) == hipSuccess) {
       prof_ms[pd.id] += ms;
-      prof_n[pd.id] += 1;
+      prof_n[pd.id] += pd.count;
     }
     event_pool.push_back(pd.a);
     event_pool.push_back(pd.b);
@@ -391,11 +391,23 @@ ep_status do_assemble(Ctx *c) {
     return EP_ESTATE;
   }
   const int epoch = ++c->epoch_counter;
+  // one timed section over the colour launches: the start event travels with
+  // the first launch and the stop event with the last, and the section
+  // counts one per launch
+  int last = -1, n_launch = 0;
+  for (int col = 0; col < c->n_col; ++col)
+    if (c->colour_size[col] > 0) {
+      last = col;
+      ++n_launch;
+    }
+  const int tok = c->prof_begin(PROF_ASSEMBLE);
+  const hipEvent_t stop = c->launch_stop;
+  if (tok >= 0) c->pending[tok].count = n_launch;
   for (int col = 0; col < c->n_col; ++col) {
-    const int tok = c->prof_begin(PROF_ASSEMBLE);
+    c->launch_stop = col == last ? stop : nullptr;
     HIPC(launch_colour_assembly(*c, col, epoch));
-    c->prof_end(tok);
   }
+  c->prof_end(tok);
   c->em_asm = c->em_cur;
   return EP_OK;
 }

@@ -225,7 +225,7 @@ struct Ctx {
   // launches inside it (EP_LAUNCH); the first launch records the start
   // time, every launch the stop time
   uint32_t prof_mask = 0;  // bit k: time kernel id k
-  struct Pending { int id; hipEvent_t a, b; };
+  struct Pending { int id; hipEvent_t a, b; int count; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;
   hipEvent_t launch_start = nullptr, launch_stop = nullptr;
