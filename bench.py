@@ -80,10 +80,11 @@ def kernel_bytes(mesh, mat, counts, tangent_bytes):
         # their node-order slots, mask
         "constitutive": 2 * 8 * n_dof + 4 * NP * n_e + state * n_int + n_int
         + 8 * ndesc * pi + (8 * D + 4) * NP * n_e + 4 * n_e,
-        # per listed element: position map, epoch read + write, base value
-        # read, tangent write, mask; per plastic element its connectivity and
-        # coordinates; per plastic point its tangent descriptor
-        "assembly": listed * (blk * (4 + 8 + 2 * D * D * s) + 4) + pe * NP * (4 + 8 * D)
+        # per listed element: position map, one-byte stamp read + write, base
+        # value read, tangent write, mask; per plastic element its
+        # connectivity and coordinates; per plastic point its tangent
+        # descriptor
+        "assembly": listed * (blk * (4 + 2 + 2 * D * D * s) + 4) + pe * NP * (4 + 8 * D)
         + 8 * ndesc * pi,
         # colour-major order and two masks read, list written
         "compaction": counts["n_perm"] * 4 + 8 * n_e + 4 * listed,

@@ -390,6 +390,13 @@ ep_status do_assemble(Ctx *c) {
     c->err = "ep_assemble_tangent: no constitutive evaluation since setup or commit";
     return EP_ESTATE;
   }
+  // one-byte stamps: before the counter passes 255 every stamp is cleared
+  // (a block without this assembly's stamp starts from K_elast, so clearing
+  // is always safe)
+  if (c->epoch_counter == 255) {
+    HIPC(hipMemsetAsync(c->epoch, 0, std::max<int64_t>(c->nnzb, 1), c->stream));
+    c->epoch_counter = 0;
+  }
   const int epoch = ++c->epoch_counter;
   // one timed section over the colour launches: the start event travels with
   // the first launch and the stop event with the last, and the section
@@ -845,7 +852,7 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   SETUP_HIP(hipMemsetAsync(c->kappa_s, 0, sizeof(double) * n_int, s));
   for (int k = 0; k < 2; ++k)
     SETUP_HIP(hipMemsetAsync(c->em[k], 0, sizeof(uint32_t) * std::max<int64_t>(n_e, 1), s));
-  SETUP_HIP(hipMemsetAsync(c->epoch, 0, sizeof(int32_t) * std::max<int64_t>(nnzb, 1), s));
+  SETUP_HIP(hipMemsetAsync(c->epoch, 0, std::max<int64_t>(nnzb, 1), s));
   SETUP_HIP(hipMemsetAsync(c->Ke, 0, sizeof(double) * std::max<int64_t>(1, nnzb * dim * dim), s));
   SETUP_HIP(hipMemsetAsync(c->ptotals, 0, sizeof(int32_t) * 8, s));
   SETUP_HIP(hipMemsetAsync(c->coff, 0, sizeof(int32_t) * (n_col + 1), s));

@@ -150,7 +150,7 @@ struct Ctx {
   double *Ke = nullptr;        // [nnzb][dim][dim]
   float *Ke32 = nullptr;
   void *Kt = nullptr;          // double or float, [nnzb][dim][dim]
-  int32_t *epoch = nullptr;    // [nnzb]
+  uint8_t *epoch = nullptr;    // [nnzb] assembly stamp of each block (1..255, 0 = none)
   int epoch_counter = 0;
 
   // element force vectors are stored node by node: the entries of node m

@@ -417,8 +417,8 @@ struct KA {
   const double *Ke;
   const float *Ke32;
   void *Kt;
-  int32_t *epoch;
-  int cur;
+  uint8_t *epoch;  // stamp of the last assembly that wrote each block
+  int cur;         // this assembly's stamp, 1..255
   int elastic;
   double G, K;
 };
@@ -771,7 +771,7 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
           for (int i = 0; i < D * D; ++i) v[i] += kb[i];
         }
         block_store<D>(Kt + idx * D * D, v);
-        if (!a.elastic) a.epoch[idx] = a.cur;
+        if (!a.elastic) a.epoch[idx] = (uint8_t)a.cur;
       }
     } else {
 #pragma unroll
@@ -801,7 +801,7 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
 #pragma unroll
             for (int cc = 0; cc < D; ++cc)
               dst[r * D + cc] = (VT)(base[r * D + cc] + (side == 0 ? acc[j][r * D + cc] : acc[j][cc * D + r]));
-          if (!a.elastic) a.epoch[idx] = a.cur;
+          if (!a.elastic) a.epoch[idx] = (uint8_t)a.cur;
         }
       }
     }
@@ -1076,7 +1076,7 @@ __global__ __launch_bounds__(256) void k_assemble_mfma(KA a) {
 #pragma unroll
           for (int c3 = 0; c3 < 3; ++c3)
             dst[r3 * 3 + c3] = (VT)(base[r3 * 3 + c3] + (side == 0 ? acc[j][r3 * 3 + c3] : acc[j][c3 * 3 + r3]));
-        a.epoch[idx] = a.cur;
+        a.epoch[idx] = (uint8_t)a.cur;
       }
     }
   }

@@ -278,3 +278,33 @@ def test_split_apply_fp32_storage():
         assert np.abs(y - yo).max() > 1e-12 * scale  # the FP32 values are really used
     finally:
         ctx.close()
+
+
+def test_stamp_wraparound():
+    """The one-byte assembly stamps are cleared every 255 assemblies: over
+    600 assemblies with changing plastic sets, K_tangent equals a fresh
+    context's first assembly at the same displacement (equal values: the
+    formerly plastic elements add exact zeros)."""
+    mesh, free, mat, u0, (ep, beta, kappa) = make_case("q2_2d_dp")
+    state = (ep, None, kappa)
+    ctx = _ep.Context(mesh, free, mat)
+    try:
+        ctx.set_state(*state)
+        scales = [1.0, 0.3, 1.6, 0.0]
+        checks = {254, 255, 256, 257, 511, 599}
+        for k in range(600):
+            s = scales[k % 4]
+            ctx.constitutive(ctx.tensor(u0 * s), sig=False, D=False, flag=False)
+            ctx.assemble_tangent()
+            if k not in checks:
+                continue
+            fresh = _ep.Context(mesh, free, mat)
+            try:
+                fresh.set_state(*state)
+                fresh.constitutive(fresh.tensor(u0 * s), sig=False, D=False, flag=False)
+                fresh.assemble_tangent()
+                assert np.array_equal(_np(ctx.csr(1)[2]), _np(fresh.csr(1)[2])), k
+            finally:
+                fresh.close()
+    finally:
+        ctx.close()
