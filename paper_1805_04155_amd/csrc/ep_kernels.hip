@@ -430,8 +430,9 @@ struct AsmCfg {
   static constexpr int BS = NPAIR <= 64 ? 64 : (NPAIR <= 128 ? 128 : 256);
   static constexpr int NBT = (NPAIR + BS - 1) / BS;
   // points per LDS chunk (4 for the 8-node hexahedron: LDS bounds its
-  // occupancy)
-  static constexpr int QC = ETID == ET_Q1_3D ? 4 : (T::NQ <= 11 ? T::NQ : 9);
+  // occupancy; 6 for the 9-node quadrilateral: measured fastest of 3..9)
+  static constexpr int QC =
+      ETID == ET_Q1_3D ? 4 : (ETID == ET_Q2_2D ? 6 : (T::NQ <= 11 ? T::NQ : 9));
   static constexpr int WPE = T::D == 2 ? 6 : 4;       // occupancy target (waves/SIMD)
   // quadrilaterals and 8-node hexahedra stage the element matrix in LDS and
   // scatter it row by row in column order: on structured meshes an element's
