@@ -316,7 +316,10 @@ int Ctx::prof_begin(int id) {
     // no system-scope fence: the times are read after a stream
     // synchronisation, which makes every result visible anyway
     if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess) return -1;
-    if (hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess) return -1;
+    if (hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return -1;
+    }
   }
   pending.push_back({id, a, b, 1});
   launch_start = a;
@@ -371,16 +374,18 @@ ep_status do_constitutive(Ctx *c, const double *u, double *sig, double *D, uint8
   a.force = true;
   // the plastic masks go to the buffer the last assembly did not use
   c->em_cur = c->em_asm == 0 ? 1 : 0;
-  int tok = c->prof_begin(PROF_CONST);
-  HIPC(launch_constitutive(*c, a));
-  c->prof_end(tok);
+  {
+    ProfScope ps(*c, PROF_CONST);
+    HIPC(launch_constitutive(*c, a));
+  }
   // assembly work list, grouped by colour: elements plastic now or at the
   // last assembly
-  tok = c->prof_begin(PROF_COMPACT);
-  HIPC(launch_compact(*c, 1, c->em[c->em_cur], c->em_asm >= 0 ? c->em[c->em_asm] : nullptr,
-                      c->ecol_perm, c->n_perm, c->plist, c->d_colour_first_block, c->n_col,
-                      c->coff, c->ptotals));
-  c->prof_end(tok);
+  {
+    ProfScope ps(*c, PROF_COMPACT);
+    HIPC(launch_compact(*c, 1, c->em[c->em_cur], c->em_asm >= 0 ? c->em[c->em_asm] : nullptr,
+                        c->ecol_perm, c->n_perm, c->plist, c->d_colour_first_block, c->n_col,
+                        c->coff, c->ptotals));
+  }
   c->have_const = true;
   return EP_OK;
 }
@@ -407,14 +412,15 @@ ep_status do_assemble(Ctx *c) {
       last = col;
       ++n_launch;
     }
-  const int tok = c->prof_begin(PROF_ASSEMBLE);
-  const hipEvent_t stop = c->launch_stop;
-  if (tok >= 0) c->pending[tok].count = n_launch;
-  for (int col = 0; col < c->n_col; ++col) {
-    c->launch_stop = col == last ? stop : nullptr;
-    HIPC(launch_colour_assembly(*c, col, epoch));
+  {
+    ProfScope ps(*c, PROF_ASSEMBLE);
+    const hipEvent_t stop = c->launch_stop;
+    if (ps.tok >= 0) c->pending[ps.tok].count = n_launch;
+    for (int col = 0; col < c->n_col; ++col) {
+      c->launch_stop = col == last ? stop : nullptr;
+      HIPC(launch_colour_assembly(*c, col, epoch));
+    }
   }
-  c->prof_end(tok);
   c->em_asm = c->em_cur;
   return EP_OK;
 }
@@ -424,9 +430,10 @@ ep_status do_assemble(Ctx *c) {
 // F only (into F_out)
 ep_status do_residual(Ctx *c, const double *f, double *F_out, bool residual = true) {
   const int nblk = (int)((c->n_n + 255) / 256);
-  const int tok = c->prof_begin(PROF_FORCE);
-  HIPC(launch_force_gather(*c, f, F_out, residual ? c->r : nullptr, c->partials, nblk));
-  c->prof_end(tok);
+  {
+    ProfScope ps(*c, PROF_FORCE);
+    HIPC(launch_force_gather(*c, f, F_out, residual ? c->r : nullptr, c->partials, nblk));
+  }
   if (residual) HIPC(launch_reduce(*c, c->partials, nblk, 3, c->norms));
   return EP_OK;
 }
@@ -1083,9 +1090,10 @@ ep_status ep_assemble_elastic(ep_ctx *ctx) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   const int64_t n = c->nnzb * c->dim * c->dim;
   HIPC(hipMemsetAsync(c->Ke, 0, sizeof(double) * std::max<int64_t>(1, n), c->stream));
-  const int tok = c->prof_begin(PROF_ELASTIC);
-  HIPC(launch_elastic_assembly(*c));
-  c->prof_end(tok);
+  {
+    ProfScope ps(*c, PROF_ELASTIC);
+    HIPC(launch_elastic_assembly(*c));
+  }
   if (c->opt.tangent_prec == EP_FP32) HIPC(launch_to_float(c->Ke, c->Ke32, n, c->stream));
   HIPC(launch_copy_ke_to_kt(*c));
   c->em_asm = -1;  // K_tangent = K_elast: no element terms to restore

@@ -241,6 +241,17 @@ struct Ctx {
   }
 };
 
+// A profiled section that ends with its scope, also on an early error
+// return (no later launch then carries the section's events).
+struct ProfScope {
+  Ctx &c;
+  const int tok;
+  ProfScope(Ctx &ctx, int id) : c(ctx), tok(ctx.prof_begin(id)) {}
+  ~ProfScope() { c.prof_end(tok); }
+  ProfScope(const ProfScope &) = delete;
+  ProfScope &operator=(const ProfScope &) = delete;
+};
+
 // Kernel launch on the context's stream (hipLaunchKernelGGL's arguments with
 // the context in place of the stream).  Inside a profiled section the
 // section's events travel with the dispatch itself, so timing adds no marker

@@ -2303,30 +2303,31 @@ hipError_t launch_pcg_beta_init(Ctx &c, double rtol);
 hipError_t launch_pcg_iteration(Ctx &c, double *x) {
   const int grid = ceil_div(c.n_dof, 256);
   double *pold = c.pp[c.pcur], *pnew = c.pp[1 - c.pcur];
-  int tok = c.prof_begin(PROF_SPMV);
   int nblk = 0;
   const bool split = c.opt.operator_form == EP_OPERATOR_SPLIT;
-  // p = z + beta p_old as a vector pass, so that the product gathers one
-  // vector (beta = 0 at the first iteration)
-  EP_LAUNCH(k_pcg_direction, dim3(grid), dim3(256), 0, c, c.n_dof, c.pz, pold,
-            pnew, c.sc);
-  RT(hipGetLastError());
-  RT(spmv_any(c, split, pnew, c.pq, split ? nullptr : c.partials, c.sc, &nblk));
-  c.prof_end(tok);
+  {
+    ProfScope ps(c, PROF_SPMV);
+    // p = z + beta p_old as a vector pass, so that the product gathers one
+    // vector (beta = 0 at the first iteration)
+    EP_LAUNCH(k_pcg_direction, dim3(grid), dim3(256), 0, c, c.n_dof, c.pz, pold,
+              pnew, c.sc);
+    RT(hipGetLastError());
+    RT(spmv_any(c, split, pnew, c.pq, split ? nullptr : c.partials, c.sc, &nblk));
+  }
   if (split) {
     // q = Q K_elast p + Q sum_e Delta K_e p_e, then the partial p.q
-    tok = c.prof_begin(PROF_SPLIT);
+    ProfScope ps(c, PROF_SPLIT);
     RT(launch_split_apply(c, 0, pnew, c.sc));
     RT(launch_split_gather(c, 0, c.pq, pnew, c.partials, c.sc, &nblk));
-    c.prof_end(tok);
   }
   EP_LAUNCH(k_pcg_alpha, dim3(1), dim3(256), 0, c, c.partials, nblk, c.sc);
   RT(hipGetLastError());
-  tok = c.prof_begin(PROF_PCGVEC);
-  EP_LAUNCH(k_pcg_update, dim3(grid), dim3(256), 0, c, c.n_dof, x, pnew, c.r,
-            c.pq, c.pz, c.dinv, c.sc, c.partials);
-  c.prof_end(tok);
-  RT(hipGetLastError());
+  {
+    ProfScope ps(c, PROF_PCGVEC);
+    EP_LAUNCH(k_pcg_update, dim3(grid), dim3(256), 0, c, c.n_dof, x, pnew, c.r,
+              c.pq, c.pz, c.dinv, c.sc, c.partials);
+    RT(hipGetLastError());
+  }
   EP_LAUNCH(k_pcg_beta, dim3(1), dim3(256), 0, c, c.partials, grid, c.sc, 0, 0.0);
   RT(hipGetLastError());
   c.pcur = 1 - c.pcur;
