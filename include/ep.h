@@ -278,7 +278,7 @@ ep_status ep_pcg(ep_ctx *ctx, const double *b, double *x, double rtol, int32_t m
  * 7 K_elast assembly of ep_assemble_elastic.  While any id is timed, PCG
  * launches its kernels one by one instead of replaying a graph.
  * ep_profile_read returns the summed duration (ms) and the count of kernel
- * id k and resets both.  Both calls synchronise. */
+ * id k and resets both.  Both calls wait for the kernels timed so far. */
 #define EP_PROFILE_ALL 0xff
 ep_status ep_profile(ep_ctx *ctx, int32_t mask);
 ep_status ep_profile_read(ep_ctx *ctx, int32_t k, double *ms, int64_t *count);
