@@ -388,18 +388,23 @@ __global__ void k_geometry(const double *coord, const int32_t *elem, const doubl
 //                or plastic at the last assembly), Delta K_e = sum over its
 //                plastic points of w_q B_q^T (D_q - C) B_q is added to the
 //                base value of each node block: K_elast if the block was not
-//                written yet in this assembly (epoch != cur), else K_tangent.
+//                written yet in this assembly (stamp != cur), else K_tangent.
 //                An element that left the plastic set contributes zero and
 //                thereby restores K_elast on its untouched blocks.
 // Per plastic point q the Voigt matrix M_q = w_q (D_q - C) (or w_q C) is
 // formed from the tangent descriptor, then H_q = M_q B_q column by column
 // (three non-zeros per column of B in 3D, two in 2D), and each node block is
 // B_p^T H_p' summed over q.  The element matrix is symmetric (associative
-// models), so one thread owns a node pair p <= p' and writes the block and
-// its transpose.  One workgroup per element; the position-map and epoch
-// loads are issued with the coordinate gather and the base values before
-// the products, so their latency overlaps.  Points are processed in chunks
-// of QC so that the per-point tables fit in LDS.
+// models), so one thread owns a node pair p <= p' and computes the block and
+// its transpose.  A workgroup takes one element at a time and loops over the
+// colour's elements with a software pipeline: the next element's list entry,
+// mask, node ids and (sorted scatter) block positions load while the current
+// one is processed; the stamps are read as an element starts, the base values
+// in the scatter.  Quadrilaterals and 8-node hexahedra stage the element
+// matrix in LDS and scatter it row by row in ascending column order (sorted
+// scatter); the other elements write each pair's two blocks from registers.
+// Points are processed in chunks of QC so that the per-point tables fit in
+// LDS.
 // ----------------------------------------------------------------------------
 struct KA {
   const double *coord;
@@ -817,7 +822,7 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
 // FP32 (v_mfma_f32_16x16x4_f32) tiles, a chunk of QC points at a time, and
 // each wavefront accumulates upper-triangle 16x16 tiles of the (symmetric)
 // element matrix in FP32 registers.  The element matrix then goes through
-// LDS to the same epoch-stamped node-block scatter as the FP64 kernel.
+// LDS to the same stamped node-block scatter as the FP64 kernel.
 // Lane layouts (checked on gfx950): lane l holds A[l%16][k-group l/16],
 // B[k-group l/16][l%16], and the result rows 4(l/16)..4(l/16)+3 of column
 // l%16.
