@@ -150,6 +150,10 @@ typedef struct {
  * the node-to-element map, the geometry check (det J > 0 at every point)
  * and K_elast = B^T D_elast B.  The plastic state starts at zero.
  * quadrature and options may be NULL (built-in rule, default options).
+ * Size limits (32-bit indices): dim * n_nodes, n_elems * n_p^2 and the
+ * scalar non-zeros of K (dim^2 per node block) below 2^31; larger meshes,
+ * invalid arrays or materials, a non-positive det J or more than 512
+ * colours give EP_EINVAL, a failed allocation EP_ENOMEM.
  * On error *out is NULL and ep_last_error(NULL) holds the message.
  * Synchronises the stream. */
 ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quadrature,

@@ -688,13 +688,14 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
       deg[m] = (int32_t)lst.size();
     }
   });
-  std::vector<int32_t> bptr(n_n + 1, 0);
-  for (int64_t m = 0; m < n_n; ++m) bptr[m + 1] = bptr[m] + deg[m];
-  const int64_t nnzb = bptr[n_n];
+  int64_t nnzb = 0;
+  for (int64_t m = 0; m < n_n; ++m) nnzb += deg[m];
   if (nnzb * dim * dim >= (int64_t)1 << 31) {
     c->err = "ep_setup: matrix too large for 32-bit indices";
     return bail(EP_EINVAL);
   }
+  std::vector<int32_t> bptr(n_n + 1, 0);
+  for (int64_t m = 0; m < n_n; ++m) bptr[m + 1] = bptr[m] + deg[m];
   c->nnzb = nnzb;
   std::vector<int32_t> bcol(nnzb), bdiag(n_n);
   parallel_for(n_n, [&](int64_t a, int64_t b) {

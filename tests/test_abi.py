@@ -112,3 +112,24 @@ def test_setup_rejects_invalid_input(lib, what):
     err = _setup_error(mesh, free, mat, opts)
     assert err.status == _ep.EP_EINVAL
     assert str(err)
+
+
+@pytest.mark.parametrize("what", ["nodes", "position_map"])
+def test_setup_rejects_meshes_beyond_32bit_indices(lib, what):
+    """Meshes whose node dofs or element position map exceed 32-bit indices
+    are refused with EP_EINVAL before any array is read (the arrays passed
+    here are one element long)."""
+    import ctypes as C
+    import numpy as np
+    from paper_1805_04155_amd import workloads as W
+    coord = np.zeros(3)
+    elem = np.zeros(8, np.int32)
+    free = np.ones(3, np.uint8)
+    n_nodes, n_elems = (2 ** 30, 1) if what == "nodes" else (8, 2 ** 25)
+    m = _ep.ep_mesh(3, _ep.EP_Q1, n_nodes, n_elems, coord.ctypes.data, elem.ctypes.data,
+                    free.ctypes.data)
+    mat = _ep._material(W.VM_MATERIAL)
+    h = C.c_void_p()
+    st = lib.ep_setup(C.byref(m), None, C.byref(mat), None, C.c_void_p(0), C.byref(h))
+    assert st == _ep.EP_EINVAL and not h.value
+    assert b"32-bit" in _ep.lib().ep_last_error(None)
