@@ -156,6 +156,33 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+_SIZES = {}
+
+
+def _sizes(ctx):
+    """Sizes of a live context (cached until ep_destroy)."""
+    key = ctx.value if isinstance(ctx, C.c_void_p) else ctx
+    sz = _SIZES.get(key)
+    if sz is None:
+        sz = _SIZES[key] = ep_get_sizes(ctx)
+    return sz
+
+
+def _dev(t, dtype, n, what):
+    """Device pointer of t after checking its element type and that it holds
+    at least the n elements the library reads or writes (None passes)."""
+    if t is None:
+        return None
+    import torch
+    want = {"f64": torch.float64, "f32": torch.float32, "i32": torch.int32,
+            "u8": torch.uint8}[dtype]
+    if not isinstance(t, torch.Tensor) or t.dtype != want:
+        raise TypeError(f"{what}: expected a {want} tensor")
+    if t.numel() < n:
+        raise ValueError(f"{what}: {t.numel()} elements, the context needs {n}")
+    return _ptr(t)
+
+
 def _check(ctx, st):
     if st != EP_OK:
         msg = lib().ep_last_error(ctx)
@@ -203,6 +230,7 @@ def ep_setup(mesh, free, material, options=None, quadrature=None, stream=None):
 
 
 def ep_destroy(ctx):
+    _SIZES.pop(ctx.value if isinstance(ctx, C.c_void_p) else ctx, None)
     lib().ep_destroy(ctx)
 
 
@@ -220,24 +248,40 @@ def ep_get_sizes(ctx):
     return {k: getattr(s, k) for k, _ in ep_sizes._fields_}
 
 
+def _state_ptrs(ctx, ep, beta, kappa):
+    s = _sizes(ctx)
+    n = s["n_sc"] * s["n_int"]
+    return (_dev(ep, "f64", n, "ep"), _dev(beta, "f64", n, "beta"),
+            _dev(kappa, "f64", s["n_int"], "kappa"))
+
+
 def ep_set_state(ctx, ep=None, beta=None, kappa=None):
-    _check(ctx, lib().ep_set_state(ctx, _ptr(ep), _ptr(beta), _ptr(kappa)))
+    _check(ctx, lib().ep_set_state(ctx, *_state_ptrs(ctx, ep, beta, kappa)))
 
 
 def ep_get_state(ctx, ep=None, beta=None, kappa=None):
-    _check(ctx, lib().ep_get_state(ctx, _ptr(ep), _ptr(beta), _ptr(kappa)))
+    _check(ctx, lib().ep_get_state(ctx, *_state_ptrs(ctx, ep, beta, kappa)))
 
 
 def ep_geometry(ctx, dphi=None, w=None):
-    _check(ctx, lib().ep_geometry(ctx, _ptr(dphi), _ptr(w)))
+    s = _sizes(ctx)
+    _check(ctx, lib().ep_geometry(ctx, _dev(dphi, "f64", s["n_int"] * s["n_p"] * s["dim"], "dphi"),
+                                  _dev(w, "f64", s["n_int"], "w")))
 
 
 def ep_strain(ctx, u, eps):
-    _check(ctx, lib().ep_strain(ctx, _ptr(u), _ptr(eps)))
+    s = _sizes(ctx)
+    _check(ctx, lib().ep_strain(ctx, _dev(u, "f64", s["n_dof"], "u"),
+                                _dev(eps, "f64", s["n_str"] * s["n_int"], "eps")))
 
 
 def ep_constitutive(ctx, u, sig=None, D=None, flag=None):
-    _check(ctx, lib().ep_constitutive(ctx, _ptr(u), _ptr(sig), _ptr(D), _ptr(flag)))
+    s = _sizes(ctx)
+    n = s["n_int"]
+    _check(ctx, lib().ep_constitutive(ctx, _dev(u, "f64", s["n_dof"], "u"),
+                                      _dev(sig, "f64", s["n_sc"] * n, "sig"),
+                                      _dev(D, "f64", s["n_str"] ** 2 * n, "D"),
+                                      _dev(flag, "u8", n, "flag")))
 
 
 def ep_assemble_tangent(ctx):
@@ -248,48 +292,60 @@ def ep_assemble_elastic(ctx):
     _check(ctx, lib().ep_assemble_elastic(ctx))
 
 
+def _dof(ctx, t, what):
+    return _dev(t, "f64", _sizes(ctx)["n_dof"], what)
+
+
 def ep_internal_force(ctx, F):
-    _check(ctx, lib().ep_internal_force(ctx, _ptr(F)))
+    _check(ctx, lib().ep_internal_force(ctx, _dof(ctx, F, "F")))
 
 
 def ep_newton_step(ctx, f, u):
     """Returns (status, info dict); EP_ENOTCONV is returned, not raised."""
     info = ep_newton_info()
-    st = lib().ep_newton_step(ctx, _ptr(f), _ptr(u), C.byref(info))
+    st = lib().ep_newton_step(ctx, _dof(ctx, f, "f"), _dof(ctx, u, "u"), C.byref(info))
     if st not in (EP_OK, EP_ENOTCONV):
         _check(ctx, st)
     return st, {k: getattr(info, k) for k, _ in ep_newton_info._fields_}
 
 
 def ep_commit_step(ctx, u):
-    _check(ctx, lib().ep_commit_step(ctx, _ptr(u)))
+    _check(ctx, lib().ep_commit_step(ctx, _dof(ctx, u, "u")))
 
 
 def ep_get_plastic(ctx, ip=None, elem=None):
     n_ip, n_el = C.c_int64(), C.c_int64()
-    _check(ctx, lib().ep_get_plastic(ctx, _ptr(ip), C.byref(n_ip), _ptr(elem), C.byref(n_el)))
+    s = _sizes(ctx)
+    _check(ctx, lib().ep_get_plastic(ctx, _dev(ip, "i32", s["n_int"], "ip"), C.byref(n_ip),
+                                     _dev(elem, "i32", s["n_elems"], "elem"), C.byref(n_el)))
     return n_ip.value, n_el.value
 
 
 def ep_get_csr(ctx, which, row_ptr=None, col_idx=None, val=None):
-    _check(ctx, lib().ep_get_csr(ctx, which, _ptr(row_ptr), _ptr(col_idx), _ptr(val)))
+    s = _sizes(ctx)
+    _check(ctx, lib().ep_get_csr(ctx, which, _dev(row_ptr, "i32", s["n_dof"] + 1, "row_ptr"),
+                                 _dev(col_idx, "i32", s["nnz"], "col_idx"),
+                                 _dev(val, "f64", s["nnz"], "val")))
 
 
 def ep_get_position_map(ctx, pos):
-    _check(ctx, lib().ep_get_position_map(ctx, _ptr(pos)))
+    s = _sizes(ctx)
+    n = s["n_elems"] * (s["dim"] * s["n_p"]) ** 2
+    _check(ctx, lib().ep_get_position_map(ctx, _dev(pos, "i32", n, "pos")))
 
 
 def ep_spmv(ctx, x, y):
-    _check(ctx, lib().ep_spmv(ctx, _ptr(x), _ptr(y)))
+    _check(ctx, lib().ep_spmv(ctx, _dof(ctx, x, "x"), _dof(ctx, y, "y")))
 
 
 def ep_apply_tangent(ctx, x, y):
-    _check(ctx, lib().ep_apply_tangent(ctx, _ptr(x), _ptr(y)))
+    _check(ctx, lib().ep_apply_tangent(ctx, _dof(ctx, x, "x"), _dof(ctx, y, "y")))
 
 
 def ep_pcg(ctx, b, x, rtol, max_it):
     its, rel = C.c_int32(), C.c_double()
-    st = lib().ep_pcg(ctx, _ptr(b), _ptr(x), rtol, max_it, C.byref(its), C.byref(rel))
+    st = lib().ep_pcg(ctx, _dof(ctx, b, "b"), _dof(ctx, x, "x"), rtol, max_it, C.byref(its),
+                      C.byref(rel))
     if st not in (EP_OK, EP_ENOTCONV):
         _check(ctx, st)
     return st, its.value, rel.value
@@ -494,17 +550,20 @@ def ep_mlp_datagen(material, n, idx, n_pool, eps_pool, ep_pool, beta_pool, kappa
 
 
 def ep_mlp_features(ctx, u, X):
-    _check(ctx, lib().ep_mlp_features(ctx, _ptr(u), _ptr(X)))
+    _check(ctx, lib().ep_mlp_features(ctx, _dof(ctx, u, "u"),
+                                      _dev(X, "f32", _sizes(ctx)["n_int"] * MLP_XS, "X")))
 
 
 def ep_predictor(ctx, u_prev, u_prev2, extrap, u_out):
-    _check(ctx, lib().ep_predictor(ctx, _ptr(u_prev), _ptr(u_prev2), float(extrap), _ptr(u_out)))
+    _check(ctx, lib().ep_predictor(ctx, _dof(ctx, u_prev, "u_prev"), _dof(ctx, u_prev2, "u_prev2"),
+                                   float(extrap), _dof(ctx, u_out, "u_out")))
 
 
 def ep_warm_start(ctx, m, f, u_prev, u_prev2, extrap, pcg_rtol, u_out):
     info = ep_warm_info()
-    st = lib().ep_warm_start(ctx, m, _ptr(f), _ptr(u_prev), _ptr(u_prev2), float(extrap),
-                             float(pcg_rtol), _ptr(u_out), C.byref(info))
+    st = lib().ep_warm_start(ctx, m, _dof(ctx, f, "f"), _dof(ctx, u_prev, "u_prev"),
+                             _dof(ctx, u_prev2, "u_prev2"), float(extrap), float(pcg_rtol),
+                             _dof(ctx, u_out, "u_out"), C.byref(info))
     if st not in (EP_OK, EP_ENOTCONV):
         _check(ctx, st)
     return st, {k: getattr(info, k) for k, _ in ep_warm_info._fields_}

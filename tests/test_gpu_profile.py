@@ -109,3 +109,25 @@ def test_profile_elastic_assembly():
 
 def _np(t):
     return t.detach().cpu().numpy()
+
+
+def test_binding_checks_buffers():
+    """The binding refuses a buffer of the wrong element type or one too
+    small for the context before the library is called."""
+    mesh, free, mat, u_np, state = make_case("q2_2d_dp")
+    ctx = _ep.Context(mesh, free, mat)
+    try:
+        u = ctx.tensor(u_np)
+        with pytest.raises(TypeError):
+            _ep.ep_constitutive(ctx.h, u.float())
+        with pytest.raises(ValueError):
+            _ep.ep_constitutive(ctx.h, u[:-1])
+        with pytest.raises(ValueError):
+            _ep.ep_internal_force(ctx.h, torch.empty(mesh.n_dof - 2, dtype=torch.float64,
+                                                     device="cuda"))
+        with pytest.raises(TypeError):
+            _ep.ep_get_plastic(ctx.h, torch.empty(mesh.n_int, dtype=torch.int64, device="cuda"))
+        _ep.ep_constitutive(ctx.h, u)  # the right buffers still work
+        torch.cuda.synchronize()
+    finally:
+        ctx.close()
