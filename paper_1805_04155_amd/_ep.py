@@ -175,7 +175,7 @@ def _dev(t, dtype, n, what):
         return None
     import torch
     want = {"f64": torch.float64, "f32": torch.float32, "i32": torch.int32,
-            "u8": torch.uint8}[dtype]
+            "i64": torch.int64, "u8": torch.uint8}[dtype]
     if not isinstance(t, torch.Tensor) or t.dtype != want:
         raise TypeError(f"{what}: expected a {want} tensor")
     if t.numel() < n:
@@ -521,31 +521,43 @@ def ep_mlp_last_error(m):
 
 
 def ep_mlp_set_params(m, params):
-    _check_mlp(m, lib().ep_mlp_set_params(m, _ptr(params)))
+    _check_mlp(m, lib().ep_mlp_set_params(m, _dev(params, "f32", MLP_NPARAM, "params")))
 
 
 def ep_mlp_get_params(m, params):
-    _check_mlp(m, lib().ep_mlp_get_params(m, _ptr(params)))
+    _check_mlp(m, lib().ep_mlp_get_params(m, _dev(params, "f32", MLP_NPARAM, "params")))
 
 
 def ep_mlp_forward(m, X, n, Y):
-    _check_mlp(m, lib().ep_mlp_forward(m, _ptr(X), n, _ptr(Y)))
+    _check_mlp(m, lib().ep_mlp_forward(m, _dev(X, "f32", n * MLP_XS, "X"), n,
+                                       _dev(Y, "f32", n * MLP_YS, "Y")))
 
 
 def ep_mlp_loss_grad(m, X, T, n, grad=None, loss=None):
-    _check_mlp(m, lib().ep_mlp_loss_grad(m, _ptr(X), _ptr(T), n, _ptr(grad), _ptr(loss)))
+    _check_mlp(m, lib().ep_mlp_loss_grad(m, _dev(X, "f32", n * MLP_XS, "X"),
+                                         _dev(T, "f32", n * MLP_YS, "T"), n,
+                                         _dev(grad, "f32", MLP_NPARAM, "grad"),
+                                         _dev(loss, "f32", 1, "loss")))
 
 
 def ep_mlp_adam_step(m, X, T, n, lr, loss=None):
-    _check_mlp(m, lib().ep_mlp_adam_step(m, _ptr(X), _ptr(T), n, float(lr), _ptr(loss)))
+    _check_mlp(m, lib().ep_mlp_adam_step(m, _dev(X, "f32", n * MLP_XS, "X"),
+                                         _dev(T, "f32", n * MLP_YS, "T"), n, float(lr),
+                                         _dev(loss, "f32", 1, "loss")))
 
 
 def ep_mlp_datagen(material, n, idx, n_pool, eps_pool, ep_pool, beta_pool, kappa_pool, deps,
                    X, T, stream=None):
     mat = _material(material)
-    _check(None, lib().ep_mlp_datagen(C.byref(mat), n, _ptr(idx), n_pool, _ptr(eps_pool),
-                                      _ptr(ep_pool), _ptr(beta_pool), _ptr(kappa_pool),
-                                      _ptr(deps), _ptr(X), _ptr(T),
+    pool = 6 * n_pool
+    _check(None, lib().ep_mlp_datagen(C.byref(mat), n, _dev(idx, "i64", n, "idx"), n_pool,
+                                      _dev(eps_pool, "f64", pool, "eps_pool"),
+                                      _dev(ep_pool, "f64", pool, "ep_pool"),
+                                      _dev(beta_pool, "f64", pool, "beta_pool"),
+                                      _dev(kappa_pool, "f64", n_pool, "kappa_pool"),
+                                      _dev(deps, "f64", 6 * n, "deps"),
+                                      _dev(X, "f32", n * MLP_XS, "X"),
+                                      _dev(T, "f32", n * MLP_YS, "T"),
                                       stream if stream is not None else _stream()))
 
 
