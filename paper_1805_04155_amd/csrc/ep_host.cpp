@@ -386,6 +386,7 @@ ep_status do_constitutive(Ctx *c, const double *u, double *sig, double *D, uint8
                         c->ecol_perm, c->n_perm, c->plist, c->d_colour_first_block, c->n_col,
                         c->coff, c->ptotals));
   }
+  c->coff_known = false;  // new offsets on the device
   c->have_const = true;
   return EP_OK;
 }
@@ -403,25 +404,31 @@ ep_status do_assemble(Ctx *c) {
     c->epoch_counter = 0;
   }
   const int epoch = ++c->epoch_counter;
-  // one timed section over the colour launches: the start event travels with
-  // the first launch and the stop event with the last, and the section
-  // counts one per launch
+  // colours with an empty work list are skipped when the host holds the
+  // list's colour offsets (after a Newton step's synchronisation)
+  auto listed = [&](int col) -> int64_t {
+    return c->coff_known ? (int64_t)(c->coff_h[col + 1] - c->coff_h[col]) : -1;
+  };
   int last = -1, n_launch = 0;
   for (int col = 0; col < c->n_col; ++col)
-    if (c->colour_size[col] > 0) {
+    if (c->colour_size[col] > 0 && listed(col) != 0) {
       last = col;
       ++n_launch;
     }
+  // one timed section over the colour launches: the start event travels with
+  // the first launch and the stop event with the last, and the section
+  // counts one per launch
   {
     ProfScope ps(*c, PROF_ASSEMBLE);
     const hipEvent_t stop = c->launch_stop;
     if (ps.tok >= 0) c->pending[ps.tok].count = n_launch;
     for (int col = 0; col < c->n_col; ++col) {
       c->launch_stop = col == last ? stop : nullptr;
-      HIPC(launch_colour_assembly(*c, col, epoch));
+      HIPC(launch_colour_assembly(*c, col, epoch, listed(col)));
     }
   }
   c->em_asm = c->em_cur;
+  c->coff_known = false;
   return EP_OK;
 }
 
@@ -996,7 +1003,11 @@ ep_status ep_newton_step(ep_ctx *ctx, const double *f, double *u, ep_newton_info
   HIPC(hipMemcpyAsync(c->norms_h, c->norms, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   int32_t tot[3];
   HIPC(hipMemcpyAsync(tot, c->ptotals, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  c->coff_h.resize(c->n_col + 1);
+  HIPC(hipMemcpyAsync(c->coff_h.data(), c->coff, sizeof(int32_t) * (c->n_col + 1),
+                      hipMemcpyDeviceToHost, c->stream));
   HIPC(hipStreamSynchronize(c->stream));
+  c->coff_known = true;
   info->res_norm = std::sqrt(c->norms_h[0]);
   info->f_norm = std::sqrt(c->norms_h[1]);
   info->res_rel = relative_residual(c->norms_h);

@@ -76,7 +76,9 @@ hipError_t launch_compact(Ctx &c, int kind, const void *src, const uint32_t *src
                           int32_t *colour_first_block, int n_col, int32_t *colour_off,
                           int32_t *totals);
 hipError_t launch_elastic_assembly(Ctx &c);
-hipError_t launch_colour_assembly(Ctx &c, int colour, int epoch);
+// listed: the colour's work-list length when the host knows it (-1: not
+// known; the grid then covers the colour)
+hipError_t launch_colour_assembly(Ctx &c, int colour, int epoch, int64_t listed);
 hipError_t launch_copy_ke_to_kt(Ctx &c);
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t s);
 hipError_t launch_csr_expand(Ctx &c, int which, int32_t *row_ptr, int32_t *col_idx, double *val);
@@ -183,6 +185,8 @@ struct Ctx {
   // work list of the assembly (colour-major): elements plastic now or at
   // the last assembly; coff[c] .. coff[c+1] is colour c's segment
   int32_t *plist = nullptr;
+  std::vector<int32_t> coff_h;  // host copy of the colour offsets of the work list
+  bool coff_known = false;     // coff_h matches the device offsets
   int32_t *coff = nullptr;                 // [n_col+1]
   int32_t *ptotals = nullptr;              // [8]: list length, plastic points,
                                            // plastic elements, scratch

@@ -2075,7 +2075,7 @@ static hipError_t elastic_et(Ctx &c) {
 hipError_t launch_elastic_assembly(Ctx &c) { DISPATCH_ET(elastic_et, c) }
 
 template <int ETID>
-static hipError_t colour_et(Ctx &c, int colour, int epoch) {
+static hipError_t colour_et(Ctx &c, int colour, int epoch, int64_t listed) {
   using Cfg = AsmCfg<ETID>;
   KA a{};
   a.coord = c.coord;
@@ -2098,7 +2098,7 @@ static hipError_t colour_et(Ctx &c, int colour, int epoch) {
   a.elastic = 0;
   a.G = c.mat.G;
   a.K = c.mat.K;
-  const int64_t cnt = c.colour_size[colour];
+  const int64_t cnt = listed >= 0 ? listed : c.colour_size[colour];
   if (cnt == 0) return hipSuccess;
   const int grid = (int)(cnt < 65536 ? cnt : 65536);
   // the FP64/FP32 kernel loops over elements with a software pipeline: a grid
@@ -2126,8 +2126,8 @@ static hipError_t colour_et(Ctx &c, int colour, int epoch) {
     EP_LAUNCH((k_assemble<ETID, double>), dim3(gpipe), dim3(Cfg::BS), 0, c, a);
   return hipGetLastError();
 }
-hipError_t launch_colour_assembly(Ctx &c, int colour, int epoch) {
-  DISPATCH_ET(colour_et, c, colour, epoch)
+hipError_t launch_colour_assembly(Ctx &c, int colour, int epoch, int64_t listed) {
+  DISPATCH_ET(colour_et, c, colour, epoch, listed)
 }
 
 hipError_t launch_copy_ke_to_kt(Ctx &c) {
