@@ -140,7 +140,10 @@ def _state_args(mat, ep, beta, kappa):
 
 def run_path(wl, state, options, mlp=None, extrapolate=False, keep_u=False, steps=None):
     """One load path solved to |Q(f - F)| <= 1e-10 |Q f| per step; wall time
-    from the first Newton evaluation to the last commit (setup excluded)."""
+    summed over the steps, each from its first Newton evaluation (or warm
+    start) to its commit (setup excluded).  With a network: the precision and
+    recall of its plastic set at each step's start against the converged
+    set (bookkeeping outside the step times)."""
     import torch
     from paper_1805_04155_amd import _ep, learned
     opts = {"newton_rtol": 1e-10}
@@ -149,10 +152,10 @@ def run_path(wl, state, options, mlp=None, extrapolate=False, keep_u=False, step
     ctx.set_state(*state)
     u = torch.zeros(wl.mesh.n_dof, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    recs = learned.solve_path_warm(ctx, wl, u, mlp, steps=steps, extrapolate=extrapolate)
+    recs = learned.solve_path_warm(ctx, wl, u, mlp, steps=steps, extrapolate=extrapolate,
+                                   plastic_set=mlp is not None)
     torch.cuda.synchronize()
-    t = time.perf_counter() - t0
+    t = sum(r["seconds"] for r in recs)
     ctx.close()
     out = {"seconds": round(t, 3), "newton_its": sum(r["newton_its"] for r in recs),
            "pcg_its": sum(r["pcg_its"] for r in recs),
@@ -160,6 +163,9 @@ def run_path(wl, state, options, mlp=None, extrapolate=False, keep_u=False, step
            "final_plastic_points": recs[-1]["n_plastic_ip"]}
     if mlp is not None:
         out["warm_starts_accepted"] = sum(r["warm"]["accepted"] for r in recs)
+        both, npred, ntrue = (sum(r["plastic_set"][i] for r in recs) for i in range(3))
+        out["plastic_set_precision"] = round(both / npred, 4) if npred else None
+        out["plastic_set_recall"] = round(both / ntrue, 4) if ntrue else None
     return out, (u if keep_u else None)
 
 

@@ -136,13 +136,16 @@ def evaluate(mlp, X, T):
 
 
 def solve_path_warm(ctx, wl, u, mlp=None, steps=None, max_newton=50, pcg_rtol=1e-2,
-                    extrapolate=True, callback=None):
+                    extrapolate=True, callback=None, plastic_set=False):
     """Load path where each step's Newton iterations start from
     ep_warm_start (mlp given; u_pred is the secant extrapolation of the last
     two converged steps when extrapolate is on), from that extrapolation
     alone (mlp None, extrapolate on: ep_predictor) or from u_{k-1} (mlp None,
     extrapolate off: the paper's start).  The warm-start solve counts as one
-    Newton iteration in the records."""
+    Newton iteration in the records.  plastic_set (mlp given): each record
+    also holds the network's plastic set at u_pred (logit > 0) against the
+    step's converged plastic set, as (both, predicted, converged) point
+    counts; that bookkeeping is excluded from the step's seconds."""
     import torch
     steps = range(len(wl.load_factors)) if steps is None else steps
     f_unit = ctx.tensor(wl.f_unit)
@@ -151,12 +154,17 @@ def solve_path_warm(ctx, wl, u, mlp=None, steps=None, max_newton=50, pcg_rtol=1e
     records = []
     for k in steps:
         f = f_unit * lam[k + 1]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
         extrap = 0.0
         if u_prev2 is not None and extrapolate:
             d = lam[k] - lam[k - 1] if k >= 1 else 0.0
             extrap = (lam[k + 1] - lam[k]) / d if d != 0.0 else 0.0
+        pred = None
+        if plastic_set and mlp is not None:
+            u_pred = torch.empty_like(u)
+            _ep.ep_predictor(ctx.h, u, u_prev2 if extrap else None, extrap, u_pred)
+            pred = mlp.forward(ctx.mlp_features(u_pred))[:, 6] > 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         warm = None
         u_old = u.clone()
         if mlp is not None:
@@ -165,14 +173,22 @@ def solve_path_warm(ctx, wl, u, mlp=None, steps=None, max_newton=50, pcg_rtol=1e
         elif extrap != 0.0:
             _ep.ep_predictor(ctx.h, u, u_prev2, extrap, u)
         hist = solver.solve_load_step(ctx, f, u, max_newton)
+        t_set, counts = 0.0, None
+        if pred is not None:
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            true = ctx.constitutive(u, sig=False, D=False, flag=True)[2] != 0
+            counts = ((pred & true).sum().item(), pred.sum().item(), true.sum().item())
+            t_set = time.perf_counter() - ts
         ctx.commit_step(u)
         torch.cuda.synchronize()
-        t = time.perf_counter() - t0
+        t = time.perf_counter() - t0 - t_set
         u_prev2 = u_old
         rec = {"step": k, "load": lam[k + 1], "newton_its": len(hist) - 1 + (warm is not None),
                "pcg_its": sum(h["pcg_its"] for h in hist) + (warm["pcg_its"] if warm else 0),
                "res_rel": hist[-1]["res_rel"], "n_plastic_ip": hist[-1]["n_plastic_ip"],
-               "seconds": t, "warm": warm, "res_history": [h["res_rel"] for h in hist]}
+               "seconds": t, "warm": warm, "res_history": [h["res_rel"] for h in hist],
+               "plastic_set": counts}
         records.append(rec)
         if callback is not None:
             callback(k, rec)

@@ -329,14 +329,22 @@ def test_trained_warm_start_gain():
     # measured run (seed 0)
     ep0, beta0, _, _ = W.seeded_state(wl, 0.5, seed=0)
     res = {}
-    for name, mlp, ex in (("plain", None, False), ("predictor", None, True),
-                          ("untrained", untrained, True), ("trained", trained, True)):
+    for name, mlp, ex, ps in (("plain", None, False, False), ("predictor", None, True, False),
+                              ("untrained", untrained, True, False),
+                              ("trained", trained, True, False),
+                              ("trained_set", trained, True, True)):
         c = _ep.Context(mesh, wl.free, mat, options=opts)
         c.set_state(ep0, beta0, None)
         uu = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
-        recs = learned.solve_path_warm(c, wl, uu, mlp, extrapolate=ex)
+        recs = learned.solve_path_warm(c, wl, uu, mlp, extrapolate=ex, plastic_set=ps)
         res[name] = (sum(r["newton_its"] for r in recs), _np(uu), recs)
         c.close()
+    # the plastic-set bookkeeping leaves the iterates unchanged, and its
+    # counts are consistent
+    assert np.array_equal(res["trained_set"][1], res["trained"][1])
+    for r in res["trained_set"][2]:
+        both, npred, ntrue = r["plastic_set"]
+        assert 0 <= both <= min(npred, ntrue) and ntrue == r["n_plastic_ip"]
     trained.close()
     untrained.close()
     its = {k: v[0] for k, v in res.items()}
