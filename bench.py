@@ -121,8 +121,17 @@ def cpu_baseline(wl, ep, beta, kappa, u):
     one_pass()
     times = sorted(one_pass() for _ in range(3))
     t = times[1]
+    cpu = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": mesh.n_int / t / 1e6, "unit": "M integration pts/s", "cores": 1,
-            "kind": "oracle", "seconds": round(t, 3),
+            "kind": "oracle", "seconds": round(t, 3), "host_cpu": cpu,
+            "host_cpu_count": os.cpu_count(),
             "sample": f"full passes over all {mesh.n_elems} elements ({mesh.n_int} points): "
                       "strain, return map, COO-sorted K assembly, internal force; geometry "
                       "and sparsity pattern precomputed; median of 3 timed passes after 1 "
