@@ -150,9 +150,10 @@ def _state_args(mat, ep, beta, kappa):
 def run_path(wl, state, options, mlp=None, extrapolate=False, keep_u=False, steps=None):
     """One load path solved to |Q(f - F)| <= 1e-10 |Q f| per step; wall time
     summed over the steps, each from its first Newton evaluation (or warm
-    start) to its commit (setup excluded).  With a network: the precision and
-    recall of its plastic set at each step's start against the converged
-    set (bookkeeping outside the step times)."""
+    start) to its commit (setup excluded); and the precision and recall of the
+    plastic set each step starts from (the network's, or the exact map's at
+    the start displacement) against the converged set (bookkeeping outside
+    the step times)."""
     import torch
     from paper_1805_04155_amd import _ep, learned
     opts = {"newton_rtol": 1e-10}
@@ -162,7 +163,7 @@ def run_path(wl, state, options, mlp=None, extrapolate=False, keep_u=False, step
     u = torch.zeros(wl.mesh.n_dof, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     recs = learned.solve_path_warm(ctx, wl, u, mlp, steps=steps, extrapolate=extrapolate,
-                                   plastic_set=mlp is not None)
+                                   plastic_set=True)
     torch.cuda.synchronize()
     t = sum(r["seconds"] for r in recs)
     ctx.close()
@@ -172,9 +173,9 @@ def run_path(wl, state, options, mlp=None, extrapolate=False, keep_u=False, step
            "final_plastic_points": recs[-1]["n_plastic_ip"]}
     if mlp is not None:
         out["warm_starts_accepted"] = sum(r["warm"]["accepted"] for r in recs)
-        both, npred, ntrue = (sum(r["plastic_set"][i] for r in recs) for i in range(3))
-        out["plastic_set_precision"] = round(both / npred, 4) if npred else None
-        out["plastic_set_recall"] = round(both / ntrue, 4) if ntrue else None
+    both, npred, ntrue = (sum(r["plastic_set"][i] for r in recs) for i in range(3))
+    out["start_plastic_set_precision"] = round(both / npred, 4) if npred else None
+    out["start_plastic_set_recall"] = round(both / ntrue, 4) if ntrue else None
     return out, (u if keep_u else None)
 
 

@@ -142,10 +142,11 @@ def solve_path_warm(ctx, wl, u, mlp=None, steps=None, max_newton=50, pcg_rtol=1e
     two converged steps when extrapolate is on), from that extrapolation
     alone (mlp None, extrapolate on: ep_predictor) or from u_{k-1} (mlp None,
     extrapolate off: the paper's start).  The warm-start solve counts as one
-    Newton iteration in the records.  plastic_set (mlp given): each record
-    also holds the network's plastic set at u_pred (logit > 0) against the
-    step's converged plastic set, as (both, predicted, converged) point
-    counts; that bookkeeping is excluded from the step's seconds."""
+    Newton iteration in the records.  plastic_set: each record also holds
+    the plastic set the step starts from against the step's converged set,
+    as (both, start, converged) point counts: the network's set at u_pred
+    (logit > 0) with mlp, else the exact return map's set at the start
+    displacement; that bookkeeping is excluded from the step's seconds."""
     import torch
     steps = range(len(wl.load_factors)) if steps is None else steps
     f_unit = ctx.tensor(wl.f_unit)
@@ -159,10 +160,13 @@ def solve_path_warm(ctx, wl, u, mlp=None, steps=None, max_newton=50, pcg_rtol=1e
             d = lam[k] - lam[k - 1] if k >= 1 else 0.0
             extrap = (lam[k + 1] - lam[k]) / d if d != 0.0 else 0.0
         pred = None
-        if plastic_set and mlp is not None:
+        if plastic_set:
             u_pred = torch.empty_like(u)
             _ep.ep_predictor(ctx.h, u, u_prev2 if extrap else None, extrap, u_pred)
-            pred = mlp.forward(ctx.mlp_features(u_pred))[:, 6] > 0
+            if mlp is not None:
+                pred = mlp.forward(ctx.mlp_features(u_pred))[:, 6] > 0
+            else:
+                pred = ctx.constitutive(u_pred, sig=False, D=False, flag=True)[2] != 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         warm = None

@@ -332,7 +332,8 @@ def test_trained_warm_start_gain():
     for name, mlp, ex, ps in (("plain", None, False, False), ("predictor", None, True, False),
                               ("untrained", untrained, True, False),
                               ("trained", trained, True, False),
-                              ("trained_set", trained, True, True)):
+                              ("trained_set", trained, True, True),
+                              ("predictor_set", None, True, True)):
         c = _ep.Context(mesh, wl.free, mat, options=opts)
         c.set_state(ep0, beta0, None)
         uu = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
@@ -342,9 +343,11 @@ def test_trained_warm_start_gain():
     # the plastic-set bookkeeping leaves the iterates unchanged, and its
     # counts are consistent
     assert np.array_equal(res["trained_set"][1], res["trained"][1])
-    for r in res["trained_set"][2]:
-        both, npred, ntrue = r["plastic_set"]
-        assert 0 <= both <= min(npred, ntrue) and ntrue == r["n_plastic_ip"]
+    assert np.array_equal(res["predictor_set"][1], res["predictor"][1])
+    for name in ("trained_set", "predictor_set"):
+        for r in res[name][2]:
+            both, npred, ntrue = r["plastic_set"]
+            assert 0 <= both <= min(npred, ntrue) and ntrue == r["n_plastic_ip"]
     trained.close()
     untrained.close()
     its = {k: v[0] for k, v in res.items()}
