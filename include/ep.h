@@ -224,8 +224,9 @@ ep_status ep_internal_force(ep_ctx *ctx, double *F);
  * u are kept).  Computes the residual r = Q(f - F(u)); if |r| <= newton_rtol
  * |Q f| it sets info->converged = 1 and leaves u unchanged; otherwise it
  * assembles K_tangent (operator_form ASSEMBLED; SPLIT assembles nothing),
- * solves K du = r on the free dofs by Jacobi-PCG to
- * the relative tolerance min(pcg_forcing_max, res_rel) and adds du to u.
+ * solves K du = r on the free dofs by Jacobi-PCG to the relative tolerance
+ * min(pcg_forcing_max, max(res_rel, newton_rtol / (2 res_rel))) (no tighter
+ * than the step needs to reach newton_rtol) and adds du to u.
  * Writes info (host).  Synchronises the stream.  EP_ENOTCONV if PCG hits
  * its limit (u is still updated with the last iterate). */
 ep_status ep_newton_step(ep_ctx *ctx, const double *f, double *u,
