@@ -151,8 +151,8 @@ def _ptr(t):
     if t is None:
         return None
     import torch
-    assert isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous(), \
-        "device pointers must be contiguous CUDA (HIP) tensors"
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+        raise TypeError("device pointers must be contiguous CUDA (HIP) tensors")
     return C.c_void_p(t.data_ptr())
 
 
