@@ -79,3 +79,30 @@ def test_quadratic_local_convergence():
             ratios.append(math.log(res[l + 1]) / math.log(res[l]))
     assert ratios, res
     assert max(ratios) > 1.7, (res, ratios)
+
+
+def test_seeded_cyclic_cube_path_converges():
+    """The cyclic traction history on the 8^3 cube from the seeded state
+    (half of the elements plastic): every step, the zero-load instants
+    included, reaches |Q(f - F)| <= 1e-10 |Q f| (or the reaction scale where
+    Q f = 0: the seeded plastic strain leaves residual stresses), in a few
+    Newton iterations per step."""
+    wl = W.workload_q1_cube_cyclic(8, 30)
+    mesh, mat = wl.mesh, wl.material
+    ep, beta, _, _ = W.seeded_state(wl, 0.5, seed=0)
+    ep6, beta6 = O.state_to_ip6(ep, 3), O.state_to_ip6(beta, 3)
+    kappa = np.zeros(mesh.n_int)
+    u = np.zeros(mesh.n_dof)
+    dphi, w = O.geometry(mesh)
+    pat = O.pattern(mesh)
+    its = []
+    for k in range(len(wl.load_factors)):
+        f = wl.f_unit * wl.load_factors[k]
+        u, it, res, out = O.newton_solve(mesh, mat, wl.free, f, u, ep6, beta6, kappa, tol=1e-10,
+                                         dphi=dphi, w=w, pattern_=pat)
+        assert res[-1] <= 1e-10
+        ep6, beta6, kappa = out["ep"], out["beta"], out["kappa"]
+        its.append(it)
+    assert min(wl.load_factors) < 0.0 < max(wl.load_factors)
+    assert 0.0 in [float(x) for x in wl.load_factors]
+    assert sum(its) < 4 * len(its)
