@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 from gpu_cases import make_case  # noqa: E402
-from paper_1805_04155_amd import _ep, learned, solver  # noqa: E402
+from paper_1805_04155_amd import _ep, learned  # noqa: E402
 from paper_1805_04155_amd import workloads as W  # noqa: E402
 
 PREC = {"fp32": _ep.EP_FP32, "bf16": _ep.EP_BF16}
