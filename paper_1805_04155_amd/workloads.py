@@ -642,7 +642,8 @@ def seeded_state(wl: Workload, fraction: float, seed: int = 0):
     Drucker-Prager: eps_p0 = r * N + v * I/3 with r chosen so that the trial
     deviatoric norm at u = 0 is 1.5*sqrt(2)*c and v = -zeta*c/(eta*K) with
     zeta ~ U(0, 2), so seeded points fall on both the smooth and the apex
-    branches.
+    branches where the bulk modulus allows (nu = 0.3); at nu = 0.49 the
+    apex test is out of reach and every seeded point is on the cone.
 
     Returns (ep, beta, kappa) as SoA arrays (n_sc, n_int) / (n_int,), with
     n_sc = 6 in 3D and 4 (11, 22, 33, 12) in plane strain."""
