@@ -432,7 +432,8 @@ static void T4_to_voigt(T4 C, double *D) {
    (1 = plastic), updated ep and beta. */
 static void rm_vm(double G, double K, double a, double Y,
                   const double *eps_v, const double *ep_v, const double *beta_v,
-                  double *sig_v, double *D, uint8_t *flag, double *ep_out, double *beta_out) {
+                  double *sig_v, double *D, uint8_t *flag, double *ep_out, double *beta_out,
+                  double *crit_out) {
   T2 eps, ep, beta, etr, str, sdev, s, sig, n;
   T4 C;
   double ns, crit;
@@ -446,6 +447,7 @@ static void rm_vm(double G, double K, double a, double Y,
   for (i = 0; i < 3; ++i) for (j = 0; j < 3; ++j) s[i][j] = sdev[i][j] - beta[i][j];
   ns = fnorm(s);
   crit = ns - Y;
+  if (crit_out) { crit_out[0] = crit; crit_out[1] = 0.0; }
   elastic_T4(G, K, C);
   memcpy(sig, str, sizeof(T2));
   memcpy(ep_out, ep_v, 6 * sizeof(double));
@@ -481,7 +483,8 @@ static void rm_vm(double G, double K, double a, double Y,
    decision follows the paper's listing: smooth iff CRIT2 <= 0. */
 static void rm_dp(double G, double K, double a, double eta, double c,
                   const double *eps_v, const double *ep_v, double kappa,
-                  double *sig_v, double *D, uint8_t *flag, double *ep_out, double *kappa_out) {
+                  double *sig_v, double *D, uint8_t *flag, double *ep_out, double *kappa_out,
+                  double *crit_out) {
   T2 eps, ep, etr, str, s, sig, n, M, epn;
   T4 C;
   double ptr, rho, ck, crit1, crit2;
@@ -497,6 +500,7 @@ static void rm_dp(double G, double K, double a, double eta, double c,
   ck = c + a * kappa;
   crit1 = rho / r2 + eta * ptr - ck;
   crit2 = eta * ptr - ck - (K * eta * eta + a) * rho / (r2 * G);
+  if (crit_out) { crit_out[0] = crit1; crit_out[1] = crit2; }
   elastic_T4(G, K, C);
   memcpy(sig, str, sizeof(T2));
   memcpy(ep_out, ep_v, 6 * sizeof(double));
@@ -537,20 +541,25 @@ static void rm_dp(double G, double K, double a, double eta, double c,
 }
 
 /* model: 1 = von Mises kinematic, 2 = Drucker-Prager (a >= 0).
-   Any of the output pointers may be NULL. */
-void or_constitutive(int model, int64_t n, const double *eps, const double *ep,
-                     const double *beta, const double *kappa,
-                     double G, double K, double a, double Y, double eta, double c,
-                     double *sig, double *D, uint8_t *flag,
-                     double *ep_new, double *beta_new, double *kappa_new) {
+   Any of the output pointers may be NULL.  crit[n][2] receives the yield
+   tests the branch decisions are taken on: von Mises |s_tr| - Y (and 0);
+   Drucker-Prager CRIT1 (trial yield function) and CRIT2 (the smooth / apex
+   test). */
+void or_constitutive_crit(int model, int64_t n, const double *eps, const double *ep,
+                          const double *beta, const double *kappa,
+                          double G, double K, double a, double Y, double eta, double c,
+                          double *sig, double *D, uint8_t *flag,
+                          double *ep_new, double *beta_new, double *kappa_new, double *crit) {
   int64_t i;
   for (i = 0; i < n; ++i) {
     double s[6], d[36], epn[6], bn[6], kn = 0;
     uint8_t f;
+    double *cr = crit ? crit + 2 * i : NULL;
     if (model == 1) {
-      rm_vm(G, K, a, Y, eps + 6 * i, ep + 6 * i, beta + 6 * i, s, d, &f, epn, bn);
+      rm_vm(G, K, a, Y, eps + 6 * i, ep + 6 * i, beta + 6 * i, s, d, &f, epn, bn, cr);
     } else {
-      rm_dp(G, K, a, eta, c, eps + 6 * i, ep + 6 * i, kappa ? kappa[i] : 0.0, s, d, &f, epn, &kn);
+      rm_dp(G, K, a, eta, c, eps + 6 * i, ep + 6 * i, kappa ? kappa[i] : 0.0, s, d, &f, epn, &kn,
+            cr);
       memset(bn, 0, sizeof bn);
     }
     if (sig) memcpy(sig + 6 * i, s, sizeof s);
@@ -560,6 +569,15 @@ void or_constitutive(int model, int64_t n, const double *eps, const double *ep,
     if (beta_new) memcpy(beta_new + 6 * i, bn, sizeof bn);
     if (kappa_new) kappa_new[i] = kn;
   }
+}
+
+void or_constitutive(int model, int64_t n, const double *eps, const double *ep,
+                     const double *beta, const double *kappa,
+                     double G, double K, double a, double Y, double eta, double c,
+                     double *sig, double *D, uint8_t *flag,
+                     double *ep_new, double *beta_new, double *kappa_new) {
+  or_constitutive_crit(model, n, eps, ep, beta, kappa, G, K, a, Y, eta, c, sig, D, flag, ep_new,
+                       beta_new, kappa_new, NULL);
 }
 
 /* ------------------------------------------------------------------------ */

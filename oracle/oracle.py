@@ -48,6 +48,8 @@ def lib():
         L.or_geometry.restype = I64
         L.or_strain.argtypes = [I, I64, P, P, P, P]
         L.or_constitutive.argtypes = [I, I64, P, P, P, P, D, D, D, D, D, D, P, P, P, P, P, P]
+        L.or_constitutive_crit.argtypes = [I, I64, P, P, P, P, D, D, D, D, D, D, P, P, P, P,
+                                           P, P, P]
         L.or_internal_force.argtypes = [I, I64, I64, P, P, P, P, P]
         L.or_pattern.argtypes = [I, I64, I64, P, P, P]
         L.or_pattern.restype = I64
@@ -127,10 +129,12 @@ def ip6_to_state(arr, dim):
     return np.ascontiguousarray(arr.T if dim == 3 else arr[:, :4].T)
 
 
-def constitutive(material, eps, ep6, beta6=None, kappa=None):
+def constitutive(material, eps, ep6, beta6=None, kappa=None, crit=False):
     """Return map at every point (Sections 2.2, 2.3 and the linear cohesion
     hardening extension).  Returns dict(sig (n,6), D (n,6,6), flag (n,),
-    ep (n,6), beta (n,6), kappa (n,))."""
+    ep (n,6), beta (n,6), kappa (n,)); with crit=True also crit (n,2), the
+    yield tests the branches are decided on (von Mises |s_tr| - Y;
+    Drucker-Prager CRIT1 and CRIT2)."""
     n = eps.shape[0]
     model = 1 if material.model == "VM" else 2
     eps = np.ascontiguousarray(eps, dtype=np.float64)
@@ -139,12 +143,27 @@ def constitutive(material, eps, ep6, beta6=None, kappa=None):
     kappa = np.zeros(n) if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
     out = dict(sig=np.zeros((n, 6)), D=np.zeros((n, 6, 6)), flag=np.zeros(n, np.uint8),
                ep=np.zeros((n, 6)), beta=np.zeros((n, 6)), kappa=np.zeros(n))
-    lib().or_constitutive(model, n, _p(eps), _p(ep6), _p(beta6), _p(kappa),
-                          material.shear, material.bulk, material.a, material.Y,
-                          material.eta, material.c,
-                          _p(out["sig"]), _p(out["D"]), _p(out["flag"]),
-                          _p(out["ep"]), _p(out["beta"]), _p(out["kappa"]))
+    if crit:
+        out["crit"] = np.zeros((n, 2))
+    lib().or_constitutive_crit(model, n, _p(eps), _p(ep6), _p(beta6), _p(kappa),
+                               material.shear, material.bulk, material.a, material.Y,
+                               material.eta, material.c,
+                               _p(out["sig"]), _p(out["D"]), _p(out["flag"]),
+                               _p(out["ep"]), _p(out["beta"]), _p(out["kappa"]),
+                               _p(out["crit"]) if crit else None)
     return out
+
+
+def tie_band(material, crit, rel=1e-12):
+    """Points whose branch decision lies within rel of a tie: |CRIT| < rel*Y
+    (von Mises), or |CRIT1| < rel*c, or CRIT1 > 0 with |CRIT2| < rel*c
+    (Drucker-Prager).  Two codes that round the yield test differently may
+    take different branches only there.  Returns a boolean mask."""
+    crit = np.asarray(crit)
+    if material.model == "VM":
+        return np.abs(crit[:, 0]) < rel * material.Y
+    s = rel * material.c
+    return (np.abs(crit[:, 0]) < s) | ((crit[:, 0] > 0) & (np.abs(crit[:, 1]) < s))
 
 
 def internal_force(mesh, dphi, w, sig, elem=None):

@@ -551,16 +551,9 @@ def workload_lshape_vm(level=2, steps=40) -> Workload:
 
 def dp_strip_footing_material(phi=math.pi / 9, c0=450.0, E=1e7, nu=0.48, plane=True):
     """Drucker-Prager parameters of the strip-footing example (Section 8.3):
-    eta and c from the friction angle phi and the cohesion c0, the plane
-    strain fit or the 3D fit of the paper's formulas."""
-    if plane:
-        t = math.tan(phi)
-        d = math.sqrt(9.0 + 12.0 * t * t)
-        eta, c = 3.0 * t / d, c0 * 3.0 / d
-    else:
-        s, co = math.sin(phi), math.cos(phi)
-        d = math.sqrt(3.0) * (3.0 + s)
-        eta, c = 6.0 * s / d, c0 * 6.0 * co / d
+    eta and c from the friction angle phi and the cohesion c0 by
+    dp_parameters (the plane strain fit or the 3D fit)."""
+    eta, c = dp_parameters(c0, phi, plane_strain=plane)
     return Material("DP", E=E, nu=nu, eta=eta, c=c, a=0.0)
 
 
