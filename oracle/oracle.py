@@ -10,6 +10,7 @@ equation references are to Cermak, Sysala, Valdman (arXiv 1805.04155).
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -242,9 +243,56 @@ def csr_to_scipy(row_ptr, col_idx, val, n):
     return sp.csr_matrix((val, col_idx, row_ptr), shape=(n, n))
 
 
+def energy_norm_increment(Ke, du, u_old):
+    """The stopping quantity of ALG-NEWTON (Section 4):
+    |du|_e / (|u_old|_e + |u_old + du|_e) with |v|_e^2 = v^T K_elast v."""
+    u_new = u_old + du
+    a = float(du @ (Ke @ du))
+    b = float(u_old @ (Ke @ u_old))
+    c = float(u_new @ (Ke @ u_new))
+    den = math.sqrt(max(b, 0.0)) + math.sqrt(max(c, 0.0))
+    return math.sqrt(max(a, 0.0)) / den if den > 0 else 0.0
+
+
+def line_search(g, g0, theta, max_evals=12):
+    """Step length of the damped Newton method (the damped variant Section 4
+    mentions): the Newton correction du is scaled by the minimiser of the
+    incremental energy J(u + a du) over a in (0, 1].  J is convex along the
+    line (the models are associative), its derivative is -g(a) with
+    g(a) = du . Q(f - F(u + a du)) and g(0) = g0 > 0.  The full step is kept
+    if g(1) >= -theta g0 (the minimiser is not far before 1); otherwise the
+    root of g in (0, 1) is bracketed and found by regula falsi with the
+    Illinois modification to |g| <= theta g0.  g is a callable; returns
+    (a, number of evaluations of g)."""
+    g1 = g(1.0)
+    n = 1
+    if not (g0 > 0) or g1 >= -theta * g0:
+        return 1.0, n
+    a, ga, b, gb = 0.0, g0, 1.0, g1
+    side = 0
+    x = 1.0
+    while n < max_evals:
+        x = (a * gb - b * ga) / (gb - ga)
+        gx = g(x)
+        n += 1
+        if abs(gx) <= theta * g0:
+            break
+        if gx > 0:
+            a, ga = x, gx
+            if side == 1:
+                gb *= 0.5
+            side = 1
+        else:
+            b, gb = x, gx
+            if side == -1:
+                ga *= 0.5
+            side = -1
+    return x, n
+
+
 def newton_solve(mesh, material, free, f, u0, ep6, beta6, kappa, *, tol=1e-10,
                  max_it=50, linear="direct", dphi=None, w=None, pattern_=None,
-                 history=None, raise_on_limit=True):
+                 history=None, raise_on_limit=True, damping=None):
     """Solve one load step: find u with |Q(f - F(u))| <= tol |Q f| (with
     Q f = 0, under pure displacement control, relative to the reactions
     |(I - Q) F(u)| instead).
@@ -252,9 +300,13 @@ def newton_solve(mesh, material, free, f, u0, ep6, beta6, kappa, *, tol=1e-10,
     The first iterate is u0 (the previous step's displacement on free dofs;
     Dirichlet values are already in u0).  The linear solve is either a sparse
     direct solve (scipy, tiny meshes) or the oracle's Jacobi-PCG with
-    forcing tolerance min(1e-2, |r|/|f|).  Returns (u, its, residual history,
-    last constitutive output); at max_it iterations it raises, or returns the
-    last iterate if raise_on_limit is False."""
+    forcing tolerance min(1e-2, |r|/|f|).  damping = theta turns on the
+    damped Newton method (line_search with that theta).  history, if given,
+    receives per iteration the relative residual, the plastic count and, for
+    iterations that made a correction, the step length, the line-search
+    evaluations and the energy-norm increment of ALG-NEWTON.  Returns (u,
+    its, residual history, last constitutive output); at max_it iterations
+    it raises, or returns the last iterate if raise_on_limit is False."""
     import scipy.sparse.linalg as spla
     if dphi is None:
         dphi, w = geometry(mesh)
@@ -265,16 +317,22 @@ def newton_solve(mesh, material, free, f, u0, ep6, beta6, kappa, *, tol=1e-10,
     u = u0.copy()
     fq = np.linalg.norm(f[q])
     res = []
+    Ke = None
+
+    def evaluate(v):
+        eps = strain(mesh, dphi, v)
+        o = constitutive(material, eps, ep6, beta6, kappa)
+        F = internal_force(mesh, dphi, w, o["sig"])
+        return o, F, (f - F) * free
+
     for it in range(max_it + 1):
-        eps = strain(mesh, dphi, u)
-        out = constitutive(material, eps, ep6, beta6, kappa)
-        F = internal_force(mesh, dphi, w, out["sig"])
-        r = (f - F) * free
+        out, F, r = evaluate(u)
         scale = fq if fq > 0 else np.linalg.norm(F[~q])
         rel = np.linalg.norm(r) / scale if scale > 0 else np.linalg.norm(r)
         res.append(rel)
+        rec = dict(rel=rel, n_plastic=int((out["flag"] != 0).sum()))
         if history is not None:
-            history.append(dict(rel=rel, n_plastic=int((out["flag"] != 0).sum())))
+            history.append(rec)
         if rel <= tol:
             return u, it, res, out
         if it == max_it:
@@ -290,5 +348,18 @@ def newton_solve(mesh, material, free, f, u0, ep6, beta6, kappa, *, tol=1e-10,
             du, pits, _ = pcg(row_ptr, col_idx, val, free, r, min(1e-2, rel), 100000)
             if pits < 0:
                 raise RuntimeError("oracle PCG did not converge")
-        u = u + du * free
+        du = du * free
+        alpha, evals = 1.0, 0
+        if damping is not None:
+            alpha, evals = line_search(lambda a: float(du @ evaluate(u + a * du)[2]),
+                                       float(du @ r), damping)
+        if history is not None:
+            if Ke is None:
+                D0 = constitutive(material, np.zeros((mesh.n_int, 6)),
+                                  np.zeros((mesh.n_int, 6)))["D"]
+                _, _, kv = assemble(mesh, dphi, w, D0, row_ptr, col_idx)
+                Ke = csr_to_scipy(row_ptr, col_idx, kv, mesh.n_dof)
+            rec.update(step=alpha, ls_evals=evals,
+                       energy_incr=energy_norm_increment(Ke, alpha * du, u))
+        u = u + alpha * du
     raise RuntimeError(f"Newton did not converge: {res[-5:]}")
