@@ -53,7 +53,8 @@ typedef enum {
   EP_ENOMEM = -2,    /* device or host allocation failed                   */
   EP_EDEVICE = -3,   /* a HIP runtime call failed                          */
   EP_ENOTCONV = -4,  /* PCG reached its iteration limit                    */
-  EP_ESTATE = -5     /* call out of order (e.g. assembly before constitutive) */
+  EP_ESTATE = -5,    /* call out of order (e.g. assembly before constitutive) */
+  EP_ENONFINITE = -6 /* a residual, PCG scalar or correction is NaN or Inf   */
 } ep_status;
 
 /* Lagrange elements of the paper's Appendix.  EP_P1: 3-node triangle /
@@ -123,6 +124,10 @@ typedef struct {
   double pcg_forcing_max;    /* PCG stops at min(this, res_rel) relative     */
   int32_t operator_form;     /* ep_operator (default EP_OPERATOR_ASSEMBLED); SPLIT
                                 requires local_prec = EP_FP64                 */
+  double newton_damping;     /* theta of the damped Newton method (Section 4
+                                remark after eq. lin_syst); 0 = full steps    */
+  int32_t ls_max_evals;      /* residual evaluations per line search (<= 0:
+                                12)                                          */
 } ep_options;
 
 typedef struct {
@@ -142,6 +147,15 @@ typedef struct {
   int32_t pcg_its;
   int32_t converged;         /* 1: res_rel <= newton_rtol; u left unchanged  */
   int64_t n_plastic_ip, n_plastic_elem;
+  double energy_incr;        /* stopping quantity of ALG-NEWTON for the
+                                correction made: |du|_e / (|u_old|_e +
+                                |u_old + du|_e), |v|_e^2 = v^T K_elast v
+                                (whole vectors, Dirichlet dofs included)    */
+  double step;               /* step length a of the correction du = a dx
+                                (1 without damping)                         */
+  int32_t ls_evals;          /* residual evaluations of the line search     */
+  int32_t pcg_breakdown;     /* 1: PCG stopped on p.q <= 0 or a non-finite
+                                scalar                                       */
 } ep_newton_info;
 
 /* Builds everything that depends only on the mesh (Sections 6.1-6.3):
@@ -205,7 +219,9 @@ ep_status ep_constitutive(ep_ctx *ctx, const double *u, double *sig, double *D,
  * the position map, one colour at a time (deterministic, no float atomics);
  * elements that left the plastic set restore K_elast on their blocks.  Cost
  * is proportional to that list, not to the mesh.
- * Returns EP_ESTATE if ep_constitutive has not run since setup or commit. */
+ * Returns EP_ESTATE if ep_constitutive has not run since setup or commit,
+ * EP_EINVAL for a context with operator_form SPLIT (nothing is assembled
+ * there). */
 ep_status ep_assemble_tangent(ep_ctx *ctx);
 
 /* Recomputes K_elast = B^T D_elast B (eq. K_elast-split, the setup step)
@@ -224,11 +240,23 @@ ep_status ep_internal_force(ep_ctx *ctx, double *F);
  * u are kept).  Computes the residual r = Q(f - F(u)); if |r| <= newton_rtol
  * |Q f| it sets info->converged = 1 and leaves u unchanged; otherwise it
  * assembles K_tangent (operator_form ASSEMBLED; SPLIT assembles nothing),
- * solves K du = r on the free dofs by Jacobi-PCG to the relative tolerance
+ * solves K dx = r on the free dofs by Jacobi-PCG to the relative tolerance
  * min(pcg_forcing_max, max(res_rel, newton_rtol / (2 res_rel))) (no tighter
- * than the step needs to reach newton_rtol) and adds du to u.
- * Writes info (host).  Synchronises the stream.  EP_ENOTCONV if PCG hits
- * its limit (u is still updated with the last iterate). */
+ * than the step needs to reach newton_rtol) and adds du = a dx to u.
+ * a = 1 unless newton_damping = theta > 0 (the damped Newton method the
+ * paper mentions after eq. lin_syst): then a minimises the incremental
+ * energy along dx, whose derivative is -g(a), g(a) = dx . Q(f - F(u + a dx))
+ * (each evaluation is a constitutive pass and a residual); a = 1 is kept if
+ * g(1) >= -theta g(0), otherwise a is the root of g in (0, 1) by regula
+ * falsi with the Illinois modification, stopped at |g(a)| <= theta g(0) or
+ * after ls_max_evals evaluations.  info->energy_incr is the paper's
+ * stopping quantity of the correction made (logged; the stopping test stays
+ * the residual test).
+ * Writes info (host).  Synchronises the stream.
+ * Errors: EP_ENOTCONV if PCG hits its limit or breaks down (p.q <= 0;
+ * info->pcg_breakdown = 1): u is still updated with the last finite
+ * iterate.  EP_ENONFINITE if the residual at u, the correction or a
+ * line-search residual is NaN or Inf: u is left unchanged. */
 ep_status ep_newton_step(ep_ctx *ctx, const double *f, double *u,
                          ep_newton_info *info);
 

@@ -17,6 +17,13 @@
  * Compile with -ffp-contract=off so that no fused multiply-add changes a
  * yield decision.
  *
+ * Threads (OpenMP, or_set_threads): only loops whose iterations write
+ * disjoint outputs run in parallel (strain and return map per point,
+ * element force vectors and element matrices per element); every sum keeps
+ * its serial order (the node sums of the internal force and the sorted COO
+ * sums of K run on one thread), so the results do not depend on the thread
+ * count.
+ *
  * Array layouts at this interface (all 0-based, C order):
  *   coord [dim][n_n], elem [n_e][n_p], dphi [n_int][n_p][dim], w [n_int],
  *   eps/sig/ep/beta [n_int][6] Voigt (11,22,33,12,23,13; strain-type vectors
@@ -29,6 +36,21 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads used by the parallel loops (n <= 0: keep the current setting);
+   returns the count in effect (1 without OpenMP). */
+int or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* Element types (oracle-own codes)                                          */
@@ -341,11 +363,13 @@ static const int PLANE[3] = {0, 1, 3};
 /* E = B u at every integration point; eps [n_int][6]. */
 void or_strain(int et, int64_t n_e, const int32_t *elem, const double *dphi,
                const double *u, double *eps) {
-  int dim, n_p, n_q, q, p, r, c;
+  int dim, n_p, n_q;
   int64_t e;
-  double B[6 * 81], ue[81];
   or_elem_info(et, &dim, &n_p, &n_q);
+#pragma omp parallel for schedule(static)
   for (e = 0; e < n_e; ++e) {
+    int q, p, r, c;
+    double B[6 * 81], ue[81];
     for (p = 0; p < n_p; ++p)
       for (c = 0; c < dim; ++c) ue[dim * p + c] = u[(int64_t)dim * elem[e * n_p + p] + c];
     for (q = 0; q < n_q; ++q) {
@@ -551,6 +575,7 @@ void or_constitutive_crit(int model, int64_t n, const double *eps, const double 
                           double *sig, double *D, uint8_t *flag,
                           double *ep_new, double *beta_new, double *kappa_new, double *crit) {
   int64_t i;
+#pragma omp parallel for schedule(static)
   for (i = 0; i < n; ++i) {
     double s[6], d[36], epn[6], bn[6], kn = 0;
     uint8_t f;
@@ -585,23 +610,37 @@ void or_constitutive(int model, int64_t n, const double *eps, const double *ep,
 /* ------------------------------------------------------------------------ */
 void or_internal_force(int et, int64_t n_n, int64_t n_e, const int32_t *elem,
                        const double *dphi, const double *w, const double *sig, double *F) {
-  int dim, n_p, n_q, q, r, c, nrow;
-  int64_t e;
-  double B[6 * 81];
+  int dim, n_p, n_q, nrow, nl;
+  int64_t e, t;
+  double *v;
   or_elem_info(et, &dim, &n_p, &n_q);
   nrow = dim == 3 ? 6 : 3;
-  memset(F, 0, sizeof(double) * dim * n_n);
-  for (e = 0; e < n_e; ++e)
+  nl = dim * n_p;
+  /* v[e][q][c] = w (B^T sigma)_c at point q of element e */
+  v = (double *)malloc(sizeof(double) * (size_t)(n_e * n_q * nl > 0 ? n_e * n_q * nl : 1));
+#pragma omp parallel for schedule(static)
+  for (e = 0; e < n_e; ++e) {
+    int q, r, c;
+    double B[6 * 81];
     for (q = 0; q < n_q; ++q) {
       int64_t ip = e * n_q + q;
       build_B(dim, n_p, dphi + ip * n_p * dim, B);
-      for (c = 0; c < dim * n_p; ++c) {
+      for (c = 0; c < nl; ++c) {
         double s = 0;
         for (r = 0; r < nrow; ++r)
-          s += B[r * dim * n_p + c] * sig[ip * 6 + (dim == 3 ? r : PLANE[r])];
-        F[(int64_t)dim * elem[e * n_p + c / dim] + c % dim] += w[ip] * s;
+          s += B[r * nl + c] * sig[ip * 6 + (dim == 3 ? r : PLANE[r])];
+        v[ip * nl + c] = w[ip] * s;
       }
     }
+  }
+  /* node sums in element, point, local-dof order */
+  memset(F, 0, sizeof(double) * dim * n_n);
+  for (t = 0; t < n_e * n_q * nl; ++t) {
+    int64_t ee = t / ((int64_t)n_q * nl);
+    int c = (int)(t % nl);
+    F[(int64_t)dim * elem[ee * n_p + c / dim] + c % dim] += v[t];
+  }
+  free(v);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -706,24 +745,27 @@ static void element_matrix(int dim, int n_p, int n_q, const double *dphi_e,
 int or_assemble(int et, int64_t n_e, const int32_t *elem, const double *dphi,
                 const double *w, const double *D, const int32_t *row_ptr,
                 const int32_t *col_idx, double *val) {
-  int dim, n_p, n_q, a, b, nl;
-  int64_t e, m = 0, t, k;
+  int dim, n_p, n_q, nl;
+  int64_t e, m, t, k;
   trip *T;
-  double *Ke;
   or_elem_info(et, &dim, &n_p, &n_q);
   nl = dim * n_p;
-  T = (trip *)malloc(sizeof(trip) * (size_t)(n_e * nl * nl));
-  Ke = (double *)malloc(sizeof(double) * nl * nl);
+  T = (trip *)malloc(sizeof(trip) * (size_t)(n_e * nl * nl > 0 ? n_e * nl * nl : 1));
+#pragma omp parallel for schedule(static)
   for (e = 0; e < n_e; ++e) {
+    double Ke[81 * 81];
+    int64_t mm = e * nl * nl;
+    int a, b;
     element_matrix(dim, n_p, n_q, dphi + e * n_q * n_p * dim, w + e * n_q, D + e * n_q * 36, Ke);
     for (a = 0; a < nl; ++a)
-      for (b = 0; b < nl; ++b, ++m) {
-        T[m].r = (int64_t)dim * elem[e * n_p + a / dim] + a % dim;
-        T[m].c = (int64_t)dim * elem[e * n_p + b / dim] + b % dim;
-        T[m].seq = m;
-        T[m].v = Ke[a * nl + b];
+      for (b = 0; b < nl; ++b, ++mm) {
+        T[mm].r = (int64_t)dim * elem[e * n_p + a / dim] + a % dim;
+        T[mm].c = (int64_t)dim * elem[e * n_p + b / dim] + b % dim;
+        T[mm].seq = mm;
+        T[mm].v = Ke[a * nl + b];
       }
   }
+  m = n_e * nl * nl;
   qsort(T, (size_t)m, sizeof(trip), cmp_rc);
   k = -1;
   for (t = 0; t < m; ++t) {
@@ -731,12 +773,12 @@ int or_assemble(int et, int64_t n_e, const int32_t *elem, const double *dphi,
       /* next pattern entry of row r */
       int64_t r = T[t].r;
       if (k < row_ptr[r]) k = row_ptr[r]; else ++k;
-      if (k >= row_ptr[r + 1] || col_idx[k] != T[t].c) { free(T); free(Ke); return -1; }
+      if (k >= row_ptr[r + 1] || col_idx[k] != T[t].c) { free(T); return -1; }
       val[k] = 0.0;
     }
     val[k] += T[t].v;
   }
-  free(T); free(Ke);
+  free(T);
   return 0;
 }
 

@@ -28,8 +28,8 @@ PLANE = [0, 1, 3]
 def build(force=False):
     """Compile the oracle with gcc (no fused multiply-add contraction)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-std=c99", SRC, "-o", LIB + ".tmp", "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC",
+                               "-shared", "-std=c99", SRC, "-o", LIB + ".tmp", "-lm"])
         os.replace(LIB + ".tmp", LIB)
 
 
@@ -61,8 +61,18 @@ def lib():
         L.or_K_rows.restype = I
         L.or_pcg.argtypes = [I64, P, P, P, P, P, P, D, I, P]
         L.or_pcg.restype = I
+        L.or_set_threads.argtypes = [I]
+        L.or_set_threads.restype = I
+        L.or_set_threads(1)  # one thread unless a caller asks for more
         _lib = L
     return _lib
+
+
+def set_threads(n=0):
+    """Threads of the oracle's parallel loops (1 after loading; n <= 0:
+    unchanged); returns the count in effect.  Results do not depend on it (only loops with
+    disjoint outputs run in parallel, sums keep their serial order)."""
+    return int(lib().or_set_threads(int(n)))
 
 
 def _p(a):

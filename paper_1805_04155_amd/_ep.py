@@ -12,7 +12,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libep.so")
 
-EP_OK, EP_EINVAL, EP_ENOMEM, EP_EDEVICE, EP_ENOTCONV, EP_ESTATE = 0, -1, -2, -3, -4, -5
+EP_OK, EP_EINVAL, EP_ENOMEM, EP_EDEVICE, EP_ENOTCONV, EP_ESTATE, EP_ENONFINITE = \
+    0, -1, -2, -3, -4, -5, -6
 EP_P1, EP_P2, EP_Q1, EP_Q2, EP_Q2S = 1, 2, 3, 4, 5
 EP_VM, EP_DP = 1, 2
 EP_FP64, EP_FP32, EP_BF16 = 0, 1, 2
@@ -50,7 +51,8 @@ class ep_options(C.Structure):
     _fields_ = [("tangent_prec", C.c_int32), ("local_prec", C.c_int32),
                 ("pcg_max_it", C.c_int32), ("pcg_check_every", C.c_int32),
                 ("newton_rtol", C.c_double), ("pcg_forcing_max", C.c_double),
-                ("operator_form", C.c_int32)]
+                ("operator_form", C.c_int32), ("newton_damping", C.c_double),
+                ("ls_max_evals", C.c_int32)]
 
 
 class ep_sizes(C.Structure):
@@ -63,7 +65,9 @@ class ep_sizes(C.Structure):
 class ep_newton_info(C.Structure):
     _fields_ = [("res_rel", C.c_double), ("res_norm", C.c_double), ("f_norm", C.c_double),
                 ("pcg_relres", C.c_double), ("pcg_its", C.c_int32), ("converged", C.c_int32),
-                ("n_plastic_ip", C.c_int64), ("n_plastic_elem", C.c_int64)]
+                ("n_plastic_ip", C.c_int64), ("n_plastic_elem", C.c_int64),
+                ("energy_incr", C.c_double), ("step", C.c_double), ("ls_evals", C.c_int32),
+                ("pcg_breakdown", C.c_int32)]
 
 
 class ep_warm_info(C.Structure):
@@ -214,7 +218,7 @@ def ep_setup(mesh, free, material, options=None, quadrature=None, stream=None):
     m = ep_mesh(dim, et, mesh.n_nodes, mesh.n_elems, coord.ctypes.data, elem.ctypes.data,
                 free.ctypes.data)
     mat = _material(material)
-    opt = ep_options(EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2, EP_OPERATOR_ASSEMBLED)
+    opt = ep_options(EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2, EP_OPERATOR_ASSEMBLED, 0.0, 12)
     for k, v in (options or {}).items():
         setattr(opt, k, v)
     q = None

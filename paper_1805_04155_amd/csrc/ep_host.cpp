@@ -284,7 +284,8 @@ void free_ctx(Ctx *c) {
                   c->Fe, c->em[0], c->em[1], c->plist, c->coff, c->ptotals, c->cmp_counts,
                   c->cmp_counts2, c->cmp_counts3, c->F, c->r, c->partials,
                   c->norms, c->pz, c->pp[0], c->pp[1], c->pq, c->px, c->dinv, c->sc,
-                  c->iscratch, c->mlp_x, c->mlp_y, c->wu_pred, c->wu_warm};
+                  c->iscratch, c->mlp_x, c->mlp_y, c->wu_pred, c->wu_warm, c->ky[0],
+                  c->ky[1], c->ut, c->rn};
   if (c->pcg_graph) (void)hipGraphExecDestroy(c->pcg_graph);
   if (c->gstream) (void)hipStreamDestroy(c->gstream);
   for (void *p : ptrs)
@@ -493,7 +494,7 @@ ep_status pcg_chunk(Ctx *c, double *x, int n) {
 }
 
 ep_status do_pcg(Ctx *c, const double *b, double *x, double rtol, int max_it, int *its,
-                 double *relres) {
+                 double *relres, bool *breakdown = nullptr) {
   HIPC(launch_diag_inv(*c));
   HIPC(launch_pcg_init(*c, b, x));
   HIPC(launch_pcg_beta_init(*c, rtol));
@@ -508,10 +509,17 @@ ep_status do_pcg(Ctx *c, const double *b, double *x, double rtol, int max_it, in
     done_its += n;
     HIPC(hipMemcpyAsync(c->sc_h, c->sc, 16 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPC(hipStreamSynchronize(c->stream));
-    done = c->sc_h[4] != 0.0;
+    done = c->sc_h[SC_DONE] != 0.0;
   }
-  *its = (int)c->sc_h[5];
-  *relres = c->sc_h[8] > 0 ? std::sqrt(c->sc_h[2] / c->sc_h[8]) : 0.0;
+  *its = (int)c->sc_h[SC_ITS];
+  *relres = c->sc_h[SC_RR0] > 0 ? std::sqrt(c->sc_h[SC_RR] / c->sc_h[SC_RR0]) : 0.0;
+  const bool brk = c->sc_h[SC_BREAK] != 0.0;
+  if (breakdown) *breakdown = brk;
+  if (brk) {
+    c->err = "PCG breakdown after " + std::to_string(*its) +
+             " iterations (p.q <= 0 or a non-finite scalar); x is the last finite iterate";
+    return EP_ENOTCONV;
+  }
   if (!done) {
     c->err = "PCG reached its iteration limit";
     return EP_ENOTCONV;
@@ -529,6 +537,84 @@ ep_status exact_residual(Ctx *c, const double *f, const double *u, double *res_r
   HIPC(hipMemcpyAsync(c->norms_h, c->norms, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPC(hipStreamSynchronize(c->stream));
   *res_rel = relative_residual(c->norms_h);
+  return EP_OK;
+}
+
+// Energy products of the correction dx = c->px at u (whole vectors, no
+// Dirichlet mask): y0 = K_elast u, y1 = K_elast dx, then
+// norms[4..7] = dx.y1, u.y0, dx.y0, dx.dx (fixed-order sums).  Enqueued.
+ep_status energy_dots(Ctx *c, const double *u) {
+  HIPC(launch_spmv_elastic_full(*c, u, c->ky[0]));
+  HIPC(launch_spmv_elastic_full(*c, c->px, c->ky[1]));
+  const double *x[4] = {c->px, u, c->px, c->px};
+  const double *y[4] = {c->ky[1], c->ky[0], c->ky[0], c->px};
+  HIPC(launch_dots(*c, 4, x, y, c->norms + 4));
+  return EP_OK;
+}
+
+// g(a) = dx . Q(f - F(u + a dx)), the negative derivative of the incremental
+// energy along the Newton correction dx = c->px: constitutive pass and
+// residual at the trial displacement, fixed-order dot.  Synchronises.
+ep_status ls_g(Ctx *c, const double *f, const double *u, double a, double *g) {
+  HIPC(launch_trial(*c, u, c->px, a, c->ut));
+  ep_status st = do_constitutive(c, c->ut, nullptr, nullptr, nullptr);
+  if (st) return st;
+  st = do_residual(c, f, nullptr);
+  if (st) return st;
+  const double *x[1] = {c->px};
+  const double *y[1] = {c->r};
+  HIPC(launch_dots(*c, 1, x, y, c->norms + 8));
+  HIPC(hipMemcpyAsync(c->norms_h + 8, c->norms + 8, sizeof(double), hipMemcpyDeviceToHost,
+                      c->stream));
+  HIPC(hipStreamSynchronize(c->stream));
+  *g = c->norms_h[8];
+  if (!std::isfinite(*g)) {
+    c->err = "ep_newton_step: line-search residual not finite at step length " +
+             std::to_string(a);
+    return EP_ENONFINITE;
+  }
+  return EP_OK;
+}
+
+// Step length of the damped Newton method.  The models are associative, so
+// the incremental energy J(u + a dx) is convex in a and g = -J' decreases;
+// g(0) = dx . r > 0 when dx is a descent direction.  The full step is kept
+// if g(1) >= -theta g(0) (the minimiser is at or close before a = 1);
+// otherwise the root of g in (0, 1) is bracketed by [0, 1] and approached by
+// regula falsi with the Illinois modification (the end point kept twice in
+// a row has its value halved), stopping at |g| <= theta g(0) or after
+// ls_max_evals evaluations (the last point is taken).
+ep_status line_search(Ctx *c, const double *f, const double *u, double g0, double *alpha,
+                      int *evals) {
+  const double theta = c->opt.newton_damping;
+  double g1 = 0.0;
+  ep_status st = ls_g(c, f, u, 1.0, &g1);
+  if (st) return st;
+  *evals = 1;
+  *alpha = 1.0;
+  if (!(g0 > 0.0) || g1 >= -theta * g0) return EP_OK;
+  double lo = 0.0, g_lo = g0, hi = 1.0, g_hi = g1, x = 1.0;
+  int kept = 0;  // +1: the upper end was kept last time, -1: the lower end
+  while (*evals < c->opt.ls_max_evals) {
+    x = (lo * g_hi - hi * g_lo) / (g_hi - g_lo);
+    double gx = 0.0;
+    st = ls_g(c, f, u, x, &gx);
+    if (st) return st;
+    ++*evals;
+    if (std::fabs(gx) <= theta * g0) break;
+    if (gx > 0.0) {
+      lo = x;
+      g_lo = gx;
+      if (kept == 1) g_hi *= 0.5;
+      kept = 1;
+    } else {
+      hi = x;
+      g_hi = gx;
+      if (kept == -1) g_lo *= 0.5;
+      kept = -1;
+    }
+  }
+  *alpha = x;
   return EP_OK;
 }
 
@@ -588,8 +674,11 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
         if (en[i] == en[j]) return fail("ep_setup: repeated node in an element", EP_EINVAL);
   }
 
-  ep_options opt{EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2, EP_OPERATOR_ASSEMBLED};
+  ep_options opt{EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2, EP_OPERATOR_ASSEMBLED, 0.0, 12};
   if (opt_in) opt = *opt_in;
+  if (!(opt.newton_damping >= 0.0 && opt.newton_damping < 1.0))
+    return fail("ep_setup: newton_damping must lie in [0, 1)", EP_EINVAL);
+  if (opt.ls_max_evals <= 0) opt.ls_max_evals = 12;
   if (opt.operator_form != EP_OPERATOR_ASSEMBLED && opt.operator_form != EP_OPERATOR_SPLIT)
     return fail("ep_setup: operator_form must be EP_OPERATOR_ASSEMBLED or EP_OPERATOR_SPLIT",
                 EP_EINVAL);
@@ -832,6 +921,8 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   SETUP_HIP(dalloc(&c->cmp_counts3, c->cmp_cap));
   SETUP_HIP(dalloc(&c->F, n_dof));
   SETUP_HIP(dalloc(&c->r, n_dof));
+  SETUP_HIP(dalloc(&c->ky[0], n_dof));
+  SETUP_HIP(dalloc(&c->ky[1], n_dof));
   // reductions: 2 per 256 dofs (PCG vectors, force gather) or 1 per SpMV
   // block of up to 32 lanes per node
   c->partials_cap = std::max<int64_t>(2 * ((n_dof + 255) / 256), (n_n * 32 + 255) / 256) + 64;
@@ -978,7 +1069,16 @@ ep_status ep_constitutive(ep_ctx *ctx, const double *u, double *sig, double *D, 
 
 ep_status ep_assemble_tangent(ep_ctx *ctx) {
   CHECK_CTX(ctx);
-  return do_assemble(reinterpret_cast<Ctx *>(ctx));
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (c->opt.operator_form == EP_OPERATOR_SPLIT) {
+    // the split form's PCG applies K_elast and the element terms of the
+    // current plastic masks; an assembly would also move the mask buffer the
+    // next evaluation writes
+    c->err = "ep_assemble_tangent: the context applies the split operator form "
+             "(operator_form SPLIT); K_tangent is not assembled";
+    return EP_EINVAL;
+  }
+  return do_assemble(c);
 }
 
 ep_status ep_internal_force(ep_ctx *ctx, double *F) {
@@ -1013,9 +1113,21 @@ ep_status ep_newton_step(ep_ctx *ctx, const double *f, double *u, ep_newton_info
   info->res_rel = relative_residual(c->norms_h);
   info->n_plastic_elem = tot[2];
   info->n_plastic_ip = tot[1];
+  if (!std::isfinite(info->res_rel)) {
+    c->err = "ep_newton_step: the residual at u is not finite (NaN or Inf in u, f or the state)";
+    return EP_ENONFINITE;
+  }
   if (info->res_rel <= c->opt.newton_rtol) {
     info->converged = 1;
     return EP_OK;
+  }
+  const bool damped = c->opt.newton_damping > 0.0;
+  if (damped) {
+    if (!c->ut) HIPC(dalloc(&c->ut, c->n_dof));
+    if (!c->rn) HIPC(dalloc(&c->rn, c->n_dof));
+    // PCG works in place on r: keep the Newton residual for g(0) = dx . r
+    HIPC(hipMemcpyAsync(c->rn, c->r, sizeof(double) * c->n_dof, hipMemcpyDeviceToDevice,
+                        c->stream));
   }
   if (c->opt.operator_form == EP_OPERATOR_ASSEMBLED) {
     st = do_assemble(c);
@@ -1027,11 +1139,46 @@ ep_status ep_newton_step(ep_ctx *ctx, const double *f, double *u, ep_newton_info
                                std::max(info->res_rel, 0.5 * c->opt.newton_rtol / info->res_rel));
   int its = 0;
   double rel = 0;
-  const ep_status ps = do_pcg(c, c->r, c->px, rtol, c->opt.pcg_max_it, &its, &rel);
+  bool brk = false;
+  const ep_status ps = do_pcg(c, c->r, c->px, rtol, c->opt.pcg_max_it, &its, &rel, &brk);
   if (ps != EP_OK && ps != EP_ENOTCONV) return ps;
+  const std::string pcg_err = c->err;
   info->pcg_its = its;
   info->pcg_relres = rel;
-  HIPC(launch_axpy_free(*c, c->px, u));
+  info->pcg_breakdown = brk ? 1 : 0;
+  // energy norms of ALG-NEWTON's stopping test at u (before the update)
+  st = energy_dots(c, u);
+  if (st) return st;
+  if (damped) {
+    const double *x[1] = {c->px};
+    const double *y[1] = {c->rn};
+    HIPC(launch_dots(*c, 1, x, y, c->norms + 8));
+  }
+  HIPC(hipMemcpyAsync(c->norms_h + 4, c->norms + 4, 5 * sizeof(double), hipMemcpyDeviceToHost,
+                      c->stream));
+  HIPC(hipStreamSynchronize(c->stream));
+  const double dKd = c->norms_h[4], uKu = c->norms_h[5], dKu = c->norms_h[6],
+               dd = c->norms_h[7];
+  if (!std::isfinite(dd) || !std::isfinite(dKd) || !std::isfinite(dKu) || !std::isfinite(uKu)) {
+    c->err = "ep_newton_step: the Newton correction is not finite; u left unchanged";
+    return EP_ENONFINITE;
+  }
+  double alpha = 1.0;
+  int evals = 0;
+  if (damped) {
+    st = line_search(c, f, u, c->norms_h[8], &alpha, &evals);
+    if (st) return st;
+  }
+  info->step = alpha;
+  info->ls_evals = evals;
+  // |du|_e / (|u|_e + |u + du|_e) for du = alpha dx, the norms expanded in
+  // the products above
+  const double e_du = alpha * alpha * dKd;
+  const double e_new = uKu + 2.0 * alpha * dKu + alpha * alpha * dKd;
+  const double den = std::sqrt(std::max(uKu, 0.0)) + std::sqrt(std::max(e_new, 0.0));
+  info->energy_incr = den > 0.0 ? std::sqrt(std::max(e_du, 0.0)) / den : 0.0;
+  HIPC(launch_axpy_free(*c, c->px, u, alpha));
+  if (ps != EP_OK) c->err = pcg_err;
   return ps;
 }
 

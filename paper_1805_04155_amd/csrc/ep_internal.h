@@ -39,6 +39,11 @@ constexpr int CMP_THREADS = 256;
 constexpr int CMP_ITEMS = 8;
 constexpr int CMP_CHUNK = CMP_THREADS * CMP_ITEMS;
 
+// PCG scalars on the device (sc[SC_N]); SC_BREAK = 1 when PCG stopped on
+// p.q <= 0 or a non-finite scalar.
+enum { SC_RZ = 0, SC_PQ, SC_RR, SC_TOL, SC_DONE, SC_ITS, SC_ALPHA, SC_BETA, SC_RR0, SC_BREAK,
+       SC_N };
+
 // Kernel ids for ep_profile.
 enum ProfId { PROF_CONST = 0, PROF_COMPACT, PROF_SPLIT, PROF_ASSEMBLE, PROF_FORCE, PROF_SPMV,
               PROF_PCGVEC, PROF_ELASTIC, PROF_COUNT };
@@ -90,7 +95,15 @@ hipError_t launch_spmv(Ctx &c, const double *x, double *y);
 hipError_t launch_apply_split(Ctx &c, const double *x, double *y);
 hipError_t launch_pcg_init(Ctx &c, const double *b, double *x);
 hipError_t launch_pcg_iteration(Ctx &c, double *x);
-hipError_t launch_axpy_free(Ctx &c, const double *du, double *u);
+// u += a du on free dofs
+hipError_t launch_axpy_free(Ctx &c, const double *du, double *u, double a = 1.0);
+// out = u + a du on free dofs, u on Dirichlet dofs
+hipError_t launch_trial(Ctx &c, const double *u, const double *du, double a, double *out);
+// y = K_elast x (FP64 values, every row: no Dirichlet mask)
+hipError_t launch_spmv_elastic_full(Ctx &c, const double *x, double *y);
+// out[k] = x_k . y_k for the n_pairs (<= 4) pairs, fixed-order sums
+hipError_t launch_dots(Ctx &c, int n_pairs, const double *const *x, const double *const *y,
+                       double *out);
 // u_out = u + t (u - u2) on free dofs, u on Dirichlet dofs (u2 == nullptr: copy)
 hipError_t launch_extrapolate(Ctx &c, const double *u, const double *u2, double t, double *u_out);
 
@@ -206,6 +219,12 @@ struct Ctx {
   int64_t partials_cap = 0;
   double *norms = nullptr;     // [8] device
   double *norms_h = nullptr;   // pinned host [8]
+
+  // energy norms of a Newton correction: K_elast u, K_elast dx; line search:
+  // trial displacement and the Newton residual kept through PCG (allocated
+  // at the first damped step)
+  double *ky[2] = {nullptr, nullptr};
+  double *ut = nullptr, *rn = nullptr;
 
   // PCG
   double *pz = nullptr, *pp[2] = {nullptr, nullptr}, *pq = nullptr, *px = nullptr,

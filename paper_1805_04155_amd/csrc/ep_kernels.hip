@@ -12,6 +12,8 @@
 // Determinism: every reduction has a fixed order; the scatter of element
 // matrices uses colour rounds (elements of one colour share no node) and no
 // floating-point atomics.
+#include <cfloat>
+
 #include "ep_internal.h"
 #include "ep_return_map.h"
 
@@ -24,9 +26,6 @@ namespace ep {
   } while (0)
 
 static inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
-
-// PCG scalars on the device
-enum { SC_RZ = 0, SC_PQ, SC_RR, SC_TOL, SC_DONE, SC_ITS, SC_ALPHA, SC_BETA, SC_RR0, SC_N };
 
 // Per-thread part of a one-block reduction of n partial results:
 // sum over b = t, t + nt, t + 2 nt, ... < n of p[b * stride] in increasing
@@ -1710,8 +1709,9 @@ __global__ void k_diag_inv(int64_t n_n, const int32_t *bdiag, const VT *Kt, cons
 // y = Q K x with G lanes per node row: the lanes of a group read consecutive
 // node blocks of the row (coalesced), each lane accumulates the dim rows of
 // the block row, and a butterfly over the G lanes (fixed order, identical
-// in every lane) reduces them.  Optional per-block partial x.y (fixed
-// order); with sc, nothing is done once PCG has converged.
+// in every lane) reduces them.  freem == nullptr: y = K x on every row.
+// Optional per-block partial x.y (fixed order); with sc, nothing is done
+// once PCG has converged.
 template <int D, typename VT, int G>
 __global__ __launch_bounds__(256) void k_spmv(int64_t n_n, const int32_t *bptr,
                                               const int32_t *bcol, const VT *val,
@@ -1758,7 +1758,7 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n_n, const int32_t *bptr,
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       const int64_t r = D * m + i;
-      const double yv = freem[r] ? acc[i] : 0.0;
+      const double yv = (!freem || freem[r]) ? acc[i] : 0.0;
       y[r] = yv;
       dot += x[r] * yv;
     }
@@ -1786,8 +1786,18 @@ __global__ __launch_bounds__(256) void k_pcg_alpha(const double *partials, int n
     __syncthreads();
   }
   if (tid == 0) {
-    sc[SC_PQ] = s[0];
-    sc[SC_ALPHA] = sc[SC_RZ] / s[0];
+    const double pq = s[0];
+    sc[SC_PQ] = pq;
+    // breakdown: the operator is not positive definite along p (possible
+    // for a tangent near the Drucker-Prager apex) or a scalar is not finite;
+    // stop with the last iterate
+    if (!(pq > 0.0 && pq <= DBL_MAX) || !(fabs(sc[SC_RZ]) <= DBL_MAX)) {
+      sc[SC_ALPHA] = 0.0;
+      sc[SC_BREAK] = 1.0;
+      sc[SC_DONE] = 1.0;
+    } else {
+      sc[SC_ALPHA] = sc[SC_RZ] / pq;
+    }
   }
 }
 
@@ -1853,6 +1863,7 @@ __global__ __launch_bounds__(256) void k_pcg_beta(const double *partials, int nb
     __syncthreads();
   }
   if (tid == 0) {
+    const bool finite = fabs(sa[0]) <= DBL_MAX && sb[0] <= DBL_MAX;
     if (init) {
       sc[SC_RZ] = sa[0];
       sc[SC_RR] = sb[0];
@@ -1860,7 +1871,12 @@ __global__ __launch_bounds__(256) void k_pcg_beta(const double *partials, int nb
       sc[SC_TOL] = rtol * rtol * sb[0];
       sc[SC_ITS] = 0.0;
       sc[SC_BETA] = 0.0;
-      sc[SC_DONE] = (sb[0] <= sc[SC_TOL]) ? 1.0 : 0.0;
+      sc[SC_BREAK] = finite ? 0.0 : 1.0;
+      sc[SC_DONE] = (!finite || sb[0] <= sc[SC_TOL]) ? 1.0 : 0.0;
+    } else if (!finite) {
+      // the update just made is not trusted beyond this point: stop
+      sc[SC_BREAK] = 1.0;
+      sc[SC_DONE] = 1.0;
     } else {
       sc[SC_BETA] = sa[0] / sc[SC_RZ];
       sc[SC_RZ] = sa[0];
@@ -1905,9 +1921,44 @@ __global__ __launch_bounds__(256) void k_pcg_init(int64_t n, const double *b, co
   }
 }
 
-__global__ void k_axpy_free(int64_t n, const double *du, const uint8_t *freem, double *u) {
+__global__ void k_axpy_free(int64_t n, const double *du, const uint8_t *freem, double a,
+                            double *u) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && freem[i]) u[i] += du[i];
+  if (i < n && freem[i]) u[i] += a * du[i];
+}
+
+// trial displacement of a line search: out = u + a du on free dofs
+__global__ void k_trial(int64_t n, const double *u, const double *du, double a,
+                        const uint8_t *freem, double *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = freem[i] ? u[i] + a * du[i] : u[i];
+}
+
+// per-block partial dot products x_k . y_k (up to 4 pairs), fixed-order
+// tree in the block; k_reduce sums the blocks in order
+struct DotPairs {
+  const double *x[4];
+  const double *y[4];
+};
+template <int NPAIR>
+__global__ __launch_bounds__(256) void k_dots(int64_t n, DotPairs p, double *partials) {
+  __shared__ double s[NPAIR][256];
+  const int tid = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+#pragma unroll
+  for (int k = 0; k < NPAIR; ++k) s[k][tid] = i < n ? p.x[k][i] * p.y[k][i] : 0.0;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+#pragma unroll
+      for (int k = 0; k < NPAIR; ++k) s[k][tid] += s[k][tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+#pragma unroll
+    for (int k = 0; k < NPAIR; ++k) partials[NPAIR * blockIdx.x + k] = s[k][0];
+  }
 }
 
 __global__ void k_extrapolate(int64_t n, const double *u, const double *u2, double t,
@@ -2251,14 +2302,16 @@ static int spmv_lanes(const Ctx &c) {
 
 template <int D, typename VT>
 static hipError_t spmv_launch(Ctx &c, const void *vals, const double *x, double *y,
-                              double *partials, const double *sc, int *nblk) {
+                              double *partials, const double *sc, int *nblk,
+                              bool masked = true) {
   const int G = spmv_lanes(c);
   const int grid = ceil_div(c.n_n * G, 256);
   *nblk = grid;
   if (grid == 0) return hipSuccess;
 #define SPG(GG)                                                                              \
   EP_LAUNCH((k_spmv<D, VT, GG>), dim3(grid), dim3(256), 0, c, c.n_n, c.bptr, \
-            c.bcol, (const VT *)vals, x, c.freem, y, partials, sc, x + 1, x + 2)
+            c.bcol, (const VT *)vals, x, masked ? c.freem : nullptr, y, partials, sc, x + 1, \
+            x + 2)
   switch (G) {
     case 4: SPG(4); break;
     case 8: SPG(8); break;
@@ -2345,11 +2398,47 @@ hipError_t launch_pcg_beta_init(Ctx &c, double rtol) {
   return hipGetLastError();
 }
 
-hipError_t launch_axpy_free(Ctx &c, const double *du, double *u) {
+hipError_t launch_axpy_free(Ctx &c, const double *du, double *u, double a) {
   if (c.n_dof == 0) return hipSuccess;
   EP_LAUNCH(k_axpy_free, dim3(ceil_div(c.n_dof, 256)), dim3(256), 0, c, c.n_dof,
-            du, c.freem, u);
+            du, c.freem, a, u);
   return hipGetLastError();
+}
+
+hipError_t launch_trial(Ctx &c, const double *u, const double *du, double a, double *out) {
+  if (c.n_dof == 0) return hipSuccess;
+  EP_LAUNCH(k_trial, dim3(ceil_div(c.n_dof, 256)), dim3(256), 0, c, c.n_dof, u, du, a,
+            c.freem, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_elastic_full(Ctx &c, const double *x, double *y) {
+  int nblk = 0;
+  if (c.dim == 2) return spmv_launch<2, double>(c, c.Ke, x, y, nullptr, nullptr, &nblk, false);
+  return spmv_launch<3, double>(c, c.Ke, x, y, nullptr, nullptr, &nblk, false);
+}
+
+hipError_t launch_dots(Ctx &c, int n_pairs, const double *const *x, const double *const *y,
+                       double *out) {
+  if (n_pairs < 1 || n_pairs > 4) return hipErrorInvalidValue;
+  DotPairs p{};
+  for (int k = 0; k < n_pairs; ++k) {
+    p.x[k] = x[k];
+    p.y[k] = y[k];
+  }
+  const int grid = std::max(1, ceil_div(c.n_dof, 256));
+  if ((int64_t)grid * n_pairs > c.partials_cap) return hipErrorInvalidValue;
+#define DT(NP_)                                                                          \
+  EP_LAUNCH((k_dots<NP_>), dim3(grid), dim3(256), 0, c, c.n_dof, p, c.partials)
+  switch (n_pairs) {
+    case 1: DT(1); break;
+    case 2: DT(2); break;
+    case 3: DT(3); break;
+    default: DT(4); break;
+  }
+#undef DT
+  RT(hipGetLastError());
+  return launch_reduce(c, c.partials, grid, n_pairs, out);
 }
 
 hipError_t launch_extrapolate(Ctx &c, const double *u, const double *u2, double t, double *out) {

@@ -370,3 +370,181 @@ def test_strip_footing_limit_load_prandtl():
             ctx.close()
     assert abs(out["Q2_2D"] - nc) < 0.06 * nc, out
     assert out["Q1_2D"] > 1.25 * nc, out
+
+
+# --------------------------------------------------------------------------
+# damped Newton (Section 4, the remark after eq. lin_syst), the energy-norm
+# increment of ALG-NEWTON, non-finite inputs
+# --------------------------------------------------------------------------
+
+def _footing_single_step():
+    wl = W.workload_strip_footing(16, "Q2_2D")
+    mesh = wl.mesh
+    u0 = wl.u_dir_unit * 0.5
+    return wl, mesh, u0
+
+
+def _oracle_damped_footing(wl, mesh, u0):
+    n = mesh.n_int
+    dphi, w = O.geometry(mesh)
+    pat = O.pattern(mesh)
+    args = (mesh, wl.material, wl.free, np.zeros(mesh.n_dof), u0, np.zeros((n, 6)), None,
+            np.zeros(n))
+    u, it, res, out = O.newton_solve(*args, tol=1e-10, max_it=60, dphi=dphi, w=w,
+                                     pattern_=pat, damping=0.25)
+    return u, dphi, w, pat
+
+
+def test_damped_newton_footing_step_matches_oracle():
+    """The strip footing on 16 x 16 nine-node quadrilaterals pushed to
+    u_D = 0.5 in one displacement step (the case the oracle's plain Newton
+    does not solve in 60 iterations): the GPU's damped Newton (theta = 1/4)
+    converges, takes shortened steps while the plastic zone forms and full
+    steps at the end, and its displacement equals the oracle's damped
+    direct-solve solution (the solution is unique: the oracle's PCG and
+    direct paths agree to 2e-12)."""
+    wl, mesh, u0 = _footing_single_step()
+    uo, *_ = _oracle_damped_footing(wl, mesh, u0)
+    ctx = _ep.Context(mesh, wl.free, wl.material,
+                      options={"newton_rtol": 1e-10, "newton_damping": 0.25})
+    try:
+        u = ctx.tensor(u0)
+        f = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
+        hist = solver.solve_load_step(ctx, f, u, max_newton=60)
+        assert hist[-1]["converged"] and hist[-1]["res_rel"] <= 1e-10
+        steps = [h["step"] for h in hist[:-1]]
+        assert min(steps) < 0.5 and steps[-2:] == [1.0, 1.0]
+        assert all(0.0 < s <= 1.0 for s in steps)
+        assert all(h["ls_evals"] >= 1 for h in hist[:-1])
+        assert _rel(_np(u), uo) < 1e-9
+    finally:
+        ctx.close()
+
+
+def test_line_search_matches_oracle_on_the_same_correction():
+    """One damped iteration at a time on the footing step: the step length
+    and the number of residual evaluations equal those of the oracle's line
+    search run on the same displacement and the same correction dx (taken
+    from the GPU's update u_new - u_old = a dx), with g evaluated by the
+    oracle's own return map and internal force."""
+    wl, mesh, u0 = _footing_single_step()
+    theta = 0.25
+    dphi, w = O.geometry(mesh)
+    n = mesh.n_int
+    z6, zk = np.zeros((n, 6)), np.zeros(n)
+    free = wl.free.astype(np.float64)
+    f = np.zeros(mesh.n_dof)
+
+    def resid(v):
+        o = O.constitutive(wl.material, O.strain(mesh, dphi, v), z6, None, zk)
+        return (f - O.internal_force(mesh, dphi, w, o["sig"])) * free
+
+    ctx = _ep.Context(mesh, wl.free, wl.material,
+                      options={"newton_rtol": 1e-10, "newton_damping": theta})
+    try:
+        u = ctx.tensor(u0)
+        fd = ctx.tensor(f)
+        checked = 0
+        for it in range(40):
+            ub = _np(u).copy()
+            st, info = _ep.ep_newton_step(ctx.h, fd, u)
+            assert st == _ep.EP_OK and not info["converged"]
+            a = info["step"]
+            if not (0.0 < a < 1.0 and info["ls_evals"] >= 3):
+                continue
+            dx = (_np(u) - ub) / a
+            g0 = float(dx @ resid(ub))
+            ao, no = O.line_search(lambda s: float(dx @ resid(ub + s * dx)), g0, theta)
+            assert no == info["ls_evals"], (it, no, info)
+            assert abs(ao - a) <= 1e-8 * max(a, 1e-3), (it, ao, a)
+            checked += 1
+            if checked == 3:
+                break
+        assert checked == 3
+    finally:
+        ctx.close()
+
+
+def test_energy_norm_increment_matches_oracle():
+    """info['energy_incr'] is ALG-NEWTON's |du|_e / (|u_old|_e + |u_new|_e)
+    with |v|_e^2 = v^T K_elast v: exactly 1 for the first correction from
+    u = 0, and on later (plastic) iterations of the seeded cube step equal to
+    the oracle's value for the same u_old and u_new."""
+    wl = W.workload_q1_cube(4)
+    mesh, mat = wl.mesh, wl.material
+    ep, beta, kappa, _ = W.seeded_state(wl, 0.5, seed=0)
+    dphi, w = O.geometry(mesh)
+    rp, ci = O.pattern(mesh)
+    n = mesh.n_int
+    D0 = O.constitutive(mat, np.zeros((n, 6)), np.zeros((n, 6)))["D"]
+    _, _, kv = O.assemble(mesh, dphi, w, D0, rp, ci)
+    Ke = O.csr_to_scipy(rp, ci, kv, mesh.n_dof)
+    ctx = _ep.Context(mesh, wl.free, mat, options={"newton_rtol": 1e-12})
+    try:
+        ctx.set_state(ep, beta, None)
+        u = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
+        f = ctx.tensor(wl.f(7))
+        seen = 0
+        for it in range(20):
+            ub = _np(u).copy()
+            st, info = _ep.ep_newton_step(ctx.h, f, u)
+            if info["converged"]:
+                break
+            ua = _np(u)
+            assert info["step"] == 1.0 and info["ls_evals"] == 0
+            if it == 0:
+                assert info["energy_incr"] == 1.0
+                continue
+            eo = O.energy_norm_increment(Ke, ua - ub, ub)
+            assert abs(info["energy_incr"] - eo) <= 1e-9 * eo + 1e-15, (it, info, eo)
+            seen += 1
+        assert seen >= 2
+    finally:
+        ctx.close()
+
+
+def test_nonfinite_load_is_refused_before_assembly():
+    """A NaN in the load vector gives EP_ENONFINITE from the residual test
+    (no assembly or PCG runs) and leaves u unchanged; a NaN right-hand side
+    stops ep_pcg at once as a breakdown (EP_ENOTCONV, no iteration)."""
+    wl = W.workload_q1_cube(4)
+    mesh = wl.mesh
+    ctx = _ep.Context(mesh, wl.free, wl.material)
+    try:
+        f = wl.f(3).copy()
+        f[np.flatnonzero(wl.free)[5]] = np.nan
+        u = ctx.tensor(np.full(mesh.n_dof, 1e-6) * wl.free)
+        u_before = _np(u).copy()
+        with pytest.raises(_ep.EpError) as ei:
+            _ep.ep_newton_step(ctx.h, ctx.tensor(f), u)
+        assert ei.value.status == _ep.EP_ENONFINITE
+        assert "not finite" in str(ei.value)
+        assert np.array_equal(_np(u), u_before)
+        # the context still works after the refusal
+        st, info = _ep.ep_newton_step(ctx.h, ctx.tensor(wl.f(3)), u)
+        assert st == _ep.EP_OK and np.isfinite(info["res_rel"])
+        ctx.constitutive(u, sig=False, D=False, flag=False)
+        ctx.assemble_tangent()
+        x = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
+        st, its, rel = _ep.ep_pcg(ctx.h, ctx.tensor(f), x, 1e-8, 100)
+        assert st == _ep.EP_ENOTCONV and its == 0
+        assert "breakdown" in _ep.ep_last_error(ctx.h)
+        assert torch.isfinite(x).all()
+    finally:
+        ctx.close()
+
+
+def test_assembly_refused_for_the_split_form():
+    """A split-form context assembles nothing: ep_assemble_tangent is refused
+    with EP_EINVAL (it would also move the plastic-mask buffer the split
+    PCG reads)."""
+    wl = W.workload_q1_cube(3)
+    ctx = _ep.Context(wl.mesh, wl.free, wl.material,
+                      options={"operator_form": _ep.EP_OPERATOR_SPLIT})
+    try:
+        ctx.constitutive(ctx.tensor(np.zeros(wl.mesh.n_dof)), sig=False, D=False, flag=False)
+        with pytest.raises(_ep.EpError) as ei:
+            _ep.ep_assemble_tangent(ctx.h)
+        assert ei.value.status == _ep.EP_EINVAL
+    finally:
+        ctx.close()

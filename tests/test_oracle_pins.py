@@ -229,3 +229,29 @@ def test_tie_band_marks_points_near_the_surface():
     dp = W.dp_material_2d()
     crit = np.array([[1.0, 1e-14], [-1.0, 1e-14], [1e-13, -5.0], [1.0, -1.0]])
     assert O.tie_band(dp, crit).tolist() == [True, False, True, False]
+
+
+def test_oracle_threads_do_not_change_results():
+    """The oracle's parallel loops write disjoint outputs and its sums keep
+    their serial order: strain, return map, internal force and K are bit
+    for bit the same on 1 and on 4 threads."""
+    wl = W.workload_q2_slope(8, 4)
+    mesh, mat = wl.mesh, wl.material
+    ep, beta, kappa, _ = W.seeded_state(wl, 0.5, seed=0)
+    u = W.random_displacement(mesh, 3, 1e-3, wl.free)
+    dphi, w = O.geometry(mesh)
+    rp, ci = O.pattern(mesh)
+    prev = O.set_threads(0)
+    outs = []
+    try:
+        for nt in (1, 4):
+            O.set_threads(nt)
+            eps = O.strain(mesh, dphi, u)
+            o = O.constitutive(mat, eps, O.state_to_ip6(ep, 2), None, kappa)
+            F = O.internal_force(mesh, dphi, w, o["sig"])
+            _, _, K = O.assemble(mesh, dphi, w, o["D"], rp, ci)
+            outs.append((eps, o["sig"], o["D"], F, K))
+    finally:
+        O.set_threads(prev)
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
