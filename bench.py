@@ -4,30 +4,37 @@
 A step is one pass of the hot path over the whole workload: strain and return
 map at every integration point with the fused constitutive kernel, plastic-
 element compaction, the incremental tangent K_elast + B^T (D - D_elast) B
-(colour rounds over the plastic work list) and the internal force / residual.  The metric is
-millions of integration points per second.  Inputs are resident in HBM when
-the timed region starts.  A per-kernel breakdown (every kernel timed with HIP
-events) runs first; in the timed region only the dominant kernel's dispatches
-carry HIP events, which give its mean launch duration for the roofline.
+(colour rounds over the plastic work list) and the internal force / residual.
+The metric is millions of integration points per second.  Inputs are
+resident in HBM when the timed region starts.  A per-kernel breakdown (every
+kernel timed with HIP events) runs first; in the timed region only the
+dominant kernel's dispatches carry HIP events, which give its mean launch
+duration for the roofline.
 
-Workload (default): plane strain 40 x 20 rectangle, 512 x 256 nine-node Q2
-quadrilaterals (131072 elements, 1179648 integration points), Drucker-Prager
-perfect plasticity (c0 = 450, phi = 20 deg, E = 20000, nu = 0.49), half of the
-elements seeded plastic.
+Workload (default): unit cube, 64^3 Q1 hexahedra (262144 elements, 2097152
+integration points, 823875 dofs), von Mises with linear kinematic hardening
+(E = 206900, nu = 0.29, sigma_y = 450, H = 10000), half of the elements
+seeded plastic, FP64 throughout.
 
-Also measured (unless --no-newton), as extra objects of the same line:
-  newton: time to |Q(f - F)| <= 1e-10 |Q f| summed over a load path, for the
-    plain FP64 solver and its variants: FP32 tangent values; the secant
-    predictor; the learned warm start (network trained on the GPU by the
-    library's kernels from a separate training path, FP32 and BF16 products)
-    on the 64^3 Q1 cube under the cyclic traction history; and matrix-core
-    local products (FP32, BF16) on the Q2 / P2 blocks' 20-step paths;
+Also measured (unless switched off), as extra objects of the same line:
+  q2_slope: the same pass on the plane-strain slope (512 x 256 nine-node
+    quadrilaterals, 1179648 points, Drucker-Prager perfect, half seeded),
+    with FP64 and with FP32 tangent values;
+  p1_square_newton: time to |Q(f - F)| <= 1e-10 |Q f| over the ten load
+    steps of the P1 square (2048 triangles, von Mises), FP64;
+  newton: time to 1e-10 summed over a load path, for the plain FP64 solver
+    and its variants: FP32 tangent values; the secant predictor; the learned
+    warm start (network trained on the GPU by the library's kernels from a
+    separate training path, FP32 and BF16 products) on the 64^3 Q1 cube under
+    the cyclic traction history; and matrix-core local products (FP32, BF16)
+    on the Q2 / P2 blocks' 20-step paths;
   local_precision: incremental tangent error of the FP32 / BF16 local
     products against the FP64 path, and the assembly kernel's matrix-core
     rate, on the Q2 / P2 blocks with half of the elements seeded plastic;
-  plastic_sweep: the same pass on the 64^3 Q1 cube with 0/25/50/100 % of the
-    elements seeded plastic, FP64 and FP32 tangent values, at u = 0 and at
-    the first Newton iterate of the load step t = 324.
+  plastic_sweep: the headline pass on the 64^3 cube with 0/25/50/100 % of
+    the elements seeded plastic, FP64 and FP32 tangent values, at u = 0 and
+    at the first Newton iterate of the load step t = 324;
+  lshape_vm, strip_footing: the paper's two examples (Sections 8.2, 8.3).
 
 Prints one JSON line (rank 0, one GPU).
 """
@@ -50,7 +57,7 @@ MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
 # three nonzeros per column of B: 2 (3 (d n_p)^2 + 54 n_p)
 LOCAL_FLOPS_PER_IP = {"Q2_3D": 2 * (3 * 81 ** 2 + 54 * 27), "P2_3D": 2 * (3 * 30 ** 2 + 54 * 10)}
 KERNEL_SRC = os.path.join(ROOT, "paper_1805_04155_amd", "csrc", "ep_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_q2_slope.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 WORKLOADS = {
     "q2_slope": "workload_q2_slope",
@@ -62,9 +69,9 @@ WORKLOADS = {
 
 
 def kernel_bytes(mesh, mat, counts, tangent_bytes):
-    """Algorithmic HBM bytes per step of each kernel (every array read or
-    written once at the granularity the design moves it).  counts: plastic
-    elements, plastic integration points, elements restored."""
+    """Algorithmic HBM bytes per step of each kernel in this design (every
+    array read or written once at the granularity the design moves it).
+    counts: plastic elements, plastic integration points, elements listed."""
     D, NP, NQ = mesh.dim, mesh.n_p, mesh.n_q
     n_e, n_int, n_n = mesh.n_elems, mesh.n_int, mesh.n_nodes
     n_dof = D * n_n
@@ -93,49 +100,86 @@ def kernel_bytes(mesh, mat, counts, tangent_bytes):
     }
 
 
+def assembly_bytes_scalar_model(mesh, counts, tangent_bytes):
+    """Algorithmic bytes of the incremental assembly in the scalar-CSR
+    model: per plastic point its B values and weight plus an 8 x 8 B tangent
+    (8 (d n_p + 1) + 64 B); per plastic element a scalar position map entry
+    and a read-modify-write of each of its (d n_p)^2 values, counted twice
+    (restore of the previous values, then the addition)."""
+    nl = mesh.dim * mesh.n_p
+    s = tangent_bytes
+    return counts["plastic_ips"] * (8 * (nl + 1) + 64) + \
+        counts["plastic_elems"] * nl * nl * (4 + 2 * s) * 2
+
+
 def src_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
 
 
-def cpu_baseline(wl, ep, beta, kappa, u):
-    """The FP64 oracle timed on the host for full passes of the same
-    workload (strain, return map, plain sum w B^T D B assembled by COO sort,
-    internal force), single thread: one untimed pass, then the median of
-    three timed ones."""
-    from oracle import oracle as O
-    mesh, mat = wl.mesh, wl.material
-    dphi, w = O.geometry(mesh)
-    pat = O.pattern(mesh)
-    dim = mesh.dim
-    ep6 = O.state_to_ip6(ep, dim)
-    beta6 = O.state_to_ip6(beta, dim)
-
-    def one_pass():
-        t0 = time.perf_counter()
-        eps = O.strain(mesh, dphi, u)
-        out = O.constitutive(mat, eps, ep6, beta6, kappa)
-        O.assemble(mesh, dphi, w, out["D"], *pat)
-        O.internal_force(mesh, dphi, w, out["sig"])
-        return time.perf_counter() - t0
-
-    one_pass()
-    times = sorted(one_pass() for _ in range(3))
-    t = times[1]
-    cpu = None
+def _host_cpu():
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                cpu = line.split(":", 1)[1].strip()
-                break
+                return line.split(":", 1)[1].strip()
     except OSError:
         pass
-    return {"value": mesh.n_int / t / 1e6, "unit": "M integration pts/s", "cores": 1,
-            "kind": "oracle", "seconds": round(t, 3), "host_cpu": cpu,
-            "host_cpu_count": os.cpu_count(),
-            "sample": f"full passes over all {mesh.n_elems} elements ({mesh.n_int} points): "
-                      "strain, return map, COO-sorted K assembly, internal force; geometry "
-                      "and sparsity pattern precomputed; median of 3 timed passes after 1 "
-                      "untimed"}
+    return None
+
+
+def cpu_baseline(wl, ep, beta, kappa, u, fraction=16):
+    """The FP64 oracle timed on the host for passes over a bounded sample of
+    the same workload: the first n_e / fraction elements (lexicographic
+    order: the bottom layers of the cube) with their seeded state (strain,
+    return map, plain sum w B^T D B assembled by COO sort, internal force;
+    geometry and sparsity pattern of the sample precomputed), on one thread
+    and on all threads the host offers (OMP_NUM_THREADS, else the CPU
+    count).  One untimed pass, then the median of three timed ones per
+    thread count; the rate in points per second carries over to the whole
+    workload."""
+    from oracle import oracle as O
+    from paper_1805_04155_amd import workloads as W
+    mesh, mat = wl.mesh, wl.material
+    k = max(1, mesh.n_elems // fraction)
+    sub = W.Mesh(mesh.etype, mesh.coord, mesh.elem[:k])
+    nq, dim = mesh.n_q, mesh.dim
+    dphi, w = O.geometry(sub)
+    pat = O.pattern(sub)
+    ep6 = O.state_to_ip6(ep[:, :k * nq], dim)
+    beta6 = O.state_to_ip6(beta[:, :k * nq], dim)
+    kap = kappa[:k * nq]
+
+    def one_pass():
+        t0 = time.perf_counter()
+        eps = O.strain(sub, dphi, u)
+        out = O.constitutive(mat, eps, ep6, beta6, kap)
+        O.assemble(sub, dphi, w, out["D"], *pat)
+        O.internal_force(sub, dphi, w, out["sig"])
+        return time.perf_counter() - t0
+
+    def leg(threads):
+        used = O.set_threads(threads)
+        one_pass()
+        t = sorted(one_pass() for _ in range(3))[1]
+        return {"value": round(sub.n_int / t / 1e6, 4), "seconds_per_pass": round(t, 3),
+                "cores": used}
+
+    prev = O.set_threads(0)
+    try:
+        one = leg(1)
+        n_all = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+        allc = leg(n_all)
+    finally:
+        O.set_threads(prev)
+    log(f"cpu oracle: 1 thread {one}, all threads {allc}")
+    return {"value": allc["value"], "unit": "M integration pts/s", "cores": allc["cores"],
+            "kind": "oracle", "seconds_per_pass": allc["seconds_per_pass"],
+            "one_thread": one, "host_cpu": _host_cpu(), "host_cpu_count": os.cpu_count(),
+            "sample": f"the first {k} of {mesh.n_elems} elements ({sub.n_int} of {mesh.n_int} "
+                      "points) with their seeded state: strain, return map, COO-sorted K "
+                      "assembly, internal force per pass (geometry and sparsity pattern "
+                      "precomputed); median of 3 timed passes after 1 untimed, per thread "
+                      "count; the oracle's threads cover its per-point and per-element "
+                      "loops, the COO sort and the node sums stay serial"}
 
 
 def log(msg):
@@ -371,33 +415,38 @@ def lshape_report(level, steps):
 def footing_report(n, ud_max, du_max, max_steps):
     """The strip-footing example (Section 8.3), 9-node quadrilaterals on an
     n x n grid: displacement-controlled path with the paper's doubling of
-    the increment, the normalised footing pressure p/c0 along it."""
+    the increment, the normalised footing pressure p/c0 along it; with full
+    Newton steps and with the damped Newton method (theta = 1/4)."""
     import torch
     from paper_1805_04155_amd import _ep, solver
     from paper_1805_04155_amd import workloads as W
     wl = W.workload_strip_footing(n, "Q2_2D")
-    ctx = _ep.Context(wl.mesh, wl.free, wl.material, options={"newton_rtol": 1e-10})
-    u = torch.zeros(wl.mesh.n_dof, dtype=torch.float64, device="cuda")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    recs = solver.displacement_path(ctx, wl, u, ud_max=ud_max, du0=1e-3, du_max=du_max,
-                                    max_steps=max_steps)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    ctx.close()
     c0 = 450.0
     out = {"workload": f"plane strain [0,10]^2, {n}x{n} 9-node quadrilaterals "
                        f"({wl.mesh.n_dof} dofs), Drucker-Prager perfect E=1e7 nu=0.48 c0=450 "
-                       "phi=pi/9, footing 0<=x1<=1 pushed down by u_D",
-           "seconds": round(t, 3), "steps": len(recs),
-           "newton_its": sum(r["newton_its"] for r in recs),
-           "pcg_its": sum(r["pcg_its"] for r in recs),
-           "final_u_D": recs[-1]["u_D"] if recs else 0.0,
-           "final_pressure_over_c0": round(recs[-1]["pressure"] / c0, 4) if recs else None,
-           "path_u_D_p_over_c0_plastic": [[round(r["u_D"], 6), round(r["pressure"] / c0, 4),
-                                          r["n_plastic_ip"]] for r in recs]}
-    log(f"footing: {out['steps']} steps to u_D = {out['final_u_D']}, p/c0 = "
-        f"{out['final_pressure_over_c0']}, {t:.1f} s")
+                       "phi=pi/9, footing 0<=x1<=1 pushed down by u_D"}
+    for name, theta in (("full_steps", 0.0), ("damped", 0.25)):
+        ctx = _ep.Context(wl.mesh, wl.free, wl.material,
+                          options={"newton_rtol": 1e-10, "newton_damping": theta})
+        u = torch.zeros(wl.mesh.n_dof, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs = solver.displacement_path(ctx, wl, u, ud_max=ud_max, du0=1e-3, du_max=du_max,
+                                        max_steps=max_steps)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        ctx.close()
+        out[name] = {
+            "newton_damping": theta, "seconds": round(t, 3), "steps": len(recs),
+            "newton_its": sum(r["newton_its"] for r in recs),
+            "pcg_its": sum(r["pcg_its"] for r in recs),
+            "line_search_evals": sum(r["ls_evals"] for r in recs),
+            "final_u_D": recs[-1]["u_D"] if recs else 0.0,
+            "final_pressure_over_c0": round(recs[-1]["pressure"] / c0, 4) if recs else None,
+            "path_u_D_p_over_c0_plastic": [[round(r["u_D"], 6), round(r["pressure"] / c0, 4),
+                                           r["n_plastic_ip"]] for r in recs]}
+        log(f"footing {name}: {out[name]['steps']} steps to u_D = {out[name]['final_u_D']}, "
+            f"p/c0 = {out[name]['final_pressure_over_c0']}, {t:.1f} s")
     return out
 
 
@@ -499,18 +548,194 @@ def local_precision_report(block):
     return out
 
 
+MDESC = {
+    "q1_cube": "unit cube, 64^3 Q1 hexahedra (262144 elements, 2097152 points, 823875 dofs), "
+               "von Mises kinematic E=206900 nu=0.29 sigma_y=450 H=10000",
+    "q2_slope": "plane strain 40x20 rectangle, 512x256 9-node Q2 quads (131072 elements, "
+                "1179648 points), Drucker-Prager perfect c0=450 phi=20deg E=20000 nu=0.49",
+}
+
+
+def copy_calibration():
+    """Plain copy of 512 MiB (for scaling hardware byte counters) and the
+    measured copy rate (read + write bytes over time) as the practical HBM
+    ceiling beside the published peak."""
+    import torch
+    a = torch.empty(64 * 2 ** 20, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_ms = e0.elapsed_time(e1) / 20
+    gbs = round(2 * a.numel() * 8 / (copy_ms / 1e3) / 1e9, 1)
+    log(f"copy of 512 MiB: {copy_ms:.4f} ms, {gbs} GB/s read + write")
+    return gbs
+
+
+def measure_pass(name, frac, tangent, local_prec, steps, warmup, copy_gbs=None, keep=False):
+    """Timed passes of the hot path on workload `name` with `frac` of the
+    elements seeded plastic: per-kernel breakdown (every kernel timed), then
+    the timed region with HIP events on the dominant kernel only.  Returns
+    the record (and, with keep, the inputs for the CPU baseline)."""
+    import numpy as np
+    import torch
+    from paper_1805_04155_amd import _ep
+    from paper_1805_04155_amd import workloads as W
+    wl = getattr(W, WORKLOADS[name])()
+    mesh, mat = wl.mesh, wl.material
+    ep, beta, kappa, _ = W.seeded_state(wl, frac, seed=0)
+    h = (np.prod(mesh.coord.max(axis=1) - mesh.coord.min(axis=1)) / mesh.n_elems) ** (1 / mesh.dim)
+    u_np = W.random_displacement(mesh, 1, 1e-6 * h, wl.free)
+    tb = 8 if tangent == "fp64" else 4
+    lp = {"fp64": _ep.EP_FP64, "fp32": _ep.EP_FP32, "bf16": _ep.EP_BF16}[local_prec]
+    ctx = _ep.Context(mesh, wl.free, mat,
+                      options={"tangent_prec": _ep.EP_FP64 if tb == 8 else _ep.EP_FP32,
+                               "local_prec": lp})
+    ctx.set_state(ep, beta if mat.model == "VM" else None, kappa if mat.model == "DP" else None)
+    u = ctx.tensor(u_np)
+    F = torch.empty(mesh.n_dof, dtype=torch.float64, device="cuda")
+
+    def step():
+        _ep.ep_constitutive(ctx.h, u)
+        _ep.ep_assemble_tangent(ctx.h)
+        _ep.ep_internal_force(ctx.h, F)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    n_ip, n_el = _ep.ep_get_plastic(ctx.h)
+    counts = {"plastic_elems": n_el, "plastic_ips": n_ip, "listed": n_el,
+              "n_perm": mesh.n_elems}
+    kb = kernel_bytes(mesh, mat, counts, tb)
+
+    def kernel_row(kname, tms, n):
+        t_step = tms / steps / 1e3
+        return {"ms_per_step": round(tms / steps, 4), "launches_per_step": n // steps,
+                "bytes_per_step": kb[kname],
+                "GB_s": round(kb[kname] / t_step / 1e9, 1) if t_step > 0 else None}
+
+    # per-kernel breakdown, every kernel timed: each timed dispatch costs a
+    # few microseconds, so these passes are not the timed region
+    _ep.ep_profile(ctx.h, 1)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    prof = {k: _ep.ep_profile_read(ctx.h, k) for k in _ep.PROF}
+    _ep.ep_profile(ctx.h, 0)
+    per_kernel = {k: kernel_row(k, *prof[k])
+                  for k in ("constitutive", "compaction", "assembly", "force") if prof[k][1] > 0}
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_per_step"])
+
+    # timed region: HIP events on the dominant kernel's launches only
+    _ep.ep_profile(ctx.h, 1, kernels=[dom])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    dom_ms, dom_n = _ep.ep_profile_read(ctx.h, dom)
+    _ep.ep_profile(ctx.h, 0)
+    ms = 1e3 * t / steps
+    value = mesh.n_int / (ms / 1e3) / 1e6
+    per_kernel[dom] = kernel_row(dom, dom_ms, dom_n)
+    per_kernel[dom]["timed_region"] = True
+    d = per_kernel[dom]
+    n_launch = max(1, d["launches_per_step"])
+    t_launch_s = d["ms_per_step"] / n_launch / 1e3
+    roofline = {"bound": "hbm", "kernel": dom, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "avg_launch_ms": round(d["ms_per_step"] / n_launch, 5),
+                "launches_per_step": n_launch, "copy_GB_s": copy_gbs}
+    if dom == "assembly":
+        scalar = assembly_bytes_scalar_model(mesh, counts, tb) / n_launch
+        design = kb["assembly"] / n_launch
+        roofline.update({
+            "bytes_model": "scalar-CSR model: per plastic point 8 (d n_p + 1) + 64 B, per "
+                           "plastic element (d n_p)^2 (4 + 2 s) x 2 (restore + add)",
+            "algorithmic_bytes_per_launch": int(scalar),
+            "achieved": round(scalar / t_launch_s / 1e9, 1),
+            "design_model": {
+                "what": "node-block CSR of this build: per listed element n_p^2 block "
+                        "position map entries, one-byte stamps, base value read and value "
+                        "write; per plastic element its nodes; per plastic point its tangent "
+                        "descriptor",
+                "algorithmic_bytes_per_launch": int(design),
+                "achieved": round(design / t_launch_s / 1e9, 1),
+                "frac": round(design / t_launch_s / 1e9 / HBM_PEAK_GBS, 4)}})
+    else:
+        roofline.update({"algorithmic_bytes_per_launch": int(d["bytes_per_step"] / n_launch),
+                         "achieved": d["GB_s"]})
+    roofline["frac"] = round(roofline["achieved"] / HBM_PEAK_GBS, 4)
+    roofline["frac_of_copy"] = round(roofline["achieved"] / copy_gbs, 4) if copy_gbs else None
+    roofline["traffic"] = None
+    if os.path.exists(TRAFFIC_FILE):
+        for tr in json.load(open(TRAFFIC_FILE)):
+            if tr.get("kernel_src_sha256") == src_hash() and tr.get("kernel") == dom and \
+                    tr.get("tangent") == tangent and tr.get("workload") == name:
+                roofline["traffic"] = tr.get("bytes_per_launch")
+    ctx.close()
+    del ctx, F, u
+    torch.cuda.empty_cache()
+    rec = {"workload": f"{name}: {MDESC.get(name, name)}", "plastic_fraction_seeded": frac,
+           "plastic_elements": n_el, "plastic_points": n_ip, "tangent": tangent,
+           "local_products": local_prec, "value": round(value, 2), "ms_per_step": round(ms, 4),
+           "roofline": roofline, "kernels": per_kernel}
+    log(f"pass {name} {tangent}: {value:.1f} M points/s, {ms:.4f} ms, {dom} "
+        f"{roofline['achieved']} GB/s")
+    return (rec, (wl, ep, beta, kappa, u_np)) if keep else rec
+
+
+def p1_square_newton():
+    """Time to |Q(f - F)| <= 1e-10 |Q f| over the ten load steps of the P1
+    square (FP64), from the first Newton evaluation of step 1 to the last
+    commit; one untimed run first."""
+    import torch
+    from paper_1805_04155_amd import _ep, solver
+    from paper_1805_04155_amd import workloads as W
+    wl = W.workload_p1_square()
+    rec = None
+    for rep in range(2):
+        ctx = _ep.Context(wl.mesh, wl.free, wl.material, options={"newton_rtol": 1e-10})
+        u = torch.zeros(wl.mesh.n_dof, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs = solver.solve_load_path(ctx, wl, u)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        ctx.close()
+        rec = {"workload": "plane strain 10x10 square, 32x32 squares split into 2048 P1 "
+                           "triangles (2048 points), von Mises kinematic, top traction 54k, "
+                           "k = 1..10",
+               "seconds": round(t, 4), "steps": len(recs),
+               "newton_its": sum(r["newton_its"] for r in recs),
+               "pcg_its": sum(r["pcg_its"] for r in recs),
+               "max_final_res_rel": max(r["res_rel"] for r in recs),
+               "plastic_points_last_step": recs[-1]["n_plastic_ip"]}
+    log(f"p1 square newton: {rec}")
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="q2_slope", choices=list(WORKLOADS))
+    ap.add_argument("--workload", default="q1_cube", choices=list(WORKLOADS))
     ap.add_argument("--plastic-fraction", type=float, default=0.5)
     ap.add_argument("--tangent", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-calibration-copy", action="store_true")
     ap.add_argument("--local-prec", choices=["fp64", "fp32", "bf16"], default="fp64",
                     help="element-local products (27-node hexahedra, P2 tetrahedra only)")
+    ap.add_argument("--no-slope", action="store_true",
+                    help="skip the slope passes (FP64 and FP32 tangent values)")
     ap.add_argument("--no-newton", action="store_true",
                     help="skip the time-to-1e-10 load paths and the local-precision report")
     ap.add_argument("--newton-cube-n", type=int, default=64)
@@ -531,121 +756,21 @@ def main():
               "MI355X (multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-
-    from paper_1805_04155_amd import _ep
-    from paper_1805_04155_amd import workloads as W
-
     torch.cuda.set_device(0)
-    wl = getattr(W, WORKLOADS[args.workload])()
-    mesh, mat = wl.mesh, wl.material
-    ep, beta, kappa, _ = W.seeded_state(wl, args.plastic_fraction, seed=0)
-    h = (np.prod(mesh.coord.max(axis=1) - mesh.coord.min(axis=1)) / mesh.n_elems) ** (1 / mesh.dim)
-    u_np = W.random_displacement(mesh, 1, 1e-6 * h, wl.free)
-
-    tb = 8 if args.tangent == "fp64" else 4
-    lp = {"fp64": _ep.EP_FP64, "fp32": _ep.EP_FP32, "bf16": _ep.EP_BF16}[args.local_prec]
-    ctx = _ep.Context(mesh, wl.free, mat,
-                      options={"tangent_prec": _ep.EP_FP64 if tb == 8 else _ep.EP_FP32,
-                               "local_prec": lp})
-    ctx.set_state(ep, beta if mat.model == "VM" else None, kappa if mat.model == "DP" else None)
-    u = ctx.tensor(u_np)
-    F = torch.empty(mesh.n_dof, dtype=torch.float64, device="cuda")
-
-    copy_gbs = None
-    if not args.no_calibration_copy:
-        # plain copy of a known size, for scaling hardware byte counters; then
-        # the measured copy rate (read + write bytes over time) as the
-        # practical HBM ceiling beside the published peak
-        a = torch.empty(64 * 2 ** 20, dtype=torch.float64, device="cuda").fill_(1.0)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            b.copy_(a)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(20):
-            b.copy_(a)
-        e1.record()
-        torch.cuda.synchronize()
-        copy_ms = e0.elapsed_time(e1) / 20
-        copy_gbs = round(2 * a.numel() * 8 / (copy_ms / 1e3) / 1e9, 1)
-        log(f"copy of 512 MiB: {copy_ms:.4f} ms, {copy_gbs} GB/s read + write")
-        del a, b
-
-    def step():
-        _ep.ep_constitutive(ctx.h, u)
-        _ep.ep_assemble_tangent(ctx.h)
-        _ep.ep_internal_force(ctx.h, F)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    n_ip, n_el = _ep.ep_get_plastic(ctx.h)
-    counts = {"plastic_elems": n_el, "plastic_ips": n_ip, "listed": n_el,
-              "n_perm": mesh.n_elems}
-    kb = kernel_bytes(mesh, mat, counts, tb)
-
-    def kernel_row(name, tms, n):
-        t_step = tms / args.steps / 1e3
-        return {"ms_per_step": round(tms / args.steps, 4),
-                "launches_per_step": n // args.steps,
-                "bytes_per_step": kb[name],
-                "GB_s": round(kb[name] / t_step / 1e9, 1) if t_step > 0 else None}
-
-    # per-kernel breakdown, every kernel timed: each timed dispatch costs a
-    # few microseconds, so these passes are not the timed region
-    _ep.ep_profile(ctx.h, 1)
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    prof = {k: _ep.ep_profile_read(ctx.h, k) for k in _ep.PROF}
-    _ep.ep_profile(ctx.h, 0)
-    per_kernel = {name: kernel_row(name, *prof[name])
-                  for name in ("constitutive", "compaction", "assembly", "force")
-                  if prof[name][1] > 0}
-    dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_per_step"])
-
-    # timed region: HIP events on the dominant kernel's launches only
-    _ep.ep_profile(ctx.h, 1, kernels=[dom])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    dom_ms, dom_n = _ep.ep_profile_read(ctx.h, dom)
-    _ep.ep_profile(ctx.h, 0)
-    ms = 1e3 * t / args.steps
-    value = mesh.n_int / (ms / 1e3) / 1e6
-    per_kernel[dom] = kernel_row(dom, dom_ms, dom_n)
-    per_kernel[dom]["timed_region"] = True
-    d = per_kernel[dom]
-    n_launch = max(1, d["launches_per_step"])
-    achieved = d["GB_s"]
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("kernel_src_sha256") == src_hash() and tr.get("kernel") == dom and \
-                tr.get("tangent") == args.tangent and tr.get("workload") == args.workload:
-            traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "algorithmic_bytes_per_launch": int(d["bytes_per_step"] / n_launch),
-                "avg_launch_ms": round(d["ms_per_step"] / n_launch, 5),
-                "traffic": traffic,
-                "copy_GB_s": copy_gbs,
-                "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None}
-
-    ctx.close()
-    del ctx, F, u
-    torch.cuda.empty_cache()
+    copy_gbs = None if args.no_calibration_copy else copy_calibration()
+    head, inputs = measure_pass(args.workload, args.plastic_fraction, args.tangent,
+                                args.local_prec, args.steps, args.warmup, copy_gbs, keep=True)
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, ep, beta, kappa, u_np)
-    newton = local = sweep = lshape = footing = None
+        cpu = cpu_baseline(*inputs)
+    del inputs
+    slope = p1 = newton = local = sweep = lshape = footing = None
+    if not args.no_slope and args.workload != "q2_slope":
+        slope = {t: measure_pass("q2_slope", 0.5, t, "fp64", args.steps, args.warmup, copy_gbs)
+                 for t in ("fp64", "fp32")}
+    if not args.no_newton:
+        p1 = p1_square_newton()
     if not args.no_sweep:
         sweep = plastic_sweep(max(5, args.steps // 2))
     if not args.no_lshape:
@@ -657,24 +782,26 @@ def main():
         local = local_precision_report(block)
         newton = newton_report(args.newton_cube_n, int(args.newton_samples), block)
 
-    mdesc = {"q2_slope": "plane strain 40x20 rectangle, 512x256 9-node Q2 quads (131072 elements, "
-                         "1179648 points), Drucker-Prager perfect c0=450 phi=20deg E=20000 nu=0.49",
-             "q1_cube": "unit cube, 64^3 Q1 hexahedra (2097152 points), von Mises kinematic "
-                        "E=206900 nu=0.29 sigma_y=450 H=10000"}.get(args.workload, args.workload)
     line = {
         "metric": "M integration pts/s (return map + K assembly)",
-        "value": round(value, 2), "unit": "M integration pts/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "value": head["value"], "unit": "M integration pts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if tb == 8 else "f64 (return map, force) / f32 (tangent values)",
+        "dtype": "f64" if args.tangent == "fp64" else
+                 "f64 (return map, force) / f32 (tangent values)",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {mdesc}", "plastic_fraction_seeded": args.plastic_fraction,
-                   "plastic_elements": n_el, "plastic_points": n_ip, "tangent": args.tangent,
+        "config": {"workload": head["workload"],
+                   "plastic_fraction_seeded": args.plastic_fraction,
+                   "plastic_elements": head["plastic_elements"],
+                   "plastic_points": head["plastic_points"], "tangent": args.tangent,
                    "local_products": args.local_prec,
-                   "step": "constitutive + compaction + incremental K assembly + internal force"},
-        "roofline": roofline,
-        "kernels": per_kernel,
+                   "step": "constitutive + compaction + incremental K assembly + internal "
+                           "force"},
+        "roofline": head["roofline"],
+        "kernels": head["kernels"],
         "cpu_baseline": cpu,
+        "q2_slope": slope,
+        "p1_square_newton": p1,
         "newton": newton,
         "local_precision": local,
         "plastic_sweep": sweep,

@@ -48,7 +48,8 @@ def solve_load_path(ctx, wl, u, steps=None, max_newton=50, callback=None, sync=N
         rec = {"step": k, "load": float(wl.load_factors[k]), "newton_its": len(hist) - 1,
                "pcg_its": sum(h["pcg_its"] for h in hist), "res_rel": hist[-1]["res_rel"],
                "n_plastic_ip": hist[-1]["n_plastic_ip"], "seconds": t,
-               "res_history": [h["res_rel"] for h in hist]}
+               "res_history": [h["res_rel"] for h in hist],
+               "energy_incr": [h["energy_incr"] for h in hist[:-1]]}
         records.append(rec)
         if callback is not None:
             callback(k, rec)
@@ -96,6 +97,8 @@ def displacement_path(ctx, wl, u, ud_max, du0=1e-3, du_max=None, dp_rel=0.01, ma
         rec = {"step": k, "u_D": ud_new, "pressure": p, "newton_its": len(hist) - 1,
                "pcg_its": sum(h["pcg_its"] for h in hist), "res_rel": hist[-1]["res_rel"],
                "n_plastic_ip": hist[-1]["n_plastic_ip"],
+               "ls_evals": sum(h["ls_evals"] for h in hist),
+               "steps": [h["step"] for h in hist[:-1]],
                "seconds": time.perf_counter() - t0}
         records.append(rec)
         if callback is not None:

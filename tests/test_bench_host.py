@@ -38,3 +38,15 @@ def test_assembly_bytes_scale_with_the_work_list():
     _, b1f = _bytes(10, 10, 10, tangent_bytes=4)
     assert b1["assembly"] - b1f["assembly"] == 10 * mesh.n_p ** 2 * 2 * mesh.dim ** 2 * 4
 
+
+
+def test_scalar_model_bytes_of_the_headline_pass():
+    """The scalar-CSR byte model on the 64^3 cube at half of the elements
+    plastic: 1048576 plastic points at 8 (24 + 1) + 64 = 264 B and 131072
+    plastic elements at 576 x (4 + 16) x 2 = 23040 B (FP64)."""
+    mesh = W.mesh_q1_3d(2, 2, 2, 1.0, 1.0, 1.0)
+    counts = {"plastic_elems": 131072, "plastic_ips": 1048576}
+    assert bench.assembly_bytes_scalar_model(mesh, counts, 8) == \
+        1048576 * 264 + 131072 * 23040
+    assert bench.assembly_bytes_scalar_model(mesh, counts, 4) == \
+        1048576 * 264 + 131072 * 576 * 12 * 2
