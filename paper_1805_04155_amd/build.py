@@ -16,7 +16,7 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
-SOURCES = ["ep_kernels.hip", "ep_mlp.hip", "ep_host.cpp"]
+SOURCES = ["ep_kernels.hip", "ep_mlp.hip", "ep_host.cpp", "ep_mesh_graph.cpp"]
 
 
 def build(verbose: bool = False) -> str:
@@ -25,7 +25,7 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
-        if src.endswith(".cpp"):
+        if src == "ep_host.cpp":
             cmd[1:1] = ["-x", "hip"]
         if verbose:
             print(" ".join(cmd), flush=True)

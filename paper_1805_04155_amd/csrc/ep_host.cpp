@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "ep_internal.h"
+#include "ep_mesh_graph.h"
 
 using namespace ep;
 
@@ -249,19 +250,6 @@ void builtin_rule(int id, int dim, std::vector<double> &xi, std::vector<double> 
       }
 }
 
-template <class F>
-void parallel_for(int64_t n, F f) {
-  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  if (n < 4096) nt = 1;
-  std::vector<std::thread> th;
-  const int64_t chunk = (n + nt - 1) / nt;
-  for (unsigned t = 0; t < nt; ++t) {
-    const int64_t a = t * chunk, b = std::min(n, a + chunk);
-    if (a >= b) break;
-    th.emplace_back([=] { f(a, b); });
-  }
-  for (auto &x : th) x.join();
-}
 
 template <class T>
 hipError_t dalloc(T **p, int64_t n) {
@@ -663,16 +651,6 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   if (const char *bad = material_error(mat)) return fail(std::string("ep_setup: ") + bad, EP_EINVAL);
   const int64_t n_n = mesh->n_nodes, n_e = mesh->n_elems;
   const int dim = ed.dim, n_p = ed.n_p, n_q = ed.n_q;
-  for (int64_t i = 0; i < n_e * n_p; ++i)
-    if (mesh->elem[i] < 0 || mesh->elem[i] >= n_n)
-      return fail("ep_setup: node id out of range in elem", EP_EINVAL);
-  // the nodes of an element are distinct (the assembly ranks them)
-  for (int64_t e = 0; e < n_e; ++e) {
-    const int32_t *en = mesh->elem + e * n_p;
-    for (int i = 0; i < n_p; ++i)
-      for (int j = i + 1; j < n_p; ++j)
-        if (en[i] == en[j]) return fail("ep_setup: repeated node in an element", EP_EINVAL);
-  }
 
   ep_options opt{EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2, EP_OPERATOR_ASSEMBLED, 0.0, 12};
   if (opt_in) opt = *opt_in;
@@ -710,6 +688,16 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   for (int q = 0; q < n_q; ++q) ref_gradients(ed.id, &xi[q * dim], &ref[(size_t)q * n_p * dim]);
   for (int q = 0; q < n_q; ++q) ref[(size_t)n_q * n_p * dim + q] = wq[q];
 
+  // mesh graph: node-block pattern, position maps, colouring (host)
+  const bool sorted_scatter = ed.id == ET_Q1_2D || ed.id == ET_Q2_2D || ed.id == ET_Q2S_2D ||
+                              ed.id == ET_Q1_3D;
+  MeshGraph gr;
+  {
+    const std::string why = build_mesh_graph(n_n, n_e, n_p, dim, mesh->elem, sorted_scatter,
+                                             CMP_CHUNK, 512, gr);
+    if (!why.empty()) return fail("ep_setup: " + why, EP_EINVAL);
+  }
+
   Ctx *c = new Ctx();
   c->stream = (hipStream_t)hip_stream;
   (void)hipGetDevice(&c->dev);
@@ -746,135 +734,16 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   } while (0)
 
   const int32_t *E = mesh->elem;
-  // node -> (element, local node), ascending element
-  std::vector<int32_t> n2e_ptr(n_n + 1, 0), n2e(n_e * n_p), fslot(n_e * n_p),
-      slot_elem(n_e * n_p);
-  for (int64_t i = 0; i < n_e * n_p; ++i) n2e_ptr[E[i] + 1]++;
-  for (int64_t m = 0; m < n_n; ++m) n2e_ptr[m + 1] += n2e_ptr[m];
-  {
-    std::vector<int32_t> fill(n2e_ptr.begin(), n2e_ptr.end() - 1);
-    for (int64_t e = 0; e < n_e; ++e)
-      for (int p = 0; p < n_p; ++p) {
-        const int32_t k = fill[E[e * n_p + p]]++;
-        n2e[k] = (int32_t)(e * n_p + p);
-        fslot[e * n_p + p] = k;  // element force vectors are stored node by node
-        slot_elem[k] = (int32_t)e;
-      }
-  }
-  // node adjacency -> node-block CSR
-  std::vector<int32_t> deg(n_n, 0);
-  auto neighbours = [&](int64_t m, std::vector<int32_t> &mark, std::vector<int32_t> &lst) {
-    lst.clear();
-    for (int k = n2e_ptr[m]; k < n2e_ptr[m + 1]; ++k) {
-      const int64_t e = n2e[k] / n_p;
-      for (int p = 0; p < n_p; ++p) {
-        const int32_t v = E[e * n_p + p];
-        if (mark[v] != (int32_t)m) {
-          mark[v] = (int32_t)m;
-          lst.push_back(v);
-        }
-      }
-    }
-    std::sort(lst.begin(), lst.end());
-  };
-  parallel_for(n_n, [&](int64_t a, int64_t b) {
-    std::vector<int32_t> mark(n_n, -1), lst;
-    for (int64_t m = a; m < b; ++m) {
-      neighbours(m, mark, lst);
-      deg[m] = (int32_t)lst.size();
-    }
-  });
-  int64_t nnzb = 0;
-  for (int64_t m = 0; m < n_n; ++m) nnzb += deg[m];
-  if (nnzb * dim * dim >= (int64_t)1 << 31) {
-    c->err = "ep_setup: matrix too large for 32-bit indices";
-    return bail(EP_EINVAL);
-  }
-  std::vector<int32_t> bptr(n_n + 1, 0);
-  for (int64_t m = 0; m < n_n; ++m) bptr[m + 1] = bptr[m] + deg[m];
+  const int64_t nnzb = gr.nnzb;
   c->nnzb = nnzb;
-  std::vector<int32_t> bcol(nnzb), bdiag(n_n);
-  parallel_for(n_n, [&](int64_t a, int64_t b) {
-    std::vector<int32_t> mark(n_n, -1), lst;
-    for (int64_t m = a; m < b; ++m) {
-      neighbours(m, mark, lst);
-      std::copy(lst.begin(), lst.end(), bcol.begin() + bptr[m]);
-      bdiag[m] = (int32_t)(bptr[m] + (std::lower_bound(lst.begin(), lst.end(), (int32_t)m) - lst.begin()));
-    }
-  });
-  // element position map of node pairs
-  std::vector<int32_t> bpos((size_t)n_e * n_p * n_p);
-  parallel_for(n_e, [&](int64_t a, int64_t b) {
-    for (int64_t e = a; e < b; ++e)
-      for (int p = 0; p < n_p; ++p) {
-        const int32_t m = E[e * n_p + p];
-        const int32_t *lo = bcol.data() + bptr[m], *hi = bcol.data() + bptr[m + 1];
-        for (int pp = 0; pp < n_p; ++pp) {
-          const int32_t *it = std::lower_bound(lo, hi, E[e * n_p + pp]);
-          bpos[(e * n_p + p) * n_p + pp] = (int32_t)(it - bcol.data());
-        }
-      }
-  });
-  // position map with each row's columns in ascending global node order
-  // (the sorted scatter of quadrilaterals and 8-node hexahedra)
-  const bool sorted_scatter = ed.id == ET_Q1_2D || ed.id == ET_Q2_2D || ed.id == ET_Q2S_2D ||
-                              ed.id == ET_Q1_3D;
-  std::vector<int32_t> bposs;
-  if (sorted_scatter) {
-    bposs.resize((size_t)n_e * n_p * n_p);
-    parallel_for(n_e, [&](int64_t a, int64_t b) {
-      std::vector<int> ord(n_p);
-      for (int64_t e = a; e < b; ++e) {
-        std::iota(ord.begin(), ord.end(), 0);
-        std::sort(ord.begin(), ord.end(),
-                  [&](int x, int y) { return E[e * n_p + x] < E[e * n_p + y]; });
-        for (int p = 0; p < n_p; ++p)
-          for (int r = 0; r < n_p; ++r)
-            bposs[(e * n_p + p) * n_p + r] = bpos[(e * n_p + p) * n_p + ord[r]];
-      }
-    });
-  }
-  // greedy colouring: elements of one colour share no node
-  std::vector<int32_t> colour(n_e, -1);
-  int n_col = 0;
-  {
-    std::vector<uint64_t> used(8);
-    for (int64_t e = 0; e < n_e; ++e) {
-      std::fill(used.begin(), used.end(), 0);
-      for (int p = 0; p < n_p; ++p) {
-        const int32_t m = E[e * n_p + p];
-        for (int k = n2e_ptr[m]; k < n2e_ptr[m + 1]; ++k) {
-          const int64_t e2 = n2e[k] / n_p;
-          if (e2 < e) {
-            const int cc = colour[e2];
-            used[cc >> 6] |= 1ull << (cc & 63);
-          }
-        }
-      }
-      int cc = 0;
-      while (cc < 512 && ((used[cc >> 6] >> (cc & 63)) & 1ull)) ++cc;
-      if (cc >= 512) {
-        c->err = "ep_setup: colouring needs more than 512 colours";
-        return bail(EP_EINVAL);
-      }
-      colour[e] = cc;
-      n_col = std::max(n_col, cc + 1);
-    }
-  }
+  const int n_col = gr.n_col;
   c->n_col = n_col;
-  c->colour_size.assign(n_col, 0);
-  for (int64_t e = 0; e < n_e; ++e) c->colour_size[colour[e]]++;
-  c->colour_first_block.assign(n_col + 1, 0);
-  for (int col = 0; col < n_col; ++col)
-    c->colour_first_block[col + 1] =
-        c->colour_first_block[col] + (int32_t)((c->colour_size[col] + CMP_CHUNK - 1) / CMP_CHUNK);
+  c->colour_size.assign(gr.colour_size.begin(), gr.colour_size.end());
+  c->colour_first_block = gr.colour_first_chunk;
   c->n_perm = (int64_t)c->colour_first_block[n_col] * CMP_CHUNK;
-  std::vector<int32_t> perm(std::max<int64_t>(c->n_perm, 1), -1);
-  {
-    std::vector<int64_t> fill(n_col);
-    for (int col = 0; col < n_col; ++col) fill[col] = (int64_t)c->colour_first_block[col] * CMP_CHUNK;
-    for (int64_t e = 0; e < n_e; ++e) perm[fill[colour[e]]++] = (int32_t)e;
-  }
+  const std::vector<int32_t> &n2e_ptr = gr.n2e_ptr, &fslot = gr.fslot, &slot_elem = gr.slot_elem,
+                             &bptr = gr.bptr, &bcol = gr.bcol, &bdiag = gr.bdiag,
+                             &bpos = gr.bpos, &bposs = gr.bposs, &perm = gr.perm;
 
   // device memory
   hipStream_t s = c->stream;
