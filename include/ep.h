@@ -396,6 +396,29 @@ ep_status ep_mlp_loss_grad(ep_mlp *mlp, const float *X, const float *T, int64_t 
 ep_status ep_mlp_adam_step(ep_mlp *mlp, const float *X, const float *T, int64_t n, float lr,
                            float *loss);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc): the loss gradient of ep_mlp_loss_grad for a network given
+ * by its parameters alone, params[EP_MLP_NPARAM] (device, the layout of
+ * ep_mlp_set_params), with products in prec = EP_FP32 or EP_BF16 (FP32
+ * accumulation); X, T, grad, loss as in ep_mlp_loss_grad (grad and loss
+ * may be NULL).  Allocates nothing: the per-tile partial gradients live in
+ * a static device array of ceil(EP_MLP_NOALLOC_MAX_BATCH / 32) x
+ * (EP_MLP_NPARAM + 1) floats (4.9 MB), one per device, kept until the
+ * process ends.  Runs on the current device; hip_stream (NULL: the default
+ * stream) must belong to it.  Enqueued; no synchronisation.  The result
+ * equals ep_mlp_loss_grad's bit for bit (same kernels, same fixed-order
+ * reduction).  Calls that overlap in time on one device share the array
+ * and race: order them on one stream.  Errors (no context, so the message
+ * is thread-local, from ep_mlp_noalloc_last_error): EP_EINVAL for another
+ * prec, NULL inputs or n outside 1..EP_MLP_NOALLOC_MAX_BATCH; EP_EDEVICE if
+ * the device array cannot be located or a launch fails. */
+#define EP_MLP_NOALLOC_MAX_BATCH 2048
+ep_status ep_mlp_loss_grad_noalloc(int32_t prec, const float *params, const float *X,
+                                   const float *T, int64_t n, float *grad, float *loss,
+                                   void *hip_stream);
+const char *ep_mlp_noalloc_last_error(void);
+
 /* Training samples from the exact return map (Sections 2.2, 2.3): sample j
  * takes the pooled state i = idx[j] (0 <= i < n_pool) - strain
  * eps_pool[6][n_pool], plastic strain ep_pool[6][n_pool], back stress

@@ -77,6 +77,7 @@ class ep_warm_info(C.Structure):
 
 
 MLP_IN, MLP_HID, MLP_OUT, MLP_XS, MLP_YS, MLP_NPARAM = 13, 128, 7, 16, 8, 19207
+MLP_NOALLOC_MAX_BATCH = 2048
 
 _lib = None
 
@@ -126,6 +127,8 @@ def lib():
             "ep_mlp_features": [P, P, P],
             "ep_warm_start": [P, P, P, P, P, D, D, P, P],
             "ep_predictor": [P, P, P, D, P],
+            "ep_mlp_loss_grad_noalloc": [I32, P, P, P, I64, P, P, P],
+            "ep_mlp_noalloc_last_error": [],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -135,6 +138,7 @@ def lib():
         L.ep_last_error.restype = C.c_char_p
         L.ep_mlp_destroy.restype = None
         L.ep_mlp_last_error.restype = C.c_char_p
+        L.ep_mlp_noalloc_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -148,7 +152,8 @@ EXPORTED = ["ep_setup", "ep_destroy", "ep_last_error", "ep_set_stream", "ep_get_
             "ep_profile", "ep_profile_read", "ep_mlp_create", "ep_mlp_destroy",
             "ep_mlp_last_error", "ep_mlp_set_params", "ep_mlp_get_params", "ep_mlp_forward",
             "ep_mlp_loss_grad", "ep_mlp_adam_step", "ep_mlp_datagen", "ep_mlp_features",
-            "ep_warm_start", "ep_predictor"]
+            "ep_warm_start", "ep_predictor", "ep_mlp_loss_grad_noalloc",
+            "ep_mlp_noalloc_last_error"]
 
 
 def _ptr(t):
@@ -542,6 +547,23 @@ def ep_mlp_loss_grad(m, X, T, n, grad=None, loss=None):
                                          _dev(T, "f32", n * MLP_YS, "T"), n,
                                          _dev(grad, "f32", MLP_NPARAM, "grad"),
                                          _dev(loss, "f32", 1, "loss")))
+
+
+def ep_mlp_loss_grad_noalloc(prec, params, X, T, n, grad=None, loss=None, stream=None):
+    """Loss gradient of the network given by its parameters (device, float32)
+    with the library's static device scratch (allocates nothing)."""
+    st = lib().ep_mlp_loss_grad_noalloc(int(prec), _dev(params, "f32", MLP_NPARAM, "params"),
+                                        _dev(X, "f32", max(n, 0) * MLP_XS, "X"),
+                                        _dev(T, "f32", max(n, 0) * MLP_YS, "T"), int(n),
+                                        _dev(grad, "f32", MLP_NPARAM, "grad"),
+                                        _dev(loss, "f32", 1, "loss"),
+                                        stream if stream is not None else _stream())
+    if st != EP_OK:
+        raise EpError(st, lib().ep_mlp_noalloc_last_error().decode())
+
+
+def ep_mlp_noalloc_last_error():
+    return lib().ep_mlp_noalloc_last_error().decode()
 
 
 def ep_mlp_adam_step(m, X, T, n, lr, loss=None):

@@ -127,6 +127,12 @@ hipError_t launch_mlp_datagen(const MatC &mat, int64_t n, const int64_t *idx, in
                               const double *deps, float *X, float *T, double s_in, double s_out,
                               hipStream_t s);
 int64_t mlp_tile_samples();
+// loss gradient of a batch (and, with adam_params, one Adam step on them)
+// with the per-tile partials in part[n_tiles][EP_MLP_NPARAM] and
+// part_loss[n_tiles] (n_tiles = ceil(n / 32))
+hipError_t mlp_grad(int prec, const float *params, float *part, float *part_loss, hipStream_t s,
+                    const float *X, const float *T, int64_t n, float *grad, float *loss,
+                    float *adam_params, float *m1, float *m2, float lr, float bc1, float bc2);
 // feature / output scales of a material: s_in = E/S, s_out = 1/S
 void mlp_scales(const MatC &m, double E, double &s_in, double &s_out);
 // material checks shared by ep_setup and the sample generator (ep_host.cpp)

@@ -10,6 +10,7 @@
 // Weight gradients of a block go to a partial buffer, summed afterwards in
 // block order (no atomics), so a gradient is bitwise reproducible.
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "ep_internal.h"
@@ -344,25 +345,35 @@ hipError_t launch_mlp_forward(const MlpImpl &m, const float *X, int64_t n, float
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_train(MlpImpl &m, const float *X, const float *T, int64_t n, float *grad,
-                            float *loss, bool adam, float lr, float bc1, float bc2) {
+// Loss gradient (and optionally one Adam step) of a batch with the
+// per-tile partials in part[n_tiles][NPAR] and part_loss[n_tiles]
+hipError_t mlp_grad(int prec, const float *params, float *part, float *part_loss,
+                           hipStream_t s, const float *X, const float *T, int64_t n, float *grad,
+                           float *loss, float *adam_params, float *m1, float *m2, float lr,
+                           float bc1, float bc2) {
   MlpArgs a{};
-  a.params = m.params;
+  a.params = params;
   a.X = X;
   a.T = T;
-  a.part = m.part;
-  a.part_loss = m.part_loss;
+  a.part = part;
+  a.part_loss = part_loss;
   a.n = n;
   a.inv_n = 1.0f / (float)n;
   const int nblk = blocks_of(n, TB);
-  if (m.prec == EP_BF16)
-    hipLaunchKernelGGL((k_mlp_tile<true, true>), dim3(nblk), dim3(256), 0, m.stream, a);
+  if (prec == EP_BF16)
+    hipLaunchKernelGGL((k_mlp_tile<true, true>), dim3(nblk), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((k_mlp_tile<false, true>), dim3(nblk), dim3(256), 0, m.stream, a);
-  hipLaunchKernelGGL(k_mlp_reduce, dim3(blocks_of(NPAR, RED_P)), dim3(256), 0, m.stream, m.part,
-                     m.part_loss, nblk, a.inv_n, grad, loss, m.params, m.m1, m.m2, lr, bc1, bc2,
-                     adam ? 1 : 0);
+    hipLaunchKernelGGL((k_mlp_tile<false, true>), dim3(nblk), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3(blocks_of(NPAR, RED_P)), dim3(256), 0, s, part,
+                     part_loss, nblk, a.inv_n, grad, loss, adam_params, m1, m2, lr, bc1, bc2,
+                     adam_params ? 1 : 0);
   return hipGetLastError();
+}
+
+hipError_t launch_mlp_train(MlpImpl &m, const float *X, const float *T, int64_t n, float *grad,
+                            float *loss, bool adam, float lr, float bc1, float bc2) {
+  return mlp_grad(m.prec, m.params, m.part, m.part_loss, m.stream, X, T, n, grad, loss,
+                  adam ? m.params : nullptr, m.m1, m.m2, lr, bc1, bc2);
 }
 
 hipError_t launch_mlp_datagen(const MatC &mat, int64_t n, const int64_t *idx, int64_t n_pool,
@@ -379,6 +390,38 @@ hipError_t launch_mlp_datagen(const MatC &mat, int64_t n, const int64_t *idx, in
 int64_t mlp_tile_samples() { return TB; }
 
 }  // namespace ep
+
+// ---------------------------------------------------------------------------
+// Device scratch of ep_mlp_loss_grad_noalloc: per-tile partial gradients
+// [EP_MLP_NOALLOC_MAX_BATCH / 32][NPAR] followed by the per-tile losses.  One
+// copy per device, alive until the process ends; host code uses only the
+// address hipGetSymbolAddress returns for the current device (the symbol
+// itself is a host-side stand-in).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t NOALLOC_TILES = EP_MLP_NOALLOC_MAX_BATCH / 32;
+static_assert(EP_MLP_NOALLOC_MAX_BATCH % 32 == 0, "whole tiles of 32 samples");
+__device__ __align__(256) float scratch[NOALLOC_TILES * (EP_MLP_NPARAM + 1)];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[MAX_DEVICES] = {};
+thread_local std::string g_noalloc_err;
+
+// address of this device's scratch (looked up once per device, with the
+// device current)
+hipError_t scratch_address(int dev, float **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<float *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // C ABI of the network (include/ep.h)
@@ -489,6 +532,43 @@ ep_status ep_mlp_adam_step(ep_mlp *mlp, const float *X, const float *T, int64_t 
   MLPC(m, ep::launch_mlp_train(*m, X, T, n, nullptr, loss, true, lr, bc1, bc2));
   return EP_OK;
 }
+
+ep_status ep_mlp_loss_grad_noalloc(int32_t prec, const float *params, const float *X,
+                                   const float *T, int64_t n, float *grad, float *loss,
+                                   void *hip_stream) {
+  auto fail = [](const std::string &m, ep_status st) {
+    g_noalloc_err = m;
+    return st;
+  };
+  if (prec != EP_FP32 && prec != EP_BF16)
+    return fail("ep_mlp_loss_grad_noalloc: prec must be EP_FP32 or EP_BF16", EP_EINVAL);
+  if (!params || !X || !T)
+    return fail("ep_mlp_loss_grad_noalloc: NULL params, X or T", EP_EINVAL);
+  if (n < 1 || n > EP_MLP_NOALLOC_MAX_BATCH)
+    return fail("ep_mlp_loss_grad_noalloc: need 1 <= n <= EP_MLP_NOALLOC_MAX_BATCH (" +
+                    std::to_string(EP_MLP_NOALLOC_MAX_BATCH) + "), got " + std::to_string(n),
+                EP_EINVAL);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= MAX_DEVICES)
+    return fail(std::string("ep_mlp_loss_grad_noalloc: no usable current device: ") +
+                    hipGetErrorString(e), EP_EDEVICE);
+  float *scr = nullptr;
+  e = scratch_address(dev, &scr);
+  if (e != hipSuccess)
+    return fail(std::string("ep_mlp_loss_grad_noalloc: hipGetSymbolAddress: ") +
+                    hipGetErrorString(e), EP_EDEVICE);
+  // every tile writes all of its partials: nothing needs clearing
+  e = ep::mlp_grad(prec, params, scr, scr + NOALLOC_TILES * EP_MLP_NPARAM,
+                   (hipStream_t)hip_stream, X, T, n, grad, loss, nullptr, nullptr, nullptr, 0.f,
+                   1.f, 1.f);
+  if (e != hipSuccess)
+    return fail(std::string("ep_mlp_loss_grad_noalloc: launch: ") + hipGetErrorString(e),
+                EP_EDEVICE);
+  return EP_OK;
+}
+
+const char *ep_mlp_noalloc_last_error(void) { return g_noalloc_err.c_str(); }
 
 ep_status ep_mlp_datagen(const ep_material *material, int64_t n, const int64_t *idx,
                          int64_t n_pool, const double *eps_pool, const double *ep_pool,
