@@ -89,6 +89,19 @@ typedef enum { EP_FP64 = 0, EP_FP32 = 1, EP_BF16 = 2 } ep_prec;
  *            diag K_elast plus the diagonals of those element terms. */
 typedef enum { EP_OPERATOR_ASSEMBLED = 0, EP_OPERATOR_SPLIT = 1 } ep_operator;
 
+/* How an assembled K_tangent (and K_elast) is formed from the element terms
+ * of eq. K-split; both give the same K up to the order of the sums.
+ * COLOURS: one launch per element colour (elements of a colour share no
+ *          node); each element adds its node blocks to K in place, a
+ *          one-byte stamp per block telling whether the block still holds
+ *          the previous assembly's values (then it starts from K_elast).
+ * ROWS:    two launches: the element matrices of the elements with plastic
+ *          points go to a buffer (one slot per element), then every node
+ *          row touched by an element plastic now or at the last assembly
+ *          is rewritten once as its K_elast row plus those elements' rows
+ *          (ascending element), accumulated in LDS. */
+typedef enum { EP_ASSEMBLY_COLOURS = 0, EP_ASSEMBLY_ROWS = 1 } ep_assembly;
+
 typedef struct {
   int32_t dim;               /* 2 (plane strain) or 3                        */
   int32_t type;              /* ep_elem                                      */
@@ -128,6 +141,7 @@ typedef struct {
                                 remark after eq. lin_syst); 0 = full steps    */
   int32_t ls_max_evals;      /* residual evaluations per line search (<= 0:
                                 12)                                          */
+  int32_t assembly;          /* ep_assembly (default EP_ASSEMBLY_COLOURS)    */
 } ep_options;
 
 typedef struct {

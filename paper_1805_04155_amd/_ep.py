@@ -18,6 +18,7 @@ EP_P1, EP_P2, EP_Q1, EP_Q2, EP_Q2S = 1, 2, 3, 4, 5
 EP_VM, EP_DP = 1, 2
 EP_FP64, EP_FP32, EP_BF16 = 0, 1, 2
 EP_OPERATOR_ASSEMBLED, EP_OPERATOR_SPLIT = 0, 1
+EP_ASSEMBLY_COLOURS, EP_ASSEMBLY_ROWS = 0, 1
 PROF = dict(constitutive=0, compaction=1, split=2, assembly=3, force=4, spmv=5, pcg_vec=6,
             elastic=7)
 
@@ -52,7 +53,7 @@ class ep_options(C.Structure):
                 ("pcg_max_it", C.c_int32), ("pcg_check_every", C.c_int32),
                 ("newton_rtol", C.c_double), ("pcg_forcing_max", C.c_double),
                 ("operator_form", C.c_int32), ("newton_damping", C.c_double),
-                ("ls_max_evals", C.c_int32)]
+                ("ls_max_evals", C.c_int32), ("assembly", C.c_int32)]
 
 
 class ep_sizes(C.Structure):
@@ -223,7 +224,8 @@ def ep_setup(mesh, free, material, options=None, quadrature=None, stream=None):
     m = ep_mesh(dim, et, mesh.n_nodes, mesh.n_elems, coord.ctypes.data, elem.ctypes.data,
                 free.ctypes.data)
     mat = _material(material)
-    opt = ep_options(EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2, EP_OPERATOR_ASSEMBLED, 0.0, 12)
+    opt = ep_options(EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2, EP_OPERATOR_ASSEMBLED, 0.0, 12,
+                     EP_ASSEMBLY_COLOURS)
     for k, v in (options or {}).items():
         setattr(opt, k, v)
     q = None

@@ -267,7 +267,7 @@ hipError_t upload(T *d, const std::vector<T> &h, hipStream_t s) {
 void free_ctx(Ctx *c) {
   if (!c) return;
   void *ptrs[] = {c->coord, c->elem, c->freem, c->ref, c->bptr, c->bcol, c->bdiag, c->bpos,
-                  c->Ke, c->Ke32, c->Kt, c->epoch, c->bposs, c->n2e_ptr, c->fslot, c->slot_elem, c->Fp, c->ecol_perm,
+                  c->Ke, c->Ke32, c->Kt, c->epoch, c->bposs, c->n2e_ptr, c->n2e, c->emat, c->fslot, c->slot_elem, c->Fp, c->ecol_perm,
                   c->d_colour_first_block, c->ep_s, c->beta_s, c->kappa_s, c->flag, c->desc,
                   c->Fe, c->em[0], c->em[1], c->plist, c->coff, c->ptotals, c->cmp_counts,
                   c->cmp_counts2, c->cmp_counts3, c->F, c->r, c->partials,
@@ -385,9 +385,23 @@ ep_status do_assemble(Ctx *c) {
     c->err = "ep_assemble_tangent: no constitutive evaluation since setup or commit";
     return EP_ESTATE;
   }
-  // one-byte stamps: before the counter passes 255 every stamp is cleared
-  // (a block without this assembly's stamp starts from K_elast, so clearing
-  // is always safe)
+  if (c->opt.assembly == EP_ASSEMBLY_ROWS) {
+    // element matrices of the listed elements with plastic points now, then
+    // the node-row gather of every row they or the last assembly touched
+    const int64_t listed = c->coff_known ? (int64_t)(c->coff_h[c->n_col] - c->coff_h[0]) : -1;
+    if (listed != 0) {
+      ProfScope ps(*c, PROF_ASSEMBLE);
+      if (ps.tok >= 0) c->pending[ps.tok].count = 2;
+      HIPC(launch_emat(*c, false, listed));
+      HIPC(launch_row_gather(*c, false));
+    }
+    c->em_asm = c->em_cur;
+    c->coff_known = false;
+    return EP_OK;
+  }
+  // colour rounds with one-byte stamps: before the counter passes 255 every
+  // stamp is cleared (a block without this assembly's stamp starts from
+  // K_elast, so clearing is always safe)
   if (c->epoch_counter == 255) {
     HIPC(hipMemsetAsync(c->epoch, 0, std::max<int64_t>(c->nnzb, 1), c->stream));
     c->epoch_counter = 0;
@@ -652,8 +666,11 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   const int64_t n_n = mesh->n_nodes, n_e = mesh->n_elems;
   const int dim = ed.dim, n_p = ed.n_p, n_q = ed.n_q;
 
-  ep_options opt{EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2, EP_OPERATOR_ASSEMBLED, 0.0, 12};
+  ep_options opt{EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2, EP_OPERATOR_ASSEMBLED, 0.0, 12,
+                 EP_ASSEMBLY_COLOURS};
   if (opt_in) opt = *opt_in;
+  if (opt.assembly != EP_ASSEMBLY_COLOURS && opt.assembly != EP_ASSEMBLY_ROWS)
+    return fail("ep_setup: assembly must be EP_ASSEMBLY_COLOURS or EP_ASSEMBLY_ROWS", EP_EINVAL);
   if (!(opt.newton_damping >= 0.0 && opt.newton_damping < 1.0))
     return fail("ep_setup: newton_damping must lie in [0, 1)", EP_EINVAL);
   if (opt.ls_max_evals <= 0) opt.ls_max_evals = 12;
@@ -741,6 +758,15 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   c->colour_size.assign(gr.colour_size.begin(), gr.colour_size.end());
   c->colour_first_block = gr.colour_first_chunk;
   c->n_perm = (int64_t)c->colour_first_block[n_col] * CMP_CHUNK;
+  for (int64_t m = 0; m < n_n; ++m) {
+    c->max_deg = std::max(c->max_deg, gr.bptr[m + 1] - gr.bptr[m]);
+    c->max_slots = std::max(c->max_slots, gr.n2e_ptr[m + 1] - gr.n2e_ptr[m]);
+  }
+  if (sizeof(double) * (size_t)c->max_deg * dim * dim + sizeof(int) * (size_t)c->max_slots >
+      65536) {
+    c->err = "ep_setup: a node row does not fit the 64 KB of LDS of the row gather";
+    return bail(EP_EINVAL);
+  }
   const std::vector<int32_t> &n2e_ptr = gr.n2e_ptr, &fslot = gr.fslot, &slot_elem = gr.slot_elem,
                              &bptr = gr.bptr, &bcol = gr.bcol, &bdiag = gr.bdiag,
                              &bpos = gr.bpos, &bposs = gr.bposs, &perm = gr.perm;
@@ -766,6 +792,11 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   }
   SETUP_HIP(dalloc(&c->epoch, nnzb));
   SETUP_HIP(dalloc(&c->n2e_ptr, n_n + 1));
+  SETUP_HIP(dalloc(&c->n2e, n_e * n_p));
+  // element matrices of the row-gather assembly, FP64 size (matrix-core
+  // products store FP32 in it)
+  if (opt.assembly == EP_ASSEMBLY_ROWS)
+    SETUP_HIP(hipMalloc(&c->emat, sizeof(double) * std::max<int64_t>(1, n_e * n_p * n_p * dim * dim)));
   SETUP_HIP(dalloc(&c->fslot, n_e * n_p));
   SETUP_HIP(dalloc(&c->slot_elem, n_e * n_p));
   SETUP_HIP(dalloc(&c->Fp, n_e * n_p * dim));
@@ -818,6 +849,7 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   SETUP_HIP(upload(c->bpos, bpos, s));
   if (sorted_scatter) SETUP_HIP(upload(c->bposs, bposs, s));
   SETUP_HIP(upload(c->n2e_ptr, n2e_ptr, s));
+  SETUP_HIP(upload(c->n2e, gr.n2e, s));
   SETUP_HIP(upload(c->fslot, fslot, s));
   SETUP_HIP(upload(c->slot_elem, slot_elem, s));
   SETUP_HIP(upload(c->ecol_perm, perm, s));

@@ -88,6 +88,12 @@ hipError_t launch_copy_ke_to_kt(Ctx &c);
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t s);
 hipError_t launch_csr_expand(Ctx &c, int which, int32_t *row_ptr, int32_t *col_idx, double *val);
 hipError_t launch_pos_expand(Ctx &c, int32_t *pos);
+// element matrices of the listed elements with plastic points now (elastic:
+// of every element) into c.emat; listed = work-list length if known (< 0:
+// unknown)
+hipError_t launch_emat(Ctx &c, bool elastic, int64_t listed);
+// node-row gather of c.emat into K_tangent (elastic: into K_elast)
+hipError_t launch_row_gather(Ctx &c, bool elastic);
 hipError_t launch_diag_inv(Ctx &c);
 hipError_t launch_spmv(Ctx &c, const double *x, double *y);
 // split form of the tangent: y = Q K_elast x + Q sum over plastic elements of
@@ -178,6 +184,11 @@ struct Ctx {
   // (one per incident element, ascending element) are n2e_ptr[m] ..
   // n2e_ptr[m+1]-1, and element e's local node p writes entry fslot[e*n_p+p]
   int32_t *n2e_ptr = nullptr;  // [n_n+1]
+  int32_t *n2e = nullptr;      // [n_e*n_p] slot -> e * n_p + p
+  // element matrices [n_e][n_p][n_p][dim][dim] (double, or float for
+  // matrix-core local products) of the row-gather assembly
+  void *emat = nullptr;
+  int max_deg = 0, max_slots = 0;  // largest node row (blocks) and node-to-element count
   int32_t *fslot = nullptr;    // [n_e*n_p]
 
   // colouring

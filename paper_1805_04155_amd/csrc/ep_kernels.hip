@@ -425,6 +425,13 @@ struct KA {
   int cur;         // this assembly's stamp, 1..255
   int elastic;
   double G, K;
+  // element-matrix mode: the elements of work-list colours colour ..
+  // colour_end - 1 with plastic points write Delta K_e (or K_e) to
+  // emat[e][p][p'][r][c] (FP64: emat64, matrix cores: emat32) instead of
+  // scattering it
+  int colour_end;
+  double *emat64;
+  float *emat32;
 };
 
 template <int ETID>
@@ -508,7 +515,7 @@ __device__ inline void tangent_matrix(const double *desc, bool elastic, double G
     }
 }
 
-template <int ETID, typename VT>
+template <int ETID, typename VT, bool EMAT = false>
 __global__ __launch_bounds__(AsmCfg<ETID>::BS)
 __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a) {
   using T = Et<ETID>;
@@ -537,7 +544,7 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
   int64_t k0 = a.k0, k1 = a.k1;
   if (a.off) {
     k0 = a.off[a.colour];
-    k1 = a.off[a.colour + 1];
+    k1 = a.off[EMAT ? a.colour_end : a.colour + 1];
   }
   VT *Kt = (VT *)a.Kt;
   const uint32_t qmask = NQ == 32 ? 0xffffffffu : ((1u << NQ) - 1u);
@@ -562,6 +569,7 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
   // (sorted scatter: also the block positions of the next element, so that
   // the freshness stamps can be read as soon as an element starts)
   constexpr int NIP = SORTED ? NSLOT : 1;
+  constexpr bool PREPOS = SORTED && !EMAT;  // positions prefetched for the sorted scatter
   int64_t k = k0 + blockIdx.x;
   int e_n = k < k1 ? a.list[k] : -1;
   uint32_t m_n = (e_n >= 0 && !a.elastic) ? a.emask[e_n] : 0xffffffffu;
@@ -570,7 +578,7 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
 #pragma unroll
   for (int sl = 0; sl < NIP; ++sl) {
     const int t = tid + sl * BS;
-    ip_n[sl] = (SORTED && e_n >= 0 && t < NB2) ? a.bposs[(int64_t)e_n * NB2 + t] : 0;
+    ip_n[sl] = (PREPOS && e_n >= 0 && t < NB2) ? a.bposs[(int64_t)e_n * NB2 + t] : 0;
   }
   for (; k < k1; k += gridDim.x) {
     const int e = e_n;
@@ -589,8 +597,13 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
 #pragma unroll
       for (int sl = 0; sl < NIP; ++sl) {
         const int t = tid + sl * BS;
-        ip_n[sl] = (SORTED && e_n >= 0 && t < NB2) ? a.bposs[(int64_t)e_n * NB2 + t] : 0;
+        ip_n[sl] = (PREPOS && e_n >= 0 && t < NB2) ? a.bposs[(int64_t)e_n * NB2 + t] : 0;
       }
+      continue;
+    }
+    if (EMAT && !mask) {  // no plastic point: no element term (uniform)
+      m_n = (e_n >= 0 && !a.elastic) ? a.emask[e_n] : 0xffffffffu;
+      node_n = (e_n >= 0 && tid < NP) ? a.elem[(int64_t)e_n * NP + tid] : 0;
       continue;
     }
     const int nq = __popc(mask);
@@ -598,7 +611,13 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
     // pair mode, the blocks (p, p') and (p', p) of this thread's pairs
     int64_t i1[SORTED ? NSLOT : NBT], i2[SORTED ? 1 : NBT];
     bool f1[SORTED ? NSLOT : NBT], f2[SORTED ? 1 : NBT];
-    if constexpr (SORTED) {
+    if constexpr (EMAT) {
+      if constexpr (SORTED) {
+        __syncthreads();  // LDS of the previous element is no longer read
+        if (tid < NP) s_node[tid] = node_cur;
+        __syncthreads();
+      }
+    } else if constexpr (SORTED) {
       // slot t = p * NP + r: block (p, r-th node by global id), position
       // prefetched; its stamp is read at once
 #pragma unroll
@@ -753,7 +772,28 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
 #pragma unroll
     for (int sl = 0; sl < NIP; ++sl) {
       const int t = tid + sl * BS;
-      ip_n[sl] = (SORTED && e_n >= 0 && t < NB2) ? a.bposs[(int64_t)e_n * NB2 + t] : 0;
+      ip_n[sl] = (PREPOS && e_n >= 0 && t < NB2) ? a.bposs[(int64_t)e_n * NB2 + t] : 0;
+    }
+    if constexpr (EMAT) {
+      // the element matrix, [p][p'][r][c], to its slot of the buffer
+      double *dst = a.emat64 + (int64_t)e * NB2 * D * D;
+      if constexpr (SORTED) {
+        for (int t = tid; t < NB2 * D * D; t += BS) dst[t] = s_K[t];
+      } else {
+#pragma unroll
+        for (int j = 0; j < NBT; ++j) {
+          if (!pon[j]) continue;
+          const int p = pp_[j], pq = pq_[j];
+#pragma unroll
+          for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int cc = 0; cc < D; ++cc) {
+              dst[(p * NP + pq) * D * D + r * D + cc] = acc[j][r * D + cc];
+              dst[(pq * NP + p) * D * D + cc * D + r] = acc[j][r * D + cc];
+            }
+        }
+      }
+      continue;
     }
     // base values (K_elast for blocks not yet written in this assembly, else
     // K_tangent) plus the element's contribution
@@ -849,7 +889,7 @@ struct MfmaCfg {
 template <bool BF16> struct MfmaElem { using type = float; };
 template <> struct MfmaElem<true> { using type = __bf16; };
 
-template <int ETID, typename VT, bool BF16>
+template <int ETID, typename VT, bool BF16, bool EMAT = false>
 __global__ __launch_bounds__(256) void k_assemble_mfma(KA a) {
   using T = Et<ETID>;
   using C = MfmaCfg<ETID, BF16>;
@@ -891,7 +931,7 @@ __global__ __launch_bounds__(256) void k_assemble_mfma(KA a) {
   int64_t k0 = a.k0, k1 = a.k1;
   if (a.off) {
     k0 = a.off[a.colour];
-    k1 = a.off[a.colour + 1];
+    k1 = a.off[EMAT ? a.colour_end : a.colour + 1];
   }
   VT *Kt = (VT *)a.Kt;
   const uint32_t qmask = (1u << NQ) - 1u;
@@ -899,20 +939,23 @@ __global__ __launch_bounds__(256) void k_assemble_mfma(KA a) {
     const int e = a.list[k];
     if (e < 0) continue;
     const uint32_t mask = a.emask[e] & qmask;
+    if (EMAT && !mask) continue;  // no plastic point: no element term (uniform)
     const int nq = __popc(mask);
     int64_t i1[NBT], i2[NBT];
     bool f1[NBT], f2[NBT];
+    if constexpr (!EMAT) {
 #pragma unroll
-    for (int j = 0; j < NBT; ++j) {
-      const bool on = tid + j * 256 < NPAIR;
-      i1[j] = on ? (int64_t)a.bpos[(int64_t)e * NB2 + pp_[j] * NP + pq_[j]] : 0;
-      i2[j] = on ? (int64_t)a.bpos[(int64_t)e * NB2 + pq_[j] * NP + pp_[j]] : 0;
-    }
+      for (int j = 0; j < NBT; ++j) {
+        const bool on = tid + j * 256 < NPAIR;
+        i1[j] = on ? (int64_t)a.bpos[(int64_t)e * NB2 + pp_[j] * NP + pq_[j]] : 0;
+        i2[j] = on ? (int64_t)a.bpos[(int64_t)e * NB2 + pq_[j] * NP + pp_[j]] : 0;
+      }
 #pragma unroll
-    for (int j = 0; j < NBT; ++j) {
-      const bool on = tid + j * 256 < NPAIR;
-      f1[j] = on ? (a.epoch[i1[j]] != a.cur) : false;
-      f2[j] = on ? (a.epoch[i2[j]] != a.cur) : false;
+      for (int j = 0; j < NBT; ++j) {
+        const bool on = tid + j * 256 < NPAIR;
+        f1[j] = on ? (a.epoch[i1[j]] != a.cur) : false;
+        f2[j] = on ? (a.epoch[i2[j]] != a.cur) : false;
+      }
     }
     double acc[NBT][9];
 #pragma unroll
@@ -1042,6 +1085,18 @@ __global__ __launch_bounds__(256) void k_assemble_mfma(KA a) {
         }
       }
       __syncthreads();
+      if constexpr (EMAT) {
+        // the element matrix, [p][p'][r][c] (FP32 accumulators), to its slot
+        float *dst = a.emat32 + (int64_t)e * NB2 * 9;
+        for (int t = tid; t < NB2 * 9; t += 256) {
+          const int pb = t / 9, rc = t - (t / 9) * 9;
+          const int p = pb / NP, pq = pb - (pb / NP) * NP;
+          const int m = 3 * p + rc / 3, n = 3 * pq + rc % 3;
+          dst[t] = m <= n ? s_K[m * NL + n] : s_K[n * NL + m];
+        }
+        __syncthreads();  // s_K is read before the next element writes it
+        continue;
+      }
 #pragma unroll
       for (int j = 0; j < NBT; ++j) {
         if (tid + j * 256 >= NPAIR) continue;
@@ -1084,6 +1139,105 @@ __global__ __launch_bounds__(256) void k_assemble_mfma(KA a) {
         a.epoch[idx] = (uint8_t)a.cur;
       }
     }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Node-row gather of the element matrices: K_tangent row block of node m =
+// K_elast row + sum over the elements e containing m that have plastic
+// points now (ascending e) of the node's rows of Delta K_e, taken from the
+// element-matrix buffer.  One workgroup per active row (a row is active
+// when an element containing the node has plastic points now or had them at
+// the last assembly: every row the last assembly changed is rewritten, so
+// inactive rows hold K_elast).  The row is accumulated in LDS, then written
+// once, coalesced: no colours, no stamps, no float atomics; the sum order
+// is fixed.  em_cur == nullptr: every row and element (K_elast from the
+// element matrices of C, base nullptr = 0).
+// ----------------------------------------------------------------------------
+struct KR {
+  int64_t n_n;
+  const int32_t *bptr, *n2e_ptr, *n2e, *bpos;
+  const uint32_t *em_cur, *em_prev;
+  const void *emat;   // OT [n_e][n_p][n_p][dim][dim]
+  const void *base;   // VT [nnzb][dim][dim] or nullptr
+  void *out;          // VT [nnzb][dim][dim]
+  int max_slots;      // largest node-to-element count (LDS after the row)
+};
+
+template <int ETID>
+struct RowCfg {
+  using T = Et<ETID>;
+  static constexpr int NV = T::NP * T::D * T::D;  // values of a node's rows
+  static constexpr int BS = NV <= 96 ? 64 : (NV <= 192 ? 128 : 256);
+  // node slots gathered per step (their loads issued together)
+  static constexpr int CH = ETID == ET_P1_3D ? 16 : (T::D == 2 && ETID != ET_P1_2D ? 4 : 8);
+  static constexpr int IPT = (CH * NV + BS - 1) / BS;
+};
+
+template <int ETID, typename OT, typename VT>
+__global__ __launch_bounds__(RowCfg<ETID>::BS) void k_row_gather(KR a) {
+  using T = Et<ETID>;
+  using R = RowCfg<ETID>;
+  constexpr int D = T::D, NP = T::NP, DD = D * D, NV = R::NV, BS = R::BS, CH = R::CH;
+  constexpr int IPT = R::IPT;
+  extern __shared__ double s_dyn[];
+  const int tid = threadIdx.x;
+  const bool all = a.em_cur == nullptr;
+  const OT *emat = (const OT *)a.emat;
+  const VT *base = (const VT *)a.base;
+  VT *out = (VT *)a.out;
+  for (int64_t m = blockIdx.x; m < a.n_n; m += gridDim.x) {
+    const int k0 = a.n2e_ptr[m], k1 = a.n2e_ptr[m + 1];
+    const int64_t r0 = a.bptr[m];
+    const int L = (int)(a.bptr[m + 1] - r0) * DD;
+    double *s_acc = s_dyn;
+    int *s_sv = (int *)(s_dyn + L);  // slot value e * n_p + p, or -1 (no term now)
+    // slots of the row: element terms present now, and whether the row is
+    // touched by an element listed now or at the last assembly
+    bool act = all;
+    for (int k = k0 + tid; k < k1; k += BS) {
+      const int sv = a.n2e[k];
+      const int e = sv / NP;
+      const uint32_t now = all ? 1u : a.em_cur[e];
+      const uint32_t before = (all || !a.em_prev) ? 0u : a.em_prev[e];
+      s_sv[k - k0] = now ? sv : -1;
+      act = act || ((now | before) != 0u);
+    }
+    act = __syncthreads_or(act) != 0;
+    if (!act) continue;  // uniform
+    for (int v = tid; v < L; v += BS) s_acc[v] = base ? (double)base[r0 * DD + v] : 0.0;
+    __syncthreads();
+    for (int kc = 0; kc < k1 - k0; kc += CH) {
+      const int ns = (k1 - k0 - kc) < CH ? (k1 - k0 - kc) : CH;
+      double val[IPT];
+      int dst[IPT], sl[IPT];
+#pragma unroll
+      for (int i = 0; i < IPT; ++i) {
+        const int it = tid + i * BS;  // item: slot it / NV, value it % NV
+        const int sj = it / NV, t = it - (it / NV) * NV;
+        sl[i] = -1;
+        dst[i] = 0;
+        val[i] = 0.0;
+        if (sj < ns) {
+          const int sv = s_sv[kc + sj];
+          if (sv >= 0) {
+            const int pp = t / DD, ij = t - (t / DD) * DD;
+            dst[i] = (a.bpos[(int64_t)sv * NP + pp] - (int32_t)r0) * DD + ij;
+            val[i] = (double)emat[(int64_t)sv * NV + t];
+            sl[i] = sj;
+          }
+        }
+      }
+      // slots in order: the terms of one slot go to distinct values
+      for (int sj = 0; sj < ns; ++sj) {
+#pragma unroll
+        for (int i = 0; i < IPT; ++i)
+          if (sl[i] == sj) s_acc[dst[i]] += val[i];
+        __syncthreads();
+      }
+    }
+    for (int v = tid; v < L; v += BS) out[r0 * DD + v] = (VT)s_acc[v];
+    __syncthreads();  // the LDS row is free for the next row
   }
 }
 
@@ -2123,7 +2277,15 @@ static hipError_t elastic_et(Ctx &c) {
   }
   return hipSuccess;
 }
-hipError_t launch_elastic_assembly(Ctx &c) { DISPATCH_ET(elastic_et, c) }
+hipError_t launch_emat(Ctx &c, bool elastic, int64_t listed);
+hipError_t launch_row_gather(Ctx &c, bool elastic);
+hipError_t launch_elastic_assembly(Ctx &c) {
+  if (c.opt.assembly == EP_ASSEMBLY_ROWS) {
+    RT(launch_emat(c, true, -1));
+    return launch_row_gather(c, true);
+  }
+  DISPATCH_ET(elastic_et, c)
+}
 
 template <int ETID>
 static hipError_t colour_et(Ctx &c, int colour, int epoch, int64_t listed) {
@@ -2180,6 +2342,101 @@ static hipError_t colour_et(Ctx &c, int colour, int epoch, int64_t listed) {
 hipError_t launch_colour_assembly(Ctx &c, int colour, int epoch, int64_t listed) {
   DISPATCH_ET(colour_et, c, colour, epoch, listed)
 }
+
+// Element matrices of every element of the work list with plastic points
+// now (elastic: of every element, C at every point) into the element-matrix
+// buffer: one launch, no colours (each element writes its own slot).
+template <int ETID>
+static hipError_t emat_et(Ctx &c, bool elastic, int64_t listed) {
+  using Cfg = AsmCfg<ETID>;
+  KA a{};
+  a.coord = c.coord;
+  a.elem = c.elem;
+  a.ref = c.ref;
+  a.n_n = c.n_n;
+  a.n_int = c.n_int;
+  a.desc = c.desc;
+  a.G = c.mat.G;
+  a.K = c.mat.K;
+  a.elastic = elastic ? 1 : 0;
+  a.emat64 = (double *)c.emat;
+  a.emat32 = (float *)c.emat;
+  int64_t cnt;
+  if (elastic) {
+    a.list = c.ecol_perm;
+    a.off = nullptr;
+    a.k0 = 0;
+    a.k1 = c.n_perm;
+    cnt = c.n_perm;
+  } else {
+    a.emask = c.em[c.em_cur];
+    a.list = c.plist;
+    a.off = c.coff;
+    a.colour = 0;
+    a.colour_end = c.n_col;
+    cnt = listed >= 0 ? listed : c.n_e;
+  }
+  if (cnt == 0) return hipSuccess;
+  const int gcap = 48 * c.n_cu;
+  if constexpr (ETID == ET_Q2_3D || ETID == ET_Q2S_3D || ETID == ET_P2_3D) {
+    if (!elastic && (c.opt.local_prec == EP_BF16 || c.opt.local_prec == EP_FP32)) {
+      const int grid = (int)(cnt < 65536 ? cnt : 65536);
+      if (c.opt.local_prec == EP_BF16)
+        EP_LAUNCH((k_assemble_mfma<ETID, double, true, true>), dim3(grid), dim3(256), 0, c, a);
+      else
+        EP_LAUNCH((k_assemble_mfma<ETID, double, false, true>), dim3(grid), dim3(256), 0, c, a);
+      return hipGetLastError();
+    }
+  }
+  const int grid = (int)(cnt < gcap ? cnt : gcap);
+  EP_LAUNCH((k_assemble<ETID, double, true>), dim3(grid), dim3(Cfg::BS), 0, c, a);
+  return hipGetLastError();
+}
+hipError_t launch_emat(Ctx &c, bool elastic, int64_t listed) {
+  DISPATCH_ET(emat_et, c, elastic, listed)
+}
+
+// Node-row gather of the element matrices into K_tangent (elastic: into
+// K_elast from zero).
+template <int ETID>
+static hipError_t row_gather_et(Ctx &c, bool elastic) {
+  using R = RowCfg<ETID>;
+  KR a{};
+  a.n_n = c.n_n;
+  a.bptr = c.bptr;
+  a.n2e_ptr = c.n2e_ptr;
+  a.n2e = c.n2e;
+  a.bpos = c.bpos;
+  a.emat = c.emat;
+  a.max_slots = c.max_slots;
+  if (elastic) {
+    a.em_cur = nullptr;
+    a.em_prev = nullptr;
+    a.base = nullptr;
+    a.out = c.Ke;
+  } else {
+    a.em_cur = c.em[c.em_cur];
+    a.em_prev = c.em_asm >= 0 ? c.em[c.em_asm] : nullptr;
+    a.base = c.opt.tangent_prec == EP_FP32 ? (const void *)c.Ke32 : (const void *)c.Ke;
+    a.out = c.Kt;
+  }
+  if (c.n_n == 0) return hipSuccess;
+  const int D = c.dim;
+  const size_t lds = sizeof(double) * (size_t)c.max_deg * D * D + sizeof(int) * c.max_slots;
+  const int grid = (int)(c.n_n < (1 << 20) ? c.n_n : (1 << 20));
+  const bool e32 = !elastic && c.opt.local_prec != EP_FP64;  // matrix-core element matrices
+  const bool v32 = !elastic && c.opt.tangent_prec == EP_FP32;
+#define RG(OT, VT) \
+  EP_LAUNCH((k_row_gather<ETID, OT, VT>), dim3(grid), dim3(R::BS), lds, c, a)
+  if (e32) {
+    if (v32) RG(float, float); else RG(float, double);
+  } else {
+    if (v32) RG(double, float); else RG(double, double);
+  }
+#undef RG
+  return hipGetLastError();
+}
+hipError_t launch_row_gather(Ctx &c, bool elastic) { DISPATCH_ET(row_gather_et, c, elastic) }
 
 hipError_t launch_copy_ke_to_kt(Ctx &c) {
   const int64_t n = c.nnzb * c.dim * c.dim;

@@ -62,10 +62,11 @@ def _check_rows(a, b, rp):
     assert (np.abs(a - b) / rmax[rows]).max() <= RTOL
 
 
+@pytest.mark.parametrize("mode", ["colours", "rows"])
 @pytest.mark.parametrize("matname", list(MATERIALS))
 @pytest.mark.parametrize("name", list(TINY))
 @pytest.mark.parametrize("amp", [0.3, 0.6, 300.0])
-def test_smallest_mesh(name, matname, amp):
+def test_smallest_mesh(name, matname, amp, mode):
     """One element (or one cell of simplices): mixed plastic sets at amp 0.3
     and 0.6 (none to most points, depending on the element); at amp 300 (times the yield strain) every von Mises point is plastic
     (Drucker-Prager points under strong compression may stay elastic)."""
@@ -75,7 +76,8 @@ def test_smallest_mesh(name, matname, amp):
     ref, rp, K, F = _oracle(mesh, mat, u)
     if amp > 1.0 and mat.model == "VM":
         assert ref["flag"].all()  # the input really makes every point plastic
-    ctx = _ep.Context(mesh, free, mat)
+    ctx = _ep.Context(mesh, free, mat, options={
+        "assembly": _ep.EP_ASSEMBLY_ROWS if mode == "rows" else _ep.EP_ASSEMBLY_COLOURS})
     try:
         sig, _, flag = ctx.constitutive(ctx.tensor(u), D=False)
         assert np.array_equal(_np(flag), ref["flag"])

@@ -110,3 +110,11 @@ def test_fp32_tangent_storage_rows_full(name):
     wl = {"q2_slope": W.workload_q2_slope, "q1_cube": W.workload_q1_cube}[name]()
     worst = _rows_check(wl, {"tangent_prec": _ep.EP_FP32}, TOL["store32"])
     assert worst > 0.0
+
+
+@pytest.mark.parametrize("name", ["q1_cube", "p2_block"])
+def test_row_gather_assembly_rows_full(name):
+    """The node-row gather assembly (FP64) at full size: sampled rows of
+    K_tangent at the FP64 bound of the colour-round assembly."""
+    wl = {"q1_cube": W.workload_q1_cube, "p2_block": W.workload_p2_block}[name]()
+    _rows_check(wl, {"assembly": _ep.EP_ASSEMBLY_ROWS}, 1e-12)

@@ -26,12 +26,15 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
+@pytest.mark.parametrize("mode", ["colours", "rows"])
 @pytest.mark.parametrize("case", ["q2_3d_dph", "q2s_3d_dph", "p2_3d_dph"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16_f32values"])
-def test_incremental_tangent_matrix_cores(case, prec):
-    """bf16_f32values: BF16 local products with K stored in FP32."""
+def test_incremental_tangent_matrix_cores(case, prec, mode):
+    """bf16_f32values: BF16 local products with K stored in FP32.  rows:
+    the element matrices (FP32) go through the buffer of the row gather."""
     mesh, free, mat, u, (ep, beta, kappa) = make_case(case)
-    opts = {"local_prec": _ep.EP_FP32 if prec == "fp32" else _ep.EP_BF16}
+    opts = {"local_prec": _ep.EP_FP32 if prec == "fp32" else _ep.EP_BF16,
+            "assembly": _ep.EP_ASSEMBLY_ROWS if mode == "rows" else _ep.EP_ASSEMBLY_COLOURS}
     if prec == "bf16_f32values":
         opts["tangent_prec"] = _ep.EP_FP32
     prec = prec.split("_")[0]

@@ -255,10 +255,12 @@ def test_split_operator_load_paths(name):
         ctx_a.close()
 
 
-def test_lshape_vm_cyclic_path_small():
+@pytest.mark.parametrize("mode", ["colours", "rows"])
+def test_lshape_vm_cyclic_path_small(mode):
     """The paper's von Mises example (Section 8.2) on the coarsest L-shape
     mesh of 20-node serendipity hexahedra: the whole cyclic load path
-    (loading, unloading, reverse loading) on the GPU equals the oracle's."""
+    (loading, unloading, reverse loading) on the GPU equals the oracle's,
+    with either assembly."""
     # t_k = 4k/7: loading, unloading and reverse loading without the
     # zero-load instants t = 2 and t = 4 (the oracle's relative residual
     # needs a nonzero load); the seventh step (t = 4) is left out
@@ -266,7 +268,8 @@ def test_lshape_vm_cyclic_path_small():
     steps = range(6)
     # the FP64 residual floor of this problem is ~2e-13
     uo, so = oracle_path(wl, steps, tol=1e-12)
-    ctx, ug, recs, st = gpu_path(wl, steps)
+    ctx, ug, recs, st = gpu_path(wl, steps, {
+        "assembly": _ep.EP_ASSEMBLY_ROWS if mode == "rows" else _ep.EP_ASSEMBLY_COLOURS})
     try:
         assert max(s[3] for s in so) > 0
         for k in steps:
@@ -278,11 +281,13 @@ def test_lshape_vm_cyclic_path_small():
         ctx.close()
 
 
-def test_assemble_elastic_resets_tangent():
+@pytest.mark.parametrize("mode", ["colours", "rows"])
+def test_assemble_elastic_resets_tangent(mode):
     """ep_assemble_elastic recomputes K_elast bit for bit and leaves
     K_tangent = K_elast; the next tangent assembly equals the one before."""
     wl = W.workload_lshape_vm(level=0, steps=8)
-    ctx = _ep.Context(wl.mesh, wl.free, wl.material)
+    ctx = _ep.Context(wl.mesh, wl.free, wl.material, options={
+        "assembly": _ep.EP_ASSEMBLY_ROWS if mode == "rows" else _ep.EP_ASSEMBLY_COLOURS})
     try:
         _, _, Ke0 = ctx.csr(0)
         Ke0 = _np(Ke0)

@@ -48,12 +48,23 @@ class Case:
     def du(self):
         return self.ctx.tensor(self.u)
 
+    def rows_ctx(self):
+        """A second context of the case assembling by node rows."""
+        if getattr(self, "ctx_rows", None) is None:
+            self.ctx_rows = _ep.Context(self.mesh, self.free, self.mat,
+                                        options={"assembly": _ep.EP_ASSEMBLY_ROWS})
+            self.ctx_rows.set_state(self.ep, self.beta if self.mat.model == "VM" else None,
+                                    self.kappa if self.mat.model == "DP" else None)
+        return self.ctx_rows
+
 
 @pytest.fixture(scope="module", params=list(CASES))
 def case(request):
     c = Case(request.param)
     yield c
     c.ctx.close()
+    if getattr(c, "ctx_rows", None) is not None:
+        c.ctx_rows.close()
 
 
 def _voigt_from_soa(arr, dim):
@@ -109,26 +120,32 @@ def _row_scaled_close(a_val, b_val, row_ptr, scale_val, tol=RTOL):
     assert err.max() <= tol, f"row-relative error {err.max():.3e}"
 
 
-def test_elastic_stiffness(case):
-    rp, ci, val = case.ctx.csr(0)
+@pytest.mark.parametrize("mode", ["colours", "rows"])
+def test_elastic_stiffness(case, mode):
+    ctx = case.ctx if mode == "colours" else case.rows_ctx()
+    rp, ci, val = ctx.csr(0)
     n = case.mesh.n_int
     D0 = O.constitutive(case.mat, np.zeros((n, 6)), np.zeros((n, 6)))["D"]
     _, _, ref = O.assemble(case.mesh, case.dphi, case.w, D0, *case.pattern)
     _row_scaled_close(_np(val), ref, case.pattern[0], ref)
 
 
-def test_incremental_tangent_over_iterations(case):
+@pytest.mark.parametrize("mode", ["colours", "rows"])
+def test_incremental_tangent_over_iterations(case, mode):
     """K_elast + B^T (D_t - D_e) B through several constitutive/assembly
-    rounds with changing plastic sets (exercises restore and epochs) equals
-    the oracle's plain sum w B^T D_t B each time.  The split cancels up to
-    |K_elast|, so rows are scaled by max(|K_t|, |K_elast|) of the row."""
-    _, _, Ke = case.ctx.csr(0)
+    rounds with changing plastic sets (exercises the restore of blocks whose
+    elements left the plastic set: stamps in colour rounds, rewritten rows in
+    the row gather) equals the oracle's plain sum w B^T D_t B each time.  The
+    split cancels up to |K_elast|, so rows are scaled by max(|K_t|,
+    |K_elast|) of the row."""
+    ctx = case.ctx if mode == "colours" else case.rows_ctx()
+    _, _, Ke = ctx.csr(0)
     Ke = _np(Ke)
     for k, s in enumerate([1.0, 0.3, 1.6, 0.0, 1.0]):
         u = case.u * s
-        case.ctx.constitutive(case.ctx.tensor(u), sig=False, D=False, flag=False)
-        case.ctx.assemble_tangent()
-        _, _, val = case.ctx.csr(1)
+        ctx.constitutive(ctx.tensor(u), sig=False, D=False, flag=False)
+        ctx.assemble_tangent()
+        _, _, val = ctx.csr(1)
         ref = case.oracle_const(u)
         _, _, Kt = O.assemble(case.mesh, case.dphi, case.w, ref["D"], *case.pattern)
         _row_scaled_close(_np(val), Kt, case.pattern[0], np.maximum(np.abs(Kt), np.abs(Ke)))
@@ -181,13 +198,15 @@ def test_spmv_matches_csr_product(case):
     close(y, ref)
 
 
-def test_determinism(case):
+@pytest.mark.parametrize("mode", ["colours", "rows"])
+def test_determinism(case, mode):
+    ctx = case.ctx if mode == "colours" else case.rows_ctx()
     outs = []
     for _ in range(2):
-        case.ctx.constitutive(case.du(), sig=False, D=False, flag=False)
-        case.ctx.assemble_tangent()
-        _, _, val = case.ctx.csr(1)
-        F = case.ctx.internal_force()
+        ctx.constitutive(case.du(), sig=False, D=False, flag=False)
+        ctx.assemble_tangent()
+        _, _, val = ctx.csr(1)
+        F = ctx.internal_force()
         outs.append((_np(val), _np(F)))
     assert np.array_equal(outs[0][0], outs[1][0])
     assert np.array_equal(outs[0][1], outs[1][1])
@@ -280,14 +299,17 @@ def test_split_apply_fp32_storage():
         ctx.close()
 
 
-def test_stamp_wraparound():
-    """The one-byte assembly stamps are cleared every 255 assemblies: over
-    600 assemblies with changing plastic sets, K_tangent equals a fresh
-    context's first assembly at the same displacement (equal values: the
-    formerly plastic elements add exact zeros)."""
+@pytest.mark.parametrize("mode", ["colours", "rows"])
+def test_stamp_wraparound(mode):
+    """Over 600 assemblies with changing plastic sets, K_tangent equals a
+    fresh context's first assembly at the same displacement (equal values:
+    the formerly plastic elements add exact zeros, or their rows are
+    rewritten from K_elast); in colour rounds this spans the clearing of the
+    one-byte assembly stamps every 255 assemblies."""
     mesh, free, mat, u0, (ep, beta, kappa) = make_case("q2_2d_dp")
     state = (ep, None, kappa)
-    ctx = _ep.Context(mesh, free, mat)
+    opts = {"assembly": _ep.EP_ASSEMBLY_ROWS if mode == "rows" else _ep.EP_ASSEMBLY_COLOURS}
+    ctx = _ep.Context(mesh, free, mat, options=opts)
     try:
         ctx.set_state(*state)
         scales = [1.0, 0.3, 1.6, 0.0]
@@ -298,7 +320,7 @@ def test_stamp_wraparound():
             ctx.assemble_tangent()
             if k not in checks:
                 continue
-            fresh = _ep.Context(mesh, free, mat)
+            fresh = _ep.Context(mesh, free, mat, options=opts)
             try:
                 fresh.set_state(*state)
                 fresh.constitutive(fresh.tensor(u0 * s), sig=False, D=False, flag=False)
