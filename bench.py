@@ -579,7 +579,8 @@ def copy_calibration():
     return gbs
 
 
-def measure_pass(name, frac, tangent, local_prec, steps, warmup, copy_gbs=None, keep=False):
+def measure_pass(name, frac, tangent, local_prec, steps, warmup, copy_gbs=None, keep=False,
+                 assembly="colours"):
     """Timed passes of the hot path on workload `name` with `frac` of the
     elements seeded plastic: per-kernel breakdown (every kernel timed), then
     the timed region with HIP events on the dominant kernel only.  Returns
@@ -597,7 +598,9 @@ def measure_pass(name, frac, tangent, local_prec, steps, warmup, copy_gbs=None, 
     lp = {"fp64": _ep.EP_FP64, "fp32": _ep.EP_FP32, "bf16": _ep.EP_BF16}[local_prec]
     ctx = _ep.Context(mesh, wl.free, mat,
                       options={"tangent_prec": _ep.EP_FP64 if tb == 8 else _ep.EP_FP32,
-                               "local_prec": lp})
+                               "local_prec": lp,
+                               "assembly": _ep.EP_ASSEMBLY_ROWS if assembly == "rows"
+                               else _ep.EP_ASSEMBLY_COLOURS})
     ctx.set_state(ep, beta if mat.model == "VM" else None, kappa if mat.model == "DP" else None)
     u = ctx.tensor(u_np)
     F = torch.empty(mesh.n_dof, dtype=torch.float64, device="cuda")
@@ -655,13 +658,13 @@ def measure_pass(name, frac, tangent, local_prec, steps, warmup, copy_gbs=None, 
                 "launches_per_step": n_launch, "copy_GB_s": copy_gbs}
     if dom == "assembly":
         scalar = assembly_bytes_scalar_model(mesh, counts, tb) / n_launch
-        design = kb["assembly"] / n_launch
+        design = kb["assembly"] / n_launch if assembly == "colours" else None
         roofline.update({
             "bytes_model": "scalar-CSR model: per plastic point 8 (d n_p + 1) + 64 B, per "
                            "plastic element (d n_p)^2 (4 + 2 s) x 2 (restore + add)",
             "algorithmic_bytes_per_launch": int(scalar),
             "achieved": round(scalar / t_launch_s / 1e9, 1),
-            "design_model": {
+            "design_model": None if design is None else {
                 "what": "node-block CSR of this build: per listed element n_p^2 block "
                         "position map entries, one-byte stamps, base value read and value "
                         "write; per plastic element its nodes; per plastic point its tangent "
@@ -734,6 +737,8 @@ def main():
     ap.add_argument("--no-calibration-copy", action="store_true")
     ap.add_argument("--local-prec", choices=["fp64", "fp32", "bf16"], default="fp64",
                     help="element-local products (27-node hexahedra, P2 tetrahedra only)")
+    ap.add_argument("--assembly", choices=["colours", "rows"], default="colours",
+                    help="colour rounds with stamps, or element matrices + node-row gather")
     ap.add_argument("--no-slope", action="store_true",
                     help="skip the slope passes (FP64 and FP32 tangent values)")
     ap.add_argument("--no-newton", action="store_true",
@@ -760,7 +765,8 @@ def main():
     torch.cuda.set_device(0)
     copy_gbs = None if args.no_calibration_copy else copy_calibration()
     head, inputs = measure_pass(args.workload, args.plastic_fraction, args.tangent,
-                                args.local_prec, args.steps, args.warmup, copy_gbs, keep=True)
+                                args.local_prec, args.steps, args.warmup, copy_gbs, keep=True,
+                                assembly=args.assembly)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(*inputs)
@@ -794,7 +800,7 @@ def main():
                    "plastic_fraction_seeded": args.plastic_fraction,
                    "plastic_elements": head["plastic_elements"],
                    "plastic_points": head["plastic_points"], "tangent": args.tangent,
-                   "local_products": args.local_prec,
+                   "local_products": args.local_prec, "assembly": args.assembly,
                    "step": "constitutive + compaction + incremental K assembly + internal "
                            "force"},
         "roofline": head["roofline"],

@@ -457,15 +457,17 @@ double relative_residual(const double *norms_h) {
 }
 
 // n PCG iterations.  Even chunks without profiling replay a HIP graph of
-// the chunk (captured once per solution vector and chunk length; the
-// iterations alternate two search-direction buffers, so an even chunk ends
-// where it started); otherwise the kernels are launched one by one.
+// the chunk (captured once per solution vector, chunk length and plastic
+// mask buffer, which the split form's kernels read; the iterations
+// alternate two search-direction buffers, so an even chunk ends where it
+// started); otherwise the kernels are launched one by one.
 ep_status pcg_chunk(Ctx *c, double *x, int n) {
   if (c->prof_mask || n < 2 || n % 2 != 0) {
     for (int k = 0; k < n; ++k) HIPC(launch_pcg_iteration(*c, x));
     return EP_OK;
   }
-  if (!c->pcg_graph || c->pcg_graph_x != x || c->pcg_graph_n != n) {
+  if (!c->pcg_graph || c->pcg_graph_x != x || c->pcg_graph_n != n ||
+      c->pcg_graph_em != c->em_cur) {
     if (c->pcg_graph) {
       HIPC(hipGraphExecDestroy(c->pcg_graph));
       c->pcg_graph = nullptr;
@@ -490,6 +492,7 @@ ep_status pcg_chunk(Ctx *c, double *x, int n) {
     }
     c->pcg_graph_x = x;
     c->pcg_graph_n = n;
+    c->pcg_graph_em = c->em_cur;
   }
   HIPC(hipGraphLaunch(c->pcg_graph, c->stream));
   return EP_OK;

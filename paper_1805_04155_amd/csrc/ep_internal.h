@@ -255,6 +255,7 @@ struct Ctx {
   hipGraphExec_t pcg_graph = nullptr;
   const double *pcg_graph_x = nullptr;
   int pcg_graph_n = 0;
+  int pcg_graph_em = -1;
 
   // learned warm start (allocated at first use)
   float *mlp_x = nullptr, *mlp_y = nullptr;  // [n_int][16], [n_int][8]
