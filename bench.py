@@ -352,7 +352,7 @@ def time_pass(ctx, u, F, steps):
     return 1e3 * (time.perf_counter() - t0) / steps
 
 
-def lshape_report(level, steps):
+def lshape_report(level, steps, assembly="colours"):
     """The paper's von Mises example (Section 8.2) on the L-shaped domain of
     20-node serendipity hexahedra: tangent-assembly time of every Newton
     iteration against its number of plastic points, a least-squares line
@@ -364,7 +364,9 @@ def lshape_report(level, steps):
     from paper_1805_04155_amd import workloads as W
     wl = W.workload_lshape_vm(level, steps)
     mesh = wl.mesh
-    ctx = _ep.Context(mesh, wl.free, wl.material, options={"newton_rtol": 1e-10})
+    ctx = _ep.Context(mesh, wl.free, wl.material, options={
+        "newton_rtol": 1e-10,
+        "assembly": _ep.EP_ASSEMBLY_ROWS if assembly == "rows" else _ep.EP_ASSEMBLY_COLOURS})
     u = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
     _ep.ep_profile(ctx.h, 1)
     for _ in range(5):
@@ -396,19 +398,24 @@ def lshape_report(level, steps):
     pred = a0 + a1 * n
     r2 = 1.0 - ((ms - pred) ** 2).sum() / max(((ms - ms.mean()) ** 2).sum(), 1e-30)
     full = a0 + a1 * mesh.n_int
+    small = [b for a, b in pts if 0 < a <= 30]
     out = {"workload": f"L-shaped domain, level {level}: {mesh.n_elems} 20-node serendipity "
                        f"hexahedra, {mesh.n_nodes} nodes, {mesh.n_int} points; von Mises "
                        f"kinematic, cyclic top traction 200 zeta(t), {steps} steps",
+           "assembly": assembly,
            "newton_iterations": its, "path_seconds_profiled": round(t, 3),
            "elastic_assembly_ms": round(el_ms, 4),
            "tangent_assembly_ms_vs_plastic_points": [[int(a), round(b, 4)] for a, b in pts],
            "fit_ms": {"intercept": round(float(a0), 5), "per_1000_points": round(float(a1) * 1e3, 6),
                       "r2": round(float(r2), 4)},
            "extrapolated_all_plastic_ms": round(float(full), 4),
+           "median_ms_at_1_to_30_plastic_points": round(float(np.median(small)), 4)
+           if small else None,
+           "assemblies_without_plastic_points_skipped": int(sum(1 for a, _ in pts if a == 0)),
            "ratio_all_plastic_to_elastic": round(float(full / el_ms), 3) if el_ms > 0 else None,
            "hysteresis_zeta_work": hyst}
-    log(f"lshape: {len(pts)} assemblies, fit {out['fit_ms']}, elastic {el_ms:.4f} ms, "
-        f"extrapolated {full:.4f} ms")
+    log(f"lshape {assembly}: {len(pts)} assemblies, fit {out['fit_ms']}, elastic "
+        f"{el_ms:.4f} ms, extrapolated {full:.4f} ms")
     return out
 
 
@@ -780,7 +787,8 @@ def main():
     if not args.no_sweep:
         sweep = plastic_sweep(max(5, args.steps // 2))
     if not args.no_lshape:
-        lshape = lshape_report(args.lshape_level, args.lshape_steps)
+        lshape = {m: lshape_report(args.lshape_level, args.lshape_steps, m)
+                  for m in ("colours", "rows")}
     if not args.no_footing:
         footing = footing_report(args.footing_n, 0.1, 0.016, 40)
     if not args.no_newton:

@@ -393,7 +393,7 @@ ep_status do_assemble(Ctx *c) {
       ProfScope ps(*c, PROF_ASSEMBLE);
       if (ps.tok >= 0) c->pending[ps.tok].count = 2;
       HIPC(launch_emat(*c, false, listed));
-      HIPC(launch_row_gather(*c, false));
+      HIPC(launch_row_gather(*c, false, listed));
     }
     c->em_asm = c->em_cur;
     c->coff_known = false;

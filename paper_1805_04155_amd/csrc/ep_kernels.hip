@@ -899,16 +899,26 @@ __global__ __launch_bounds__(256) void k_assemble_mfma(KA a) {
   constexpr int KK = C::KK, KP = C::KP, LDK = C::LDK, NPAIR = C::NPAIR, NBT = C::NBT;
   constexpr int TPW = C::TPW;
   static_assert(T::D == 3, "3D elements");
-  __shared__ ET s_B[MP * LDK];
-  __shared__ ET s_H[MP * LDK];
-  __shared__ float s_K[NL * NL];
+  // B and H tiles, and after the last chunk the element matrix: for the
+  // large element matrices (20- and 27-node hexahedra) one shared LDS buffer
+  // (a smaller footprint lets more workgroups share a CU; 27-node FP32
+  // products 602 -> 463 us per pass on the block), separate buffers for the
+  // small ones (whose padding would have to be cleared per element for
+  // little LDS saved)
+  constexpr bool ALIAS = NL >= 60;
+  constexpr int NBH = (2 * MP * LDK * (int)sizeof(ET) + 3) / 4;
+  __shared__ float s_BHK[ALIAS ? (NBH > NL * NL ? NBH : NL * NL) : NBH + NL * NL];
+  ET *const s_B = (ET *)s_BHK;
+  ET *const s_H = s_B + MP * LDK;
+  float *const s_K = ALIAS ? s_BHK : s_BHK + NBH;
   __shared__ double s_x[NP * 3];
   __shared__ double s_M[NQ * 36];
   __shared__ double s_Ji[NQ * 9];
   __shared__ int s_q[NQ];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r16 = lane & 15, kg = lane >> 4;
-  // padding rows / columns stay zero for the whole kernel
+  // padding rows / columns of B and H are zero (with ALIAS, the part an
+  // element matrix overwrites is cleared again per element)
   for (int t = tid; t < MP * LDK; t += 256) {
     const int m = t / LDK, kk = t - (t / LDK) * LDK;
     if (m >= NL || kk >= KC) {
@@ -964,6 +974,16 @@ __global__ __launch_bounds__(256) void k_assemble_mfma(KA a) {
       for (int i = 0; i < 9; ++i) acc[j][i] = 0.0;
     if (mask) {
       __syncthreads();  // LDS of the previous element is no longer read
+      if constexpr (ALIAS) {
+        // padding rows / columns of B and H are zero again where the
+        // previous element matrix overwrote them (its first NL^2 floats)
+        constexpr int OV = (4 * NL * NL + (int)sizeof(ET) - 1) / (int)sizeof(ET);
+        for (int t = tid; t < (OV < 2 * MP * LDK ? OV : 2 * MP * LDK); t += 256) {
+          const int tt = t < MP * LDK ? t : t - MP * LDK;
+          const int m = tt / LDK, kk = tt - (tt / LDK) * LDK;
+          if (m >= NL || kk >= KC) s_B[t] = (ET)0.0f;
+        }
+      }
       if (tid < NP * 3) {
         const int64_t node = a.elem[(int64_t)e * NP + tid / 3];
         s_x[tid] = a.coord[(tid % 3) * a.n_n + node];
@@ -1067,6 +1087,7 @@ __global__ __launch_bounds__(256) void k_assemble_mfma(KA a) {
           }
         }
       }
+      __syncthreads();  // every wave has read its last B and H tiles
       // tiles -> element matrix in LDS
 #pragma unroll
       for (int s = 0; s < TPW; ++s) {
@@ -1162,6 +1183,11 @@ struct KR {
   const void *base;   // VT [nnzb][dim][dim] or nullptr
   void *out;          // VT [nnzb][dim][dim]
   int max_slots;      // largest node-to-element count (LDS after the row)
+  // short work lists: the rows of the listed elements' nodes instead of a
+  // scan of every row (list[n_list], elem[n_e][n_p]); a row shared by two
+  // listed elements is computed twice, with the same values
+  const int32_t *list, *elem;
+  int64_t n_list;
 };
 
 template <int ETID>
@@ -1186,7 +1212,9 @@ __global__ __launch_bounds__(RowCfg<ETID>::BS) void k_row_gather(KR a) {
   const OT *emat = (const OT *)a.emat;
   const VT *base = (const VT *)a.base;
   VT *out = (VT *)a.out;
-  for (int64_t m = blockIdx.x; m < a.n_n; m += gridDim.x) {
+  const int64_t n_work = a.list ? a.n_list * NP : a.n_n;
+  for (int64_t b = blockIdx.x; b < n_work; b += gridDim.x) {
+    const int64_t m = a.list ? (int64_t)a.elem[(int64_t)a.list[b / NP] * NP + b % NP] : b;
     const int k0 = a.n2e_ptr[m], k1 = a.n2e_ptr[m + 1];
     const int64_t r0 = a.bptr[m];
     const int L = (int)(a.bptr[m + 1] - r0) * DD;
@@ -1194,7 +1222,7 @@ __global__ __launch_bounds__(RowCfg<ETID>::BS) void k_row_gather(KR a) {
     int *s_sv = (int *)(s_dyn + L);  // slot value e * n_p + p, or -1 (no term now)
     // slots of the row: element terms present now, and whether the row is
     // touched by an element listed now or at the last assembly
-    bool act = all;
+    bool act = all || a.list != nullptr;
     for (int k = k0 + tid; k < k1; k += BS) {
       const int sv = a.n2e[k];
       const int e = sv / NP;
@@ -2278,11 +2306,10 @@ static hipError_t elastic_et(Ctx &c) {
   return hipSuccess;
 }
 hipError_t launch_emat(Ctx &c, bool elastic, int64_t listed);
-hipError_t launch_row_gather(Ctx &c, bool elastic);
 hipError_t launch_elastic_assembly(Ctx &c) {
   if (c.opt.assembly == EP_ASSEMBLY_ROWS) {
     RT(launch_emat(c, true, -1));
-    return launch_row_gather(c, true);
+    return launch_row_gather(c, true, -1);
   }
   DISPATCH_ET(elastic_et, c)
 }
@@ -2399,7 +2426,7 @@ hipError_t launch_emat(Ctx &c, bool elastic, int64_t listed) {
 // Node-row gather of the element matrices into K_tangent (elastic: into
 // K_elast from zero).
 template <int ETID>
-static hipError_t row_gather_et(Ctx &c, bool elastic) {
+static hipError_t row_gather_et(Ctx &c, bool elastic, int64_t listed) {
   using R = RowCfg<ETID>;
   KR a{};
   a.n_n = c.n_n;
@@ -2423,7 +2450,16 @@ static hipError_t row_gather_et(Ctx &c, bool elastic) {
   if (c.n_n == 0) return hipSuccess;
   const int D = c.dim;
   const size_t lds = sizeof(double) * (size_t)c.max_deg * D * D + sizeof(int) * c.max_slots;
-  const int grid = (int)(c.n_n < (1 << 20) ? c.n_n : (1 << 20));
+  int64_t work = c.n_n;
+  if (!elastic && listed >= 0 && listed * c.n_p < c.n_n / 2) {
+    // short list (its length known on the host): the listed elements' rows
+    a.list = c.plist;
+    a.elem = c.elem;
+    a.n_list = listed;
+    work = listed * c.n_p;
+    if (work == 0) return hipSuccess;
+  }
+  const int grid = (int)(work < (1 << 20) ? work : (1 << 20));
   const bool e32 = !elastic && c.opt.local_prec != EP_FP64;  // matrix-core element matrices
   const bool v32 = !elastic && c.opt.tangent_prec == EP_FP32;
 #define RG(OT, VT) \
@@ -2436,7 +2472,9 @@ static hipError_t row_gather_et(Ctx &c, bool elastic) {
 #undef RG
   return hipGetLastError();
 }
-hipError_t launch_row_gather(Ctx &c, bool elastic) { DISPATCH_ET(row_gather_et, c, elastic) }
+hipError_t launch_row_gather(Ctx &c, bool elastic, int64_t listed) {
+  DISPATCH_ET(row_gather_et, c, elastic, listed)
+}
 
 hipError_t launch_copy_ke_to_kt(Ctx &c) {
   const int64_t n = c.nnzb * c.dim * c.dim;

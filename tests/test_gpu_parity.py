@@ -13,6 +13,7 @@ torch = pytest.importorskip("torch")
 
 from gpu_cases import CASES, make_case  # noqa: E402
 from paper_1805_04155_amd import _ep  # noqa: E402
+from paper_1805_04155_amd import workloads as W  # noqa: E402
 
 RTOL = 1e-12
 
@@ -330,3 +331,38 @@ def test_stamp_wraparound(mode):
                 fresh.close()
     finally:
         ctx.close()
+
+
+def test_row_gather_short_work_list():
+    """With the work list's length on the host (inside a Newton step) and
+    few listed elements, the row gather visits only the listed elements'
+    rows: K_tangent equals the colour-round assembly's and the oracle's."""
+    import types
+    mesh, free, mat, u, _ = make_case("q1_3d_vm")
+    n = mesh.n_int
+    # three elements seeded plastic (plastic at u = 0, all their points)
+    wl = types.SimpleNamespace(mesh=mesh, material=mat)
+    ep2, beta2, _, _ = W.seeded_state(wl, 3.5 / mesh.n_elems, seed=4)
+    f = np.zeros(mesh.n_dof)
+    f[-1] = 1e-9  # a nonzero load: the step is not converged at u = 0
+    vals = {}
+    for mode in ("colours", "rows"):
+        ctx = _ep.Context(mesh, free, mat, options={
+            "assembly": _ep.EP_ASSEMBLY_ROWS if mode == "rows" else _ep.EP_ASSEMBLY_COLOURS})
+        try:
+            ctx.set_state(ep2, beta2)
+            uu = ctx.tensor(np.zeros(mesh.n_dof))
+            st, info = _ep.ep_newton_step(ctx.h, ctx.tensor(f), uu)
+            assert info["n_plastic_elem"] == 3
+            vals[mode] = _np(ctx.csr(1)[2])
+        finally:
+            ctx.close()
+    dphi, w = O.geometry(mesh)
+    rp, ci = O.pattern(mesh)
+    ref = O.constitutive(mat, O.strain(mesh, dphi, np.zeros(mesh.n_dof)),
+                         O.state_to_ip6(ep2, 3), O.state_to_ip6(beta2, 3))
+    _, _, Kt = O.assemble(mesh, dphi, w, ref["D"], rp, ci)
+    D0 = O.constitutive(mat, np.zeros((n, 6)), np.zeros((n, 6)))["D"]
+    _, _, Ke = O.assemble(mesh, dphi, w, D0, rp, ci)
+    for mode in ("colours", "rows"):
+        _row_scaled_close(vals[mode], Kt, rp, np.maximum(np.abs(Kt), np.abs(Ke)))
