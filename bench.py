@@ -366,7 +366,7 @@ def lshape_report(level, steps, assembly="colours"):
     mesh = wl.mesh
     ctx = _ep.Context(mesh, wl.free, wl.material, options={
         "newton_rtol": 1e-10,
-        "assembly": _ep.EP_ASSEMBLY_ROWS if assembly == "rows" else _ep.EP_ASSEMBLY_COLOURS})
+        "assembly": _ep.ASSEMBLY[assembly]})
     u = torch.zeros(mesh.n_dof, dtype=torch.float64, device="cuda")
     _ep.ep_profile(ctx.h, 1)
     for _ in range(5):
@@ -606,8 +606,7 @@ def measure_pass(name, frac, tangent, local_prec, steps, warmup, copy_gbs=None, 
     ctx = _ep.Context(mesh, wl.free, mat,
                       options={"tangent_prec": _ep.EP_FP64 if tb == 8 else _ep.EP_FP32,
                                "local_prec": lp,
-                               "assembly": _ep.EP_ASSEMBLY_ROWS if assembly == "rows"
-                               else _ep.EP_ASSEMBLY_COLOURS})
+                               "assembly": _ep.ASSEMBLY[assembly]})
     ctx.set_state(ep, beta if mat.model == "VM" else None, kappa if mat.model == "DP" else None)
     u = ctx.tensor(u_np)
     F = torch.empty(mesh.n_dof, dtype=torch.float64, device="cuda")
@@ -744,8 +743,9 @@ def main():
     ap.add_argument("--no-calibration-copy", action="store_true")
     ap.add_argument("--local-prec", choices=["fp64", "fp32", "bf16"], default="fp64",
                     help="element-local products (27-node hexahedra, P2 tetrahedra only)")
-    ap.add_argument("--assembly", choices=["colours", "rows"], default="colours",
-                    help="colour rounds with stamps, or element matrices + node-row gather")
+    ap.add_argument("--assembly", choices=["colours", "rows", "fused"], default="colours",
+                    help="colour rounds with stamps, element matrices + node-row gather, or "
+                         "node rows with the element terms formed in place")
     ap.add_argument("--no-slope", action="store_true",
                     help="skip the slope passes (FP64 and FP32 tangent values)")
     ap.add_argument("--no-newton", action="store_true",

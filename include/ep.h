@@ -99,8 +99,18 @@ typedef enum { EP_OPERATOR_ASSEMBLED = 0, EP_OPERATOR_SPLIT = 1 } ep_operator;
  *          points go to a buffer (one slot per element), then every node
  *          row touched by an element plastic now or at the last assembly
  *          is rewritten once as its K_elast row plus those elements' rows
- *          (ascending element), accumulated in LDS. */
-typedef enum { EP_ASSEMBLY_COLOURS = 0, EP_ASSEMBLY_ROWS = 1 } ep_assembly;
+ *          (ascending element), accumulated in LDS.
+ * FUSED:   one launch, ROWS without the buffer: each touched node row forms
+ *          its part of the element terms in place (the element geometry at
+ *          a plastic point is recomputed by each row of the element), no
+ *          colours or stamps.  FP64 element-local products only
+ *          (local_prec EP_FP64), at most 64 elements per node; K_elast is
+ *          assembled by colour rounds. */
+typedef enum {
+  EP_ASSEMBLY_COLOURS = 0,
+  EP_ASSEMBLY_ROWS = 1,
+  EP_ASSEMBLY_FUSED = 2
+} ep_assembly;
 
 typedef struct {
   int32_t dim;               /* 2 (plane strain) or 3                        */

@@ -18,7 +18,8 @@ EP_P1, EP_P2, EP_Q1, EP_Q2, EP_Q2S = 1, 2, 3, 4, 5
 EP_VM, EP_DP = 1, 2
 EP_FP64, EP_FP32, EP_BF16 = 0, 1, 2
 EP_OPERATOR_ASSEMBLED, EP_OPERATOR_SPLIT = 0, 1
-EP_ASSEMBLY_COLOURS, EP_ASSEMBLY_ROWS = 0, 1
+EP_ASSEMBLY_COLOURS, EP_ASSEMBLY_ROWS, EP_ASSEMBLY_FUSED = 0, 1, 2
+ASSEMBLY = {"colours": EP_ASSEMBLY_COLOURS, "rows": EP_ASSEMBLY_ROWS, "fused": EP_ASSEMBLY_FUSED}
 PROF = dict(constitutive=0, compaction=1, split=2, assembly=3, force=4, spmv=5, pcg_vec=6,
             elastic=7)
 

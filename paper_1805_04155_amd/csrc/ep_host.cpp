@@ -399,6 +399,18 @@ ep_status do_assemble(Ctx *c) {
     c->coff_known = false;
     return EP_OK;
   }
+  if (c->opt.assembly == EP_ASSEMBLY_FUSED) {
+    // one pass over the rows touched now or at the last assembly, the
+    // element terms formed in place
+    const int64_t listed = c->coff_known ? (int64_t)(c->coff_h[c->n_col] - c->coff_h[0]) : -1;
+    if (listed != 0) {
+      ProfScope ps(*c, PROF_ASSEMBLE);
+      HIPC(launch_row_fused(*c, listed));
+    }
+    c->em_asm = c->em_cur;
+    c->coff_known = false;
+    return EP_OK;
+  }
   // colour rounds with one-byte stamps: before the counter passes 255 every
   // stamp is cleared (a block without this assembly's stamp starts from
   // K_elast, so clearing is always safe)
@@ -672,8 +684,13 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   ep_options opt{EP_FP64, EP_FP64, 20000, 50, 1e-10, 1e-2, EP_OPERATOR_ASSEMBLED, 0.0, 12,
                  EP_ASSEMBLY_COLOURS};
   if (opt_in) opt = *opt_in;
-  if (opt.assembly != EP_ASSEMBLY_COLOURS && opt.assembly != EP_ASSEMBLY_ROWS)
-    return fail("ep_setup: assembly must be EP_ASSEMBLY_COLOURS or EP_ASSEMBLY_ROWS", EP_EINVAL);
+  if (opt.assembly != EP_ASSEMBLY_COLOURS && opt.assembly != EP_ASSEMBLY_ROWS &&
+      opt.assembly != EP_ASSEMBLY_FUSED)
+    return fail("ep_setup: assembly must be EP_ASSEMBLY_COLOURS, EP_ASSEMBLY_ROWS or "
+                "EP_ASSEMBLY_FUSED", EP_EINVAL);
+  if (opt.assembly == EP_ASSEMBLY_FUSED && opt.local_prec != EP_FP64)
+    return fail("ep_setup: the fused row assembly forms its element terms in FP64 "
+                "(local_prec must be EP_FP64)", EP_EINVAL);
   if (!(opt.newton_damping >= 0.0 && opt.newton_damping < 1.0))
     return fail("ep_setup: newton_damping must lie in [0, 1)", EP_EINVAL);
   if (opt.ls_max_evals <= 0) opt.ls_max_evals = 12;
@@ -768,6 +785,10 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   if (sizeof(double) * (size_t)c->max_deg * dim * dim + sizeof(int) * (size_t)c->max_slots >
       65536) {
     c->err = "ep_setup: a node row does not fit the 64 KB of LDS of the row gather";
+    return bail(EP_EINVAL);
+  }
+  if (opt.assembly == EP_ASSEMBLY_FUSED && c->max_slots > 64) {
+    c->err = "ep_setup: the fused row assembly takes at most 64 elements per node";
     return bail(EP_EINVAL);
   }
   const std::vector<int32_t> &n2e_ptr = gr.n2e_ptr, &fslot = gr.fslot, &slot_elem = gr.slot_elem,

@@ -95,6 +95,7 @@ hipError_t launch_emat(Ctx &c, bool elastic, int64_t listed);
 // node-row gather of c.emat into K_tangent (elastic: into K_elast); listed:
 // work-list length if known on the host (< 0: unknown)
 hipError_t launch_row_gather(Ctx &c, bool elastic, int64_t listed);
+hipError_t launch_row_fused(Ctx &c, int64_t listed);
 hipError_t launch_diag_inv(Ctx &c);
 hipError_t launch_spmv(Ctx &c, const double *x, double *y);
 // split form of the tangent: y = Q K_elast x + Q sum over plastic elements of

@@ -528,14 +528,16 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
   constexpr int NSLOT = Cfg::NSLOT;
   static_assert(NP * D <= BS && NQ <= BS, "one thread per coordinate and per point");
   __shared__ double s_x[NP * D];
-  __shared__ double s_M[NQ * NS * NS];     // w (D_q - C), all points of the element
+  // per plastic point: n and the scalars c1..c4 of w (D_q - C) (see below)
+  constexpr int PT = NS + 4;
+  __shared__ double s_pt[NQ * PT];
   __shared__ double s_Ji[NQ * D * D];
-  __shared__ double s_g[QC * D * NP];      // [q][d][p]
-  // H = M B per (point, node) [q][j][k][p]; after the local product the same
-  // LDS holds the element matrix [p][p'][r][c] (sorted scatter)
-  constexpr int NH_ = QC * D * NS * NP, NK_ = SORTED ? NB2 * D * D : 0;
-  __shared__ double s_HK[NH_ > NK_ ? NH_ : NK_];
-  double *const s_H = s_HK;
+  // per (point, node) of a chunk the vectors g, a, P, Q [q][4][d][p]; after
+  // the local product the same LDS holds the element matrix [p][p'][r][c]
+  // (sorted scatter)
+  constexpr int NV_ = QC * 4 * D * NP, NK_ = SORTED ? NB2 * D * D : 0;
+  __shared__ double s_HK[NV_ > NK_ ? NV_ : NK_];
+  double *const s_V = s_HK;
   double *const s_K = s_HK;
   __shared__ int s_node[NP];
   __shared__ int s_ord[NP];                // local nodes by ascending global id
@@ -676,18 +678,39 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
         for (int i = 0; i < D; ++i)
 #pragma unroll
           for (int jj = 0; jj < D; ++jj) s_Ji[tid * D * D + i * D + jj] = Ji[i][jj];
-        double dsc[NDESC];
+        // w (D_q - C) = w (alpha DEV + beta n n^T + gamma (n 1^T + 1 n^T) +
+        // delta 1 1^T) in Voigt form; its node blocks B_p^T (.) B_p' reduce to
+        // vectors of the nodes (below) with c1 = w (delta - alpha/3),
+        // c2 = w gamma, c3 = w beta, c4 = w alpha / 2 (C itself: n = 0,
+        // alpha = 2G, delta = K)
+        double *pt = s_pt + tid * PT;
+        double al, be, ga, de;
         if (!a.elastic) {
           const int64_t ip = (int64_t)e * NQ + q;
 #pragma unroll
-          for (int c = 0; c < NDESC; ++c) dsc[c] = a.desc[c * a.n_int + ip];
+          for (int c = 0; c < NS; ++c) pt[c] = a.desc[c * a.n_int + ip];
+          al = a.desc[NS * a.n_int + ip];
+          be = a.desc[(NS + 1) * a.n_int + ip];
+          ga = a.desc[(NS + 2) * a.n_int + ip];
+          de = a.desc[(NS + 3) * a.n_int + ip];
+        } else {
+#pragma unroll
+          for (int c = 0; c < NS; ++c) pt[c] = 0.0;
+          al = 2.0 * a.G;
+          be = 0.0;
+          ga = 0.0;
+          de = a.K;
         }
-        tangent_matrix<D>(dsc, a.elastic != 0, a.G, a.K, w, s_M + tid * NS * NS);
+        pt[NS] = w * (de - al / 3.0);
+        pt[NS + 1] = w * ga;
+        pt[NS + 2] = w * be;
+        pt[NS + 3] = 0.5 * w * al;
       }
       for (int q0 = 0; q0 < nq; q0 += QC) {
         const int nc = nq - q0 < QC ? nq - q0 : QC;
         __syncthreads();
-        // gradients and H = M B, one (point, node) per thread
+        // per (point, node): g = grad phi_p, a = B_p^T n (the tensor of n
+        // applied to g), P = c1 g + c2 a, Q = c3 a + c2 g
         for (int t = tid; t < nc * NP; t += BS) {
           const int ql = t / NP, p = t - (t / NP) * NP;
           const int qi = q0 + ql;
@@ -696,55 +719,56 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
           for (int i = 0; i < D; ++i)
 #pragma unroll
             for (int jj = 0; jj < D; ++jj) Ji[i][jj] = s_Ji[qi * D * D + i * D + jj];
-          double g[D];
+          double g[D], av[D];
           grad<D>(Ji, a.ref + (s_q[qi] * NP + p) * D, g);
-          const double *M = s_M + qi * NS * NS;
-          double *H = s_H + ql * D * NS * NP + p;
-#pragma unroll
-          for (int d = 0; d < D; ++d) s_g[(ql * D + d) * NP + p] = g[d];
+          const double *pt = s_pt + qi * PT;
           if constexpr (D == 3) {
-#pragma unroll
-            for (int kk = 0; kk < 6; ++kk) {
-              const double *m = M + kk * 6;
-              H[(0 * 6 + kk) * NP] = m[0] * g[0] + m[3] * g[1] + m[5] * g[2];
-              H[(1 * 6 + kk) * NP] = m[1] * g[1] + m[3] * g[0] + m[4] * g[2];
-              H[(2 * 6 + kk) * NP] = m[2] * g[2] + m[4] * g[1] + m[5] * g[0];
-            }
+            av[0] = pt[0] * g[0] + pt[3] * g[1] + pt[5] * g[2];
+            av[1] = pt[3] * g[0] + pt[1] * g[1] + pt[4] * g[2];
+            av[2] = pt[5] * g[0] + pt[4] * g[1] + pt[2] * g[2];
           } else {
+            av[0] = pt[0] * g[0] + pt[2] * g[1];
+            av[1] = pt[2] * g[0] + pt[1] * g[1];
+          }
+          const double c1 = pt[NS], c2 = pt[NS + 1], c3 = pt[NS + 2];
+          double *V = s_V + ql * 4 * D * NP + p;
 #pragma unroll
-            for (int kk = 0; kk < 3; ++kk) {
-              const double *m = M + kk * 3;
-              H[(0 * 3 + kk) * NP] = m[0] * g[0] + m[2] * g[1];
-              H[(1 * 3 + kk) * NP] = m[1] * g[1] + m[2] * g[0];
-            }
+          for (int d = 0; d < D; ++d) {
+            V[(0 * D + d) * NP] = g[d];
+            V[(1 * D + d) * NP] = av[d];
+            V[(2 * D + d) * NP] = c1 * g[d] + c2 * av[d];
+            V[(3 * D + d) * NP] = c3 * av[d] + c2 * g[d];
           }
         }
         __syncthreads();
-        // node blocks B_p^T H_p'
+        // node blocks: (B_p^T w (D - C) B_p')_ij =
+        //   g_i P'_j + a_i Q'_j + c4 (g'_i g_j + (g . g') delta_ij)
 #pragma unroll
         for (int j = 0; j < NBT; ++j) {
           if (!pon[j]) continue;
           const int p = pp_[j], pq = pq_[j];
           for (int ql = 0; ql < nc; ++ql) {
-            const double *gq = s_g + ql * D * NP;
-            const double *H = s_H + ql * D * NS * NP + pq;
-            if constexpr (D == 3) {
-              const double g0 = gq[p], g1 = gq[NP + p], g2 = gq[2 * NP + p];
+            const double *V = s_V + ql * 4 * D * NP;
+            const double c4 = s_pt[(q0 + ql) * PT + NS + 3];
+            double gp[D], ap[D], gq[D], Pq[D], Qq[D];
 #pragma unroll
-              for (int jj = 0; jj < 3; ++jj) {
-                const double *h = H + jj * 6 * NP;
-                acc[j][0 * 3 + jj] += g0 * h[0] + g1 * h[3 * NP] + g2 * h[5 * NP];
-                acc[j][1 * 3 + jj] += g1 * h[1 * NP] + g0 * h[3 * NP] + g2 * h[4 * NP];
-                acc[j][2 * 3 + jj] += g2 * h[2 * NP] + g1 * h[4 * NP] + g0 * h[5 * NP];
-              }
-            } else {
-              const double g0 = gq[p], g1 = gq[NP + p];
+            for (int d = 0; d < D; ++d) {
+              gp[d] = V[(0 * D + d) * NP + p];
+              ap[d] = V[(1 * D + d) * NP + p];
+              gq[d] = V[(0 * D + d) * NP + pq];
+              Pq[d] = V[(2 * D + d) * NP + pq];
+              Qq[d] = V[(3 * D + d) * NP + pq];
+            }
+            double dot = 0.0;
 #pragma unroll
-              for (int jj = 0; jj < 2; ++jj) {
-                const double *h = H + jj * 3 * NP;
-                acc[j][0 * 2 + jj] += g0 * h[0] + g1 * h[2 * NP];
-                acc[j][1 * 2 + jj] += g1 * h[1 * NP] + g0 * h[2 * NP];
-              }
+            for (int d = 0; d < D; ++d) dot += gp[d] * gq[d];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+              const double hq = c4 * gq[i];
+#pragma unroll
+              for (int jj = 0; jj < D; ++jj)
+                acc[j][i * D + jj] += gp[i] * Pq[jj] + ap[i] * Qq[jj] + hq * gp[jj];
+              acc[j][i * D + i] += c4 * dot;
             }
           }
         }
@@ -1264,6 +1288,203 @@ __global__ __launch_bounds__(RowCfg<ETID>::BS) void k_row_gather(KR a) {
         __syncthreads();
       }
     }
+    for (int v = tid; v < L; v += BS) out[r0 * DD + v] = (VT)s_acc[v];
+    __syncthreads();  // the LDS row is free for the next row
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Fused node-row assembly of K_tangent: one wavefront per row of nodes forms
+// the rows of the element terms w B_p^T (D_q - C) B_p' (eq. K-split) of the
+// row's elements with plastic points now, in place, and writes the row once
+// as its K_elast row plus those terms (ascending element).  No element
+// matrices, colours or stamps; the geometry of an element at a plastic point
+// is recomputed by each row that needs it.
+//   (slot, point) items: J^-1, c1..c4 and n of w (D_q - C) (the vector form
+//   of the element-local product), g and a = N g of the row's node;
+//   (slot, column node, point part) items: the 3x3 (2x2) block of the term,
+//   g_i P'_j + a_i Q'_j + c4 (g'_i g_j + (g . g') delta_ij), summed over the
+//   element's plastic points; the parts are summed across adjacent lanes in
+//   a fixed order.
+// ----------------------------------------------------------------------------
+struct KF {
+  KR r;
+  const double *coord;  // [dim][n_n]
+  const double *ref;    // reference gradients [n_q][n_p][dim], then weights [n_q]
+  const double *desc;   // tangent descriptors [n_desc][n_int]
+  int64_t n_int;
+};
+
+template <int ETID>
+struct FusedCfg {
+  using T = Et<ETID>;
+  static constexpr int BS = 64;               // one wavefront per row
+  static constexpr int CHS = BS / T::NP;      // element slots per chunk
+  static constexpr int NS = T::D == 3 ? 6 : 3;
+  static constexpr int PW = T::D * T::D + 4 + NS + 2 * T::D;  // doubles per (slot, point)
+  static size_t lds(int max_slots, int max_deg) {
+    return sizeof(double) * ((size_t)CHS * T::NQ * PW + (size_t)CHS * T::NP * T::D +
+                             (size_t)max_slots + (size_t)max_deg * T::D * T::D);
+  }
+};
+
+template <int ETID, typename VT>
+__global__ __launch_bounds__(64) void k_row_fused(KF f) {
+  using T = Et<ETID>;
+  using F = FusedCfg<ETID>;
+  constexpr int D = T::D, NP = T::NP, NQ = T::NQ, DD = D * D, BS = F::BS, CHS = F::CHS;
+  constexpr int NS = F::NS, PW = F::PW;
+  constexpr int OC = DD, ON = DD + 4, OG = DD + 4 + NS, OA = OG + D;  // offsets in an item
+  const KR &a = f.r;
+  extern __shared__ double s_dyn[];
+  double *const s_pq = s_dyn;                               // [CHS][NQ][PW]
+  double *const s_x = s_pq + CHS * NQ * PW;                 // [CHS][NP][D]
+  int *const s_sv = (int *)(s_x + CHS * NP * D);            // active slots e * n_p + p
+  uint32_t *const s_sm = (uint32_t *)(s_sv + a.max_slots);  // their point masks
+  double *const s_acc = s_x + CHS * NP * D + a.max_slots;   // the row
+  const int tid = threadIdx.x;
+  const VT *base = (const VT *)a.base;
+  VT *out = (VT *)a.out;
+  const uint32_t qmask = NQ == 32 ? 0xffffffffu : ((1u << NQ) - 1u);
+  const int64_t n_work = a.list ? a.n_list * NP : a.n_n;
+  for (int64_t b = blockIdx.x; b < n_work; b += gridDim.x) {
+    const int64_t m = a.list ? (int64_t)a.elem[(int64_t)a.list[b / NP] * NP + b % NP] : b;
+    const int k0 = a.n2e_ptr[m], k1 = a.n2e_ptr[m + 1];
+    const int64_t r0 = a.bptr[m];
+    const int L = (int)(a.bptr[m + 1] - r0) * DD;
+    // the row's element slots with plastic points now, in slot order (a
+    // row's slots fit in the wavefront)
+    uint32_t now = 0u, before = 0u;
+    int sv = 0;
+    if (tid < k1 - k0) {
+      sv = a.n2e[k0 + tid];
+      now = a.em_cur[sv / NP] & qmask;
+      before = a.em_prev ? a.em_prev[sv / NP] : 0u;
+    }
+    const unsigned long long bal = __ballot(now != 0u);
+    if (now) {
+      const int r = __popcll(bal & ((1ull << tid) - 1ull));
+      s_sv[r] = sv;
+      s_sm[r] = now;
+    }
+    const int nact = __popcll(bal);
+    const bool act = __syncthreads_or(a.list != nullptr || (now | before) != 0u) != 0;
+    if (!act) continue;  // uniform: neither now nor at the last assembly
+    for (int v = tid; v < L; v += BS) s_acc[v] = (double)base[r0 * DD + v];
+    for (int c0 = 0; c0 < nact; c0 += CHS) {
+      const int nc = nact - c0 < CHS ? nact - c0 : CHS;
+      for (int t = tid; t < nc * NP * D; t += BS) {
+        const int j = t / (NP * D), r = t - j * (NP * D);
+        const int64_t e = s_sv[c0 + j] / NP;
+        s_x[t] = f.coord[(int64_t)(r % D) * a.n_n + a.elem[e * NP + r / D]];
+      }
+      __syncthreads();
+      for (int t = tid; t < nc * NQ; t += BS) {
+        const int j = t / NQ, q = t - j * NQ;
+        if (!((s_sm[c0 + j] >> q) & 1u)) continue;
+        const int svj = s_sv[c0 + j];
+        const int64_t e = svj / NP;
+        const int p = svj - (int)e * NP;
+        double Ji[D][D];
+        const double det = jac_inv<D, NP>(s_x + j * NP * D, f.ref + q * NP * D, Ji);
+        const double w = fabs(det) * f.ref[NQ * NP * D + q];
+        const int64_t ip = e * NQ + q;
+        double nv[NS];
+#pragma unroll
+        for (int c = 0; c < NS; ++c) nv[c] = f.desc[c * f.n_int + ip];
+        const double al = f.desc[NS * f.n_int + ip], be = f.desc[(NS + 1) * f.n_int + ip];
+        const double ga = f.desc[(NS + 2) * f.n_int + ip], de = f.desc[(NS + 3) * f.n_int + ip];
+        double g[D], av[D];
+        grad<D>(Ji, f.ref + (q * NP + p) * D, g);
+        if constexpr (D == 3) {
+          av[0] = nv[0] * g[0] + nv[3] * g[1] + nv[5] * g[2];
+          av[1] = nv[3] * g[0] + nv[1] * g[1] + nv[4] * g[2];
+          av[2] = nv[5] * g[0] + nv[4] * g[1] + nv[2] * g[2];
+        } else {
+          av[0] = nv[0] * g[0] + nv[2] * g[1];
+          av[1] = nv[2] * g[0] + nv[1] * g[1];
+        }
+        double *o = s_pq + t * PW;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int jj = 0; jj < D; ++jj) o[i * D + jj] = Ji[i][jj];
+        o[OC + 0] = w * (de - al / 3.0);
+        o[OC + 1] = w * ga;
+        o[OC + 2] = w * be;
+        o[OC + 3] = 0.5 * w * al;
+#pragma unroll
+        for (int c = 0; c < NS; ++c) o[ON + c] = nv[c];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          o[OG + d] = g[d];
+          o[OA + d] = av[d];
+        }
+      }
+      __syncthreads();
+      // points split over 2^k adjacent lanes when the chunk leaves lanes free
+      int split = 1;
+      while (4 * split * nc * NP <= 2 * BS && 2 * split <= NQ) split *= 2;
+      const bool on = tid < nc * NP * split;
+      const int h = tid & (split - 1), jp = tid / split;
+      const int j = on ? jp / NP : 0, pp = jp - j * NP;
+      double acc[DD];
+#pragma unroll
+      for (int i = 0; i < DD; ++i) acc[i] = 0.0;
+      int dst = 0;
+      if (on) {
+        const int svj = s_sv[c0 + j];
+        dst = (a.bpos[(int64_t)svj * NP + pp] - (int32_t)r0) * DD;
+        const uint32_t msk = s_sm[c0 + j];
+        for (int q = h; q < NQ; q += split) {
+          if (!((msk >> q) & 1u)) continue;
+          const double *o = s_pq + (j * NQ + q) * PW;
+          double Ji[D][D];
+#pragma unroll
+          for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int jj = 0; jj < D; ++jj) Ji[i][jj] = o[i * D + jj];
+          double g2[D], a2[D], gp[D], ap[D];
+          grad<D>(Ji, f.ref + (q * NP + pp) * D, g2);
+          if constexpr (D == 3) {
+            a2[0] = o[ON + 0] * g2[0] + o[ON + 3] * g2[1] + o[ON + 5] * g2[2];
+            a2[1] = o[ON + 3] * g2[0] + o[ON + 1] * g2[1] + o[ON + 4] * g2[2];
+            a2[2] = o[ON + 5] * g2[0] + o[ON + 4] * g2[1] + o[ON + 2] * g2[2];
+          } else {
+            a2[0] = o[ON + 0] * g2[0] + o[ON + 2] * g2[1];
+            a2[1] = o[ON + 2] * g2[0] + o[ON + 1] * g2[1];
+          }
+          const double c1 = o[OC], c2 = o[OC + 1], c3 = o[OC + 2], c4 = o[OC + 3];
+          double dot = 0.0;
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            gp[d] = o[OG + d];
+            ap[d] = o[OA + d];
+            dot += gp[d] * g2[d];
+          }
+#pragma unroll
+          for (int jj = 0; jj < D; ++jj) {
+            const double P = c1 * g2[jj] + c2 * a2[jj], Qv = c3 * a2[jj] + c2 * g2[jj];
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+              acc[i * D + jj] += gp[i] * P + ap[i] * Qv + c4 * g2[i] * gp[jj];
+          }
+#pragma unroll
+          for (int i = 0; i < D; ++i) acc[i * D + i] += c4 * dot;
+        }
+      }
+      for (int o = split >> 1; o > 0; o >>= 1)
+#pragma unroll
+        for (int i = 0; i < DD; ++i) acc[i] += __shfl_xor(acc[i], o);
+      // slots in order: the blocks of one slot go to distinct blocks of the row
+      for (int jj = 0; jj < nc; ++jj) {
+        if (on && h == 0 && j == jj)
+#pragma unroll
+          for (int i = 0; i < DD; ++i) s_acc[dst + i] += acc[i];
+        __syncthreads();
+      }
+    }
+    __syncthreads();
     for (int v = tid; v < L; v += BS) out[r0 * DD + v] = (VT)s_acc[v];
     __syncthreads();  // the LDS row is free for the next row
   }
@@ -2474,6 +2695,48 @@ static hipError_t row_gather_et(Ctx &c, bool elastic, int64_t listed) {
 }
 hipError_t launch_row_gather(Ctx &c, bool elastic, int64_t listed) {
   DISPATCH_ET(row_gather_et, c, elastic, listed)
+}
+
+// Fused node-row assembly of K_tangent (FP64 element-local products).
+template <int ETID>
+static hipError_t row_fused_et(Ctx &c, int64_t listed) {
+  using F = FusedCfg<ETID>;
+  KF f{};
+  KR &a = f.r;
+  a.n_n = c.n_n;
+  a.bptr = c.bptr;
+  a.n2e_ptr = c.n2e_ptr;
+  a.n2e = c.n2e;
+  a.bpos = c.bpos;
+  a.max_slots = c.max_slots;
+  a.em_cur = c.em[c.em_cur];
+  a.em_prev = c.em_asm >= 0 ? c.em[c.em_asm] : nullptr;
+  a.base = c.opt.tangent_prec == EP_FP32 ? (const void *)c.Ke32 : (const void *)c.Ke;
+  a.out = c.Kt;
+  a.elem = c.elem;
+  f.coord = c.coord;
+  f.ref = c.ref;
+  f.desc = c.desc;
+  f.n_int = c.n_int;
+  if (c.n_n == 0) return hipSuccess;
+  if (c.max_slots > F::BS) return hipErrorInvalidValue;  // refused at setup
+  int64_t work = c.n_n;
+  if (listed >= 0 && listed * c.n_p < c.n_n / 2) {
+    a.list = c.plist;
+    a.n_list = listed;
+    work = listed * c.n_p;
+    if (work == 0) return hipSuccess;
+  }
+  const int grid = (int)(work < (1 << 20) ? work : (1 << 20));
+  const size_t lds = F::lds(c.max_slots, c.max_deg);
+  if (c.opt.tangent_prec == EP_FP32)
+    EP_LAUNCH((k_row_fused<ETID, float>), dim3(grid), dim3(F::BS), lds, c, f);
+  else
+    EP_LAUNCH((k_row_fused<ETID, double>), dim3(grid), dim3(F::BS), lds, c, f);
+  return hipGetLastError();
+}
+hipError_t launch_row_fused(Ctx &c, int64_t listed) {
+  DISPATCH_ET(row_fused_et, c, listed)
 }
 
 hipError_t launch_copy_ke_to_kt(Ctx &c) {

@@ -62,7 +62,7 @@ def _check_rows(a, b, rp):
     assert (np.abs(a - b) / rmax[rows]).max() <= RTOL
 
 
-@pytest.mark.parametrize("mode", ["colours", "rows"])
+@pytest.mark.parametrize("mode", ["colours", "rows", "fused"])
 @pytest.mark.parametrize("matname", list(MATERIALS))
 @pytest.mark.parametrize("name", list(TINY))
 @pytest.mark.parametrize("amp", [0.3, 0.6, 300.0])
@@ -77,7 +77,7 @@ def test_smallest_mesh(name, matname, amp, mode):
     if amp > 1.0 and mat.model == "VM":
         assert ref["flag"].all()  # the input really makes every point plastic
     ctx = _ep.Context(mesh, free, mat, options={
-        "assembly": _ep.EP_ASSEMBLY_ROWS if mode == "rows" else _ep.EP_ASSEMBLY_COLOURS})
+        "assembly": _ep.ASSEMBLY[mode]})
     try:
         sig, _, flag = ctx.constitutive(ctx.tensor(u), D=False)
         assert np.array_equal(_np(flag), ref["flag"])

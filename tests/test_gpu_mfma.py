@@ -34,7 +34,7 @@ def test_incremental_tangent_matrix_cores(case, prec, mode):
     the element matrices (FP32) go through the buffer of the row gather."""
     mesh, free, mat, u, (ep, beta, kappa) = make_case(case)
     opts = {"local_prec": _ep.EP_FP32 if prec == "fp32" else _ep.EP_BF16,
-            "assembly": _ep.EP_ASSEMBLY_ROWS if mode == "rows" else _ep.EP_ASSEMBLY_COLOURS}
+            "assembly": _ep.ASSEMBLY[mode]}
     if prec == "bf16_f32values":
         opts["tangent_prec"] = _ep.EP_FP32
     prec = prec.split("_")[0]
@@ -89,3 +89,11 @@ def test_newton_solution_unchanged_by_local_precision(prec):
     ua, ub = res["fp64"][0], res[prec][0]
     assert np.abs(ua - ub).max() <= 1e-9 * np.abs(ua).max()
     assert res[prec][1] >= res["fp64"][1]
+
+
+def test_fused_rows_refuse_reduced_local_precision():
+    """The fused row assembly forms its element terms in FP64 only."""
+    mesh = W.mesh_q2_3d(2, 1, 1, 1.0, 1.0, 1.0)
+    with pytest.raises(_ep.EpError):
+        _ep.Context(mesh, np.ones(mesh.n_dof, np.uint8), W.VM_MATERIAL,
+                    options={"local_prec": _ep.EP_FP32, "assembly": _ep.EP_ASSEMBLY_FUSED})

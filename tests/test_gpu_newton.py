@@ -255,7 +255,7 @@ def test_split_operator_load_paths(name):
         ctx_a.close()
 
 
-@pytest.mark.parametrize("mode", ["colours", "rows"])
+@pytest.mark.parametrize("mode", ["colours", "rows", "fused"])
 def test_lshape_vm_cyclic_path_small(mode):
     """The paper's von Mises example (Section 8.2) on the coarsest L-shape
     mesh of 20-node serendipity hexahedra: the whole cyclic load path
@@ -269,7 +269,7 @@ def test_lshape_vm_cyclic_path_small(mode):
     # the FP64 residual floor of this problem is ~2e-13
     uo, so = oracle_path(wl, steps, tol=1e-12)
     ctx, ug, recs, st = gpu_path(wl, steps, {
-        "assembly": _ep.EP_ASSEMBLY_ROWS if mode == "rows" else _ep.EP_ASSEMBLY_COLOURS})
+        "assembly": _ep.ASSEMBLY[mode]})
     try:
         assert max(s[3] for s in so) > 0
         for k in steps:
@@ -281,13 +281,13 @@ def test_lshape_vm_cyclic_path_small(mode):
         ctx.close()
 
 
-@pytest.mark.parametrize("mode", ["colours", "rows"])
+@pytest.mark.parametrize("mode", ["colours", "rows", "fused"])
 def test_assemble_elastic_resets_tangent(mode):
     """ep_assemble_elastic recomputes K_elast bit for bit and leaves
     K_tangent = K_elast; the next tangent assembly equals the one before."""
     wl = W.workload_lshape_vm(level=0, steps=8)
     ctx = _ep.Context(wl.mesh, wl.free, wl.material, options={
-        "assembly": _ep.EP_ASSEMBLY_ROWS if mode == "rows" else _ep.EP_ASSEMBLY_COLOURS})
+        "assembly": _ep.ASSEMBLY[mode]})
     try:
         _, _, Ke0 = ctx.csr(0)
         Ke0 = _np(Ke0)

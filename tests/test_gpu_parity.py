@@ -35,6 +35,7 @@ class Case:
         self.mesh, self.free, self.mat, self.u, (self.ep, self.beta, self.kappa) = make_case(name)
         self.dim = self.mesh.dim
         self.ctx = _ep.Context(self.mesh, self.free, self.mat)
+        self.ctx_modes = {}
         self.ctx.set_state(self.ep, self.beta if self.mat.model == "VM" else None,
                            self.kappa if self.mat.model == "DP" else None)
         self.dphi, self.w = O.geometry(self.mesh)
@@ -49,14 +50,18 @@ class Case:
     def du(self):
         return self.ctx.tensor(self.u)
 
-    def rows_ctx(self):
-        """A second context of the case assembling by node rows."""
-        if getattr(self, "ctx_rows", None) is None:
-            self.ctx_rows = _ep.Context(self.mesh, self.free, self.mat,
-                                        options={"assembly": _ep.EP_ASSEMBLY_ROWS})
-            self.ctx_rows.set_state(self.ep, self.beta if self.mat.model == "VM" else None,
-                                    self.kappa if self.mat.model == "DP" else None)
-        return self.ctx_rows
+    def mode_ctx(self, mode):
+        """The case's context for an assembly mode (colours: the first one;
+        rows, fused: a context of their own, made once)."""
+        if mode == "colours":
+            return self.ctx
+        if mode not in self.ctx_modes:
+            c = _ep.Context(self.mesh, self.free, self.mat,
+                            options={"assembly": _ep.ASSEMBLY[mode]})
+            c.set_state(self.ep, self.beta if self.mat.model == "VM" else None,
+                        self.kappa if self.mat.model == "DP" else None)
+            self.ctx_modes[mode] = c
+        return self.ctx_modes[mode]
 
 
 @pytest.fixture(scope="module", params=list(CASES))
@@ -64,8 +69,8 @@ def case(request):
     c = Case(request.param)
     yield c
     c.ctx.close()
-    if getattr(c, "ctx_rows", None) is not None:
-        c.ctx_rows.close()
+    for m in c.ctx_modes.values():
+        m.close()
 
 
 def _voigt_from_soa(arr, dim):
@@ -121,9 +126,9 @@ def _row_scaled_close(a_val, b_val, row_ptr, scale_val, tol=RTOL):
     assert err.max() <= tol, f"row-relative error {err.max():.3e}"
 
 
-@pytest.mark.parametrize("mode", ["colours", "rows"])
+@pytest.mark.parametrize("mode", ["colours", "rows", "fused"])
 def test_elastic_stiffness(case, mode):
-    ctx = case.ctx if mode == "colours" else case.rows_ctx()
+    ctx = case.mode_ctx(mode)
     rp, ci, val = ctx.csr(0)
     n = case.mesh.n_int
     D0 = O.constitutive(case.mat, np.zeros((n, 6)), np.zeros((n, 6)))["D"]
@@ -131,7 +136,7 @@ def test_elastic_stiffness(case, mode):
     _row_scaled_close(_np(val), ref, case.pattern[0], ref)
 
 
-@pytest.mark.parametrize("mode", ["colours", "rows"])
+@pytest.mark.parametrize("mode", ["colours", "rows", "fused"])
 def test_incremental_tangent_over_iterations(case, mode):
     """K_elast + B^T (D_t - D_e) B through several constitutive/assembly
     rounds with changing plastic sets (exercises the restore of blocks whose
@@ -139,7 +144,7 @@ def test_incremental_tangent_over_iterations(case, mode):
     the row gather) equals the oracle's plain sum w B^T D_t B each time.  The
     split cancels up to |K_elast|, so rows are scaled by max(|K_t|,
     |K_elast|) of the row."""
-    ctx = case.ctx if mode == "colours" else case.rows_ctx()
+    ctx = case.mode_ctx(mode)
     _, _, Ke = ctx.csr(0)
     Ke = _np(Ke)
     for k, s in enumerate([1.0, 0.3, 1.6, 0.0, 1.0]):
@@ -199,9 +204,9 @@ def test_spmv_matches_csr_product(case):
     close(y, ref)
 
 
-@pytest.mark.parametrize("mode", ["colours", "rows"])
+@pytest.mark.parametrize("mode", ["colours", "rows", "fused"])
 def test_determinism(case, mode):
-    ctx = case.ctx if mode == "colours" else case.rows_ctx()
+    ctx = case.mode_ctx(mode)
     outs = []
     for _ in range(2):
         ctx.constitutive(case.du(), sig=False, D=False, flag=False)
@@ -300,7 +305,7 @@ def test_split_apply_fp32_storage():
         ctx.close()
 
 
-@pytest.mark.parametrize("mode", ["colours", "rows"])
+@pytest.mark.parametrize("mode", ["colours", "rows", "fused"])
 def test_stamp_wraparound(mode):
     """Over 600 assemblies with changing plastic sets, K_tangent equals a
     fresh context's first assembly at the same displacement (equal values:
@@ -309,7 +314,7 @@ def test_stamp_wraparound(mode):
     one-byte assembly stamps every 255 assemblies."""
     mesh, free, mat, u0, (ep, beta, kappa) = make_case("q2_2d_dp")
     state = (ep, None, kappa)
-    opts = {"assembly": _ep.EP_ASSEMBLY_ROWS if mode == "rows" else _ep.EP_ASSEMBLY_COLOURS}
+    opts = {"assembly": _ep.ASSEMBLY[mode]}
     ctx = _ep.Context(mesh, free, mat, options=opts)
     try:
         ctx.set_state(*state)
@@ -346,9 +351,9 @@ def test_row_gather_short_work_list():
     f = np.zeros(mesh.n_dof)
     f[-1] = 1e-9  # a nonzero load: the step is not converged at u = 0
     vals = {}
-    for mode in ("colours", "rows"):
+    for mode in ("colours", "rows", "fused"):
         ctx = _ep.Context(mesh, free, mat, options={
-            "assembly": _ep.EP_ASSEMBLY_ROWS if mode == "rows" else _ep.EP_ASSEMBLY_COLOURS})
+            "assembly": _ep.ASSEMBLY[mode]})
         try:
             ctx.set_state(ep2, beta2)
             uu = ctx.tensor(np.zeros(mesh.n_dof))
@@ -364,5 +369,5 @@ def test_row_gather_short_work_list():
     _, _, Kt = O.assemble(mesh, dphi, w, ref["D"], rp, ci)
     D0 = O.constitutive(mat, np.zeros((n, 6)), np.zeros((n, 6)))["D"]
     _, _, Ke = O.assemble(mesh, dphi, w, D0, rp, ci)
-    for mode in ("colours", "rows"):
+    for mode in ("colours", "rows", "fused"):
         _row_scaled_close(vals[mode], Kt, rp, np.maximum(np.abs(Kt), np.abs(Ke)))
