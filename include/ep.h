@@ -95,6 +95,9 @@ typedef enum { EP_OPERATOR_ASSEMBLED = 0, EP_OPERATOR_SPLIT = 1 } ep_operator;
  *          node); each element adds its node blocks to K in place, a
  *          one-byte stamp per block telling whether the block still holds
  *          the previous assembly's values (then it starts from K_elast).
+ *          A work list whose length the host holds (inside ep_newton_step)
+ *          with at most 65536 (element, node, point) triples, FP64 local
+ *          products, takes the single launch of FUSED instead.
  * ROWS:    two launches: the element matrices of the elements with plastic
  *          points go to a buffer (one slot per element), then every node
  *          row touched by an element plastic now or at the last assembly

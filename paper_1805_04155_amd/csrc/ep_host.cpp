@@ -411,6 +411,24 @@ ep_status do_assemble(Ctx *c) {
     c->coff_known = false;
     return EP_OK;
   }
+  // a short work list whose length the host holds (inside a Newton step):
+  // one fused row pass instead of a launch per colour, which the launch
+  // latency of the colour rounds would dominate.  Both leave every block of a
+  // listed element at K_elast plus the terms of the elements plastic now and
+  // every other block at K_elast, so the next assembly may take either path
+  // (blocks without this assembly's stamp start from K_elast).
+  if (c->coff_known && c->opt.local_prec == EP_FP64 && c->max_slots <= 64) {
+    const int64_t listed = (int64_t)(c->coff_h[c->n_col] - c->coff_h[0]);
+    if (listed > 0 && listed * c->n_p * c->n_q <= SHORT_LIST_WORK) {
+      {
+        ProfScope ps(*c, PROF_ASSEMBLE);
+        HIPC(launch_row_fused(*c, listed));
+      }
+      c->em_asm = c->em_cur;
+      c->coff_known = false;
+      return EP_OK;
+    }
+  }
   // colour rounds with one-byte stamps: before the counter passes 255 every
   // stamp is cleared (a block without this assembly's stamp starts from
   // K_elast, so clearing is always safe)

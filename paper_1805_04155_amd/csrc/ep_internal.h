@@ -38,6 +38,9 @@ struct MatC {
 constexpr int CMP_THREADS = 256;
 constexpr int CMP_ITEMS = 8;
 constexpr int CMP_CHUNK = CMP_THREADS * CMP_ITEMS;
+// colour-round assembly: work lists of at most this many (element, node,
+// point) triples (listed elements x n_p x n_q) go through the fused row pass
+constexpr int64_t SHORT_LIST_WORK = 65536;
 
 // PCG scalars on the device (sc[SC_N]); SC_BREAK = 1 when PCG stopped on
 // p.q <= 0 or a non-finite scalar.

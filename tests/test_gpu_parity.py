@@ -371,3 +371,40 @@ def test_row_gather_short_work_list():
     _, _, Ke = O.assemble(mesh, dphi, w, D0, rp, ci)
     for mode in ("colours", "rows", "fused"):
         _row_scaled_close(vals[mode], Kt, rp, np.maximum(np.abs(Kt), np.abs(Ke)))
+
+
+def test_short_lists_alternate_with_colour_rounds():
+    """Colour mode inside Newton steps: a short work list (at most 65536
+    element x node x point triples) takes the fused row pass, a long one the
+    colour rounds.  Alternating the two (fused, colours over every element,
+    colours again, fused, colours with the stamps of the earlier rounds left
+    stale), K_tangent equals the oracle's at each step's displacement."""
+    import types
+    mesh = W.mesh_q1_3d(12, 12, 12, 1.0, 1.0, 1.0)   # 1728 elements > 65536 / 64
+    mat = W.VM_MATERIAL
+    free = W.free_mask(mesh, [(2, 0.0, [0, 1, 2])])
+    wl = types.SimpleNamespace(mesh=mesh, material=mat)
+    ep2, beta2, _, _ = W.seeded_state(wl, 3.5 / mesh.n_elems, seed=4)
+    yld = mat.Y / mat.E
+    u_big = W.random_displacement(mesh, 5, 300.0 * yld, free)
+    u0 = np.zeros(mesh.n_dof)
+    f = np.zeros(mesh.n_dof)
+    f[-1] = 1e-9
+    dphi, w = O.geometry(mesh)
+    rp, ci = O.pattern(mesh)
+    n = mesh.n_int
+    D0 = O.constitutive(mat, np.zeros((n, 6)), np.zeros((n, 6)))["D"]
+    _, _, Ke = O.assemble(mesh, dphi, w, D0, rp, ci)
+    ctx = _ep.Context(mesh, free, mat)
+    try:
+        ctx.set_state(ep2, beta2)
+        for k, (uu, n_el) in enumerate([(u0, 3), (u_big, mesh.n_elems), (u0, 3), (u0, 3),
+                                        (u_big, mesh.n_elems)]):
+            st, info = _ep.ep_newton_step(ctx.h, ctx.tensor(f), ctx.tensor(uu))
+            assert info["n_plastic_elem"] == n_el, k
+            ref = O.constitutive(mat, O.strain(mesh, dphi, uu), O.state_to_ip6(ep2, 3),
+                                 O.state_to_ip6(beta2, 3))
+            _, _, Kt = O.assemble(mesh, dphi, w, ref["D"], rp, ci)
+            _row_scaled_close(_np(ctx.csr(1)[2]), Kt, rp, np.maximum(np.abs(Kt), np.abs(Ke)))
+    finally:
+        ctx.close()
