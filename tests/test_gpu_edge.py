@@ -115,3 +115,29 @@ def test_no_plastic_point(name):
         assert not _np(ctx.internal_force()).any()
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_fused_rows_many_slots(order):
+    """Fused node rows where a node has more plastic elements than one chunk
+    of the wavefront holds (Kuhn tetrahedra: 24 around an interior vertex;
+    chunks of 16 P1 or 6 P2 elements): every point plastic, K_tangent and
+    the row-by-row order of the chunks against the oracle."""
+    mesh = W.mesh_tet_3d(3, 3, 3, 1.0, 0.8, 0.7, order=order)
+    mat = W.VM_MATERIAL
+    n2e = np.bincount(mesh.elem.ravel(), minlength=mesh.n_nodes)
+    assert n2e.max() > (16 if order == 1 else 6)
+    free = np.ones(mesh.n_dof, dtype=np.uint8)
+    on = np.abs(mesh.coord[0] - mesh.coord[0].min()) < 1e-12
+    for c in range(mesh.dim):
+        free[mesh.dim * np.nonzero(on)[0] + c] = 0
+    u = W.random_displacement(mesh, 7, 300.0 * mat.Y / mat.E)
+    ref, rp, K, _ = _oracle(mesh, mat, u)
+    assert ref["flag"].all()
+    ctx = _ep.Context(mesh, free, mat, options={"assembly": _ep.EP_ASSEMBLY_FUSED})
+    try:
+        ctx.constitutive(ctx.tensor(u), sig=False, D=False, flag=False)
+        ctx.assemble_tangent()
+        _check_rows(_np(ctx.csr(1)[2]), K, rp)
+    finally:
+        ctx.close()

@@ -118,3 +118,12 @@ def test_row_gather_assembly_rows_full(name):
     K_tangent at the FP64 bound of the colour-round assembly."""
     wl = {"q1_cube": W.workload_q1_cube, "p2_block": W.workload_p2_block}[name]()
     _rows_check(wl, {"assembly": _ep.EP_ASSEMBLY_ROWS}, 1e-12)
+
+
+@pytest.mark.parametrize("name", ["q1_cube", "q2_slope"])
+def test_fused_row_assembly_rows_full(name):
+    """The fused node-row assembly (FP64, every row scanned) at full size:
+    sampled rows of K_tangent at the FP64 bound of the colour-round
+    assembly."""
+    wl = {"q1_cube": W.workload_q1_cube, "q2_slope": W.workload_q2_slope}[name]()
+    _rows_check(wl, {"assembly": _ep.EP_ASSEMBLY_FUSED}, 1e-12)
