@@ -245,7 +245,10 @@ ep_status ep_constitutive(ep_ctx *ctx, const double *u, double *sig, double *D,
  * K_elast (blocks not yet written in this assembly) or to K_tangent through
  * the position map, one colour at a time (deterministic, no float atomics);
  * elements that left the plastic set restore K_elast on their blocks.  Cost
- * is proportional to that list, not to the mesh.
+ * is proportional to that list, not to the mesh.  The ROWS and FUSED modes
+ * (options.assembly) rewrite instead every node row touched by a listed
+ * element once, as its K_elast row plus the terms of the elements plastic
+ * now; every mode gives the same K up to the order of the sums.
  * Returns EP_ESTATE if ep_constitutive has not run since setup or commit,
  * EP_EINVAL for a context with operator_form SPLIT (nothing is assembled
  * there). */
