@@ -127,3 +127,12 @@ def test_fused_row_assembly_rows_full(name):
     assembly."""
     wl = {"q1_cube": W.workload_q1_cube, "q2_slope": W.workload_q2_slope}[name]()
     _rows_check(wl, {"assembly": _ep.EP_ASSEMBLY_FUSED}, 1e-12)
+
+
+def test_fused_row_assembly_fp32_values_full():
+    """Fused rows with FP32 tangent values on the full slope: sampled rows
+    at the FP32 storage bound."""
+    wl = W.workload_q2_slope()
+    worst = _rows_check(wl, {"assembly": _ep.EP_ASSEMBLY_FUSED, "tangent_prec": _ep.EP_FP32},
+                        TOL["store32"])
+    assert worst > 0.0

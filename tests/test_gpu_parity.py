@@ -373,12 +373,14 @@ def test_row_gather_short_work_list():
         _row_scaled_close(vals[mode], Kt, rp, np.maximum(np.abs(Kt), np.abs(Ke)))
 
 
-def test_short_lists_alternate_with_colour_rounds():
+@pytest.mark.parametrize("values", ["fp64", "fp32"])
+def test_short_lists_alternate_with_colour_rounds(values):
     """Colour mode inside Newton steps: a short work list (at most 65536
     element x node x point triples) takes the fused row pass, a long one the
     colour rounds.  Alternating the two (fused, colours over every element,
     colours again, fused, colours with the stamps of the earlier rounds left
-    stale), K_tangent equals the oracle's at each step's displacement."""
+    stale), K_tangent equals the oracle's at each step's displacement (FP32
+    values: to their roundings, one per touching element plus K_elast's)."""
     import types
     mesh = W.mesh_q1_3d(12, 12, 12, 1.0, 1.0, 1.0)   # 1728 elements > 65536 / 64
     mat = W.VM_MATERIAL
@@ -395,7 +397,9 @@ def test_short_lists_alternate_with_colour_rounds():
     n = mesh.n_int
     D0 = O.constitutive(mat, np.zeros((n, 6)), np.zeros((n, 6)))["D"]
     _, _, Ke = O.assemble(mesh, dphi, w, D0, rp, ci)
-    ctx = _ep.Context(mesh, free, mat)
+    ctx = _ep.Context(mesh, free, mat, options={
+        "tangent_prec": _ep.EP_FP32 if values == "fp32" else _ep.EP_FP64})
+    tol = 16 * 2.0 ** -24 if values == "fp32" else None  # at most 9 roundings to FP32
     try:
         ctx.set_state(ep2, beta2)
         for k, (uu, n_el) in enumerate([(u0, 3), (u_big, mesh.n_elems), (u0, 3), (u0, 3),
@@ -405,6 +409,10 @@ def test_short_lists_alternate_with_colour_rounds():
             ref = O.constitutive(mat, O.strain(mesh, dphi, uu), O.state_to_ip6(ep2, 3),
                                  O.state_to_ip6(beta2, 3))
             _, _, Kt = O.assemble(mesh, dphi, w, ref["D"], rp, ci)
-            _row_scaled_close(_np(ctx.csr(1)[2]), Kt, rp, np.maximum(np.abs(Kt), np.abs(Ke)))
+            if tol is None:
+                _row_scaled_close(_np(ctx.csr(1)[2]), Kt, rp, np.maximum(np.abs(Kt), np.abs(Ke)))
+            else:
+                _row_scaled_close(_np(ctx.csr(1)[2]).astype(np.float64), Kt, rp,
+                                  np.maximum(np.abs(Kt), np.abs(Ke)), tol=tol)
     finally:
         ctx.close()
