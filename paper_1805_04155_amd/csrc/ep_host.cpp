@@ -417,7 +417,7 @@ ep_status do_assemble(Ctx *c) {
   // listed element at K_elast plus the terms of the elements plastic now and
   // every other block at K_elast, so the next assembly may take either path
   // (blocks without this assembly's stamp start from K_elast).
-  if (c->coff_known && c->opt.local_prec == EP_FP64 && c->max_slots <= 64) {
+  if (c->coff_known && c->fused_ok) {
     const int64_t listed = (int64_t)(c->coff_h[c->n_col] - c->coff_h[0]);
     if (listed > 0 && listed * c->n_p * c->n_q <= SHORT_LIST_WORK) {
       {
@@ -805,8 +805,10 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
     c->err = "ep_setup: a node row does not fit the 64 KB of LDS of the row gather";
     return bail(EP_EINVAL);
   }
-  if (opt.assembly == EP_ASSEMBLY_FUSED && c->max_slots > 64) {
-    c->err = "ep_setup: the fused row assembly takes at most 64 elements per node";
+  c->fused_ok = opt.local_prec == EP_FP64 && c->max_slots <= 64 && row_fused_lds(*c) <= 65536;
+  if (opt.assembly == EP_ASSEMBLY_FUSED && !c->fused_ok) {
+    c->err = "ep_setup: the fused row assembly takes at most 64 elements per node and a node "
+             "row that fits 64 KB of LDS with its element data";
     return bail(EP_EINVAL);
   }
   const std::vector<int32_t> &n2e_ptr = gr.n2e_ptr, &fslot = gr.fslot, &slot_elem = gr.slot_elem,

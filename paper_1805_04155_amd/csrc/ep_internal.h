@@ -99,6 +99,7 @@ hipError_t launch_emat(Ctx &c, bool elastic, int64_t listed);
 // work-list length if known on the host (< 0: unknown)
 hipError_t launch_row_gather(Ctx &c, bool elastic, int64_t listed);
 hipError_t launch_row_fused(Ctx &c, int64_t listed);
+size_t row_fused_lds(const Ctx &c);  // dynamic LDS of the fused row pass
 hipError_t launch_diag_inv(Ctx &c);
 hipError_t launch_spmv(Ctx &c, const double *x, double *y);
 // split form of the tangent: y = Q K_elast x + Q sum over plastic elements of
@@ -190,6 +191,7 @@ struct Ctx {
   // n2e_ptr[m+1]-1, and element e's local node p writes entry fslot[e*n_p+p]
   int32_t *n2e_ptr = nullptr;  // [n_n+1]
   int32_t *n2e = nullptr;      // [n_e*n_p] slot -> e * n_p + p
+  bool fused_ok = false;       // the fused row pass fits (FP64 products, slots, LDS)
   // element matrices [n_e][n_p][n_p][dim][dim] (double, or float for
   // matrix-core local products) of the row-gather assembly
   void *emat = nullptr;

@@ -2767,6 +2767,20 @@ static hipError_t row_fused_et(Ctx &c, int64_t listed) {
 hipError_t launch_row_fused(Ctx &c, int64_t listed) {
   DISPATCH_ET(row_fused_et, c, listed)
 }
+size_t row_fused_lds(const Ctx &c) {
+  switch (c.et) {
+    case ET_P1_2D: return FusedCfg<ET_P1_2D>::lds(c.max_slots, c.max_deg);
+    case ET_Q1_2D: return FusedCfg<ET_Q1_2D>::lds(c.max_slots, c.max_deg);
+    case ET_Q2_2D: return FusedCfg<ET_Q2_2D>::lds(c.max_slots, c.max_deg);
+    case ET_P1_3D: return FusedCfg<ET_P1_3D>::lds(c.max_slots, c.max_deg);
+    case ET_P2_3D: return FusedCfg<ET_P2_3D>::lds(c.max_slots, c.max_deg);
+    case ET_Q1_3D: return FusedCfg<ET_Q1_3D>::lds(c.max_slots, c.max_deg);
+    case ET_Q2_3D: return FusedCfg<ET_Q2_3D>::lds(c.max_slots, c.max_deg);
+    case ET_Q2S_2D: return FusedCfg<ET_Q2S_2D>::lds(c.max_slots, c.max_deg);
+    case ET_Q2S_3D: return FusedCfg<ET_Q2S_3D>::lds(c.max_slots, c.max_deg);
+  }
+  return (size_t)-1;
+}
 
 hipError_t launch_copy_ke_to_kt(Ctx &c) {
   const int64_t n = c.nnzb * c.dim * c.dim;
