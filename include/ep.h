@@ -338,11 +338,14 @@ ep_status ep_pcg(ep_ctx *ctx, const double *b, double *x, double rtol, int32_t m
  * EP_PROFILE_ALL = every id): 0 constitutive, 1 compaction, 2 split-form
  * element terms and their node sum inside PCG, 3 colour assembly (one
  * count per colour launch), 4 force gather, 5 SpMV, 6 PCG vector update,
- * 7 K_elast assembly of ep_assemble_elastic.  While any id is timed, PCG
- * launches its kernels one by one instead of replaying a graph.
- * ep_profile_read returns the summed duration (ms) and the count of kernel
- * id k and resets both.  Both calls wait for the kernels timed so far. */
-#define EP_PROFILE_ALL 0xff
+ * 7 K_elast assembly of ep_assemble_elastic, 8 single-workgroup PCG of small
+ * systems (at most 12288 dofs, assembled operator: one launch runs a chunk
+ * of iterations, counted once per iteration; ids 5 and 6 stay empty there).
+ * While any id is timed, PCG launches its kernels one by one instead of
+ * replaying a graph.  ep_profile_read returns the summed duration (ms) and
+ * the count of kernel id k and resets both.  Both calls wait for the kernels
+ * timed so far. */
+#define EP_PROFILE_ALL 0x1ff
 ep_status ep_profile(ep_ctx *ctx, int32_t mask);
 ep_status ep_profile_read(ep_ctx *ctx, int32_t k, double *ms, int64_t *count);
 

@@ -21,7 +21,7 @@ EP_OPERATOR_ASSEMBLED, EP_OPERATOR_SPLIT = 0, 1
 EP_ASSEMBLY_COLOURS, EP_ASSEMBLY_ROWS, EP_ASSEMBLY_FUSED = 0, 1, 2
 ASSEMBLY = {"colours": EP_ASSEMBLY_COLOURS, "rows": EP_ASSEMBLY_ROWS, "fused": EP_ASSEMBLY_FUSED}
 PROF = dict(constitutive=0, compaction=1, split=2, assembly=3, force=4, spmv=5, pcg_vec=6,
-            elastic=7)
+            elastic=7, pcg_small=8)
 
 ETYPE = {"P1_2D": (2, EP_P1), "Q1_2D": (2, EP_Q1), "Q2_2D": (2, EP_Q2), "P1_3D": (3, EP_P1),
          "P2_3D": (3, EP_P2), "Q1_3D": (3, EP_Q1), "Q2_3D": (3, EP_Q2), "Q2S_2D": (2, EP_Q2S),
@@ -363,7 +363,7 @@ def ep_pcg(ctx, b, x, rtol, max_it):
     return st, its.value, rel.value
 
 
-EP_PROFILE_ALL = 0xFF
+EP_PROFILE_ALL = 0x1FF
 
 
 def ep_profile(ctx, enable, kernels=None):

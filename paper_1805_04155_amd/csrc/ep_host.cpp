@@ -492,6 +492,11 @@ double relative_residual(const double *norms_h) {
 // alternate two search-direction buffers, so an even chunk ends where it
 // started); otherwise the kernels are launched one by one.
 ep_status pcg_chunk(Ctx *c, double *x, int n) {
+  // small assembled systems: the chunk in one single-workgroup launch
+  if (c->opt.operator_form == EP_OPERATOR_ASSEMBLED && c->n_dof <= SMALL_PCG_DOFS) {
+    HIPC(launch_pcg_small(*c, x, n));
+    return EP_OK;
+  }
   if (c->prof_mask || n < 2 || n % 2 != 0) {
     for (int k = 0; k < n; ++k) HIPC(launch_pcg_iteration(*c, x));
     return EP_OK;

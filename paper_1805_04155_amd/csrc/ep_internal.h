@@ -49,7 +49,10 @@ enum { SC_RZ = 0, SC_PQ, SC_RR, SC_TOL, SC_DONE, SC_ITS, SC_ALPHA, SC_BETA, SC_R
 
 // Kernel ids for ep_profile.
 enum ProfId { PROF_CONST = 0, PROF_COMPACT, PROF_SPLIT, PROF_ASSEMBLE, PROF_FORCE, PROF_SPMV,
-              PROF_PCGVEC, PROF_ELASTIC, PROF_COUNT };
+              PROF_PCGVEC, PROF_ELASTIC, PROF_PCGSMALL, PROF_COUNT };
+// PCG of systems of at most this many dofs runs in one workgroup (a launch
+// per chunk of iterations instead of five per iteration)
+constexpr int64_t SMALL_PCG_DOFS = 12288;
 
 struct Ctx;
 
@@ -99,6 +102,7 @@ hipError_t launch_emat(Ctx &c, bool elastic, int64_t listed);
 // work-list length if known on the host (< 0: unknown)
 hipError_t launch_row_gather(Ctx &c, bool elastic, int64_t listed);
 hipError_t launch_row_fused(Ctx &c, int64_t listed);
+hipError_t launch_pcg_small(Ctx &c, double *x, int n_it);
 size_t row_fused_lds(const Ctx &c);  // dynamic LDS of the fused row pass
 hipError_t launch_diag_inv(Ctx &c);
 hipError_t launch_spmv(Ctx &c, const double *x, double *y);

@@ -2319,6 +2319,120 @@ __global__ __launch_bounds__(256) void k_pcg_beta(const double *partials, int nb
   }
 }
 
+// PCG iterations of a small system in one workgroup: the same steps and
+// scalars as the five-kernel iteration (p = z + beta p, q = Q K p with p.q,
+// alpha with the breakdown test, x, r, z updates with r.z and r.r, beta and
+// the stopping test), the direction updated in place, the reductions over
+// the workgroup in a fixed tree, the scalars in LDS and written back at the
+// end.  At most n_it iterations; stops early when done.
+constexpr int PCGS_T = 1024;
+
+// sums of a and b over the workgroup, fixed order: a butterfly inside each
+// wavefront, then the wavefronts' sums in order (every thread gets both)
+__device__ inline void pcgs_sum2(double *s, double &a, double &b) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+  if (lane == 0) {
+    s[2 * w] = a;
+    s[2 * w + 1] = b;
+  }
+  __syncthreads();
+  double ta = 0.0, tb = 0.0;
+#pragma unroll
+  for (int k = 0; k < PCGS_T / 64; ++k) {
+    ta += s[2 * k];
+    tb += s[2 * k + 1];
+  }
+  __syncthreads();
+  a = ta;
+  b = tb;
+}
+
+template <int D, typename VT>
+__global__ __launch_bounds__(PCGS_T) void k_pcg_small(int n_it, int64_t n_n, const int32_t *bptr,
+                                                      const int32_t *bcol, const VT *val,
+                                                      const uint8_t *freem, const double *dinv,
+                                                      double *x, double *r, double *z, double *p,
+                                                      double *q, double *sc) {
+  __shared__ double s_red[2 * (PCGS_T / 64)];
+  __shared__ double s_sc[SC_N];
+  const int tid = threadIdx.x;
+  const int64_t n_dof = D * n_n;
+  if (tid < SC_N) s_sc[tid] = sc[tid];
+  __syncthreads();
+  for (int it = 0; it < n_it && s_sc[SC_DONE] == 0.0; ++it) {
+    const double beta = s_sc[SC_BETA];
+    for (int64_t i = tid; i < n_dof; i += PCGS_T) p[i] = z[i] + beta * p[i];
+    __syncthreads();
+    double dot = 0.0;
+    for (int64_t m = tid; m < n_n; m += PCGS_T) {
+      double acc[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) acc[i] = 0.0;
+      const int b1 = bptr[m + 1];
+      for (int b = bptr[m]; b < b1; ++b) {
+        const int64_t cn = bcol[b];
+        const VT *v = val + (int64_t)b * D * D;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int j = 0; j < D; ++j) acc[i] += (double)v[i * D + j] * p[D * cn + j];
+      }
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        const int64_t rr = D * m + i;
+        const double yv = freem[rr] ? acc[i] : 0.0;
+        q[rr] = yv;
+        dot += p[rr] * yv;
+      }
+    }
+    double pq = dot, unused = 0.0;
+    pcgs_sum2(s_red, pq, unused);
+    if (tid == 0) {
+      s_sc[SC_PQ] = pq;
+      if (!(pq > 0.0 && pq <= DBL_MAX) || !(fabs(s_sc[SC_RZ]) <= DBL_MAX)) {
+        s_sc[SC_ALPHA] = 0.0;
+        s_sc[SC_BREAK] = 1.0;
+        s_sc[SC_DONE] = 1.0;
+      } else {
+        s_sc[SC_ALPHA] = s_sc[SC_RZ] / pq;
+      }
+    }
+    __syncthreads();
+    if (s_sc[SC_DONE] != 0.0) break;
+    const double al = s_sc[SC_ALPHA];
+    double rz = 0.0, rsq = 0.0;
+    for (int64_t i = tid; i < n_dof; i += PCGS_T) {
+      x[i] += al * p[i];
+      const double rv = r[i] - al * q[i];
+      r[i] = rv;
+      const double zv = dinv[i] * rv;
+      z[i] = zv;
+      rz += rv * zv;
+      rsq += rv * rv;
+    }
+    double srz = rz, srr = rsq;
+    pcgs_sum2(s_red, srz, srr);
+    if (tid == 0) {
+      if (!(fabs(srz) <= DBL_MAX && srr <= DBL_MAX)) {
+        s_sc[SC_BREAK] = 1.0;
+        s_sc[SC_DONE] = 1.0;
+      } else {
+        s_sc[SC_BETA] = srz / s_sc[SC_RZ];
+        s_sc[SC_RZ] = srz;
+        s_sc[SC_RR] = srr;
+        s_sc[SC_ITS] += 1.0;
+        if (srr <= s_sc[SC_TOL]) s_sc[SC_DONE] = 1.0;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid < SC_N) sc[tid] = s_sc[tid];
+}
+
 // r = Q b, x = 0, z = dinv r, p_old = 0, partial (r.z, r.r)
 __global__ __launch_bounds__(256) void k_pcg_init(int64_t n, const double *b, const uint8_t *freem,
                                                   double *x, double *r, double *z, double *pold,
@@ -2991,6 +3105,23 @@ hipError_t launch_pcg_iteration(Ctx &c, double *x) {
   RT(hipGetLastError());
   c.pcur = 1 - c.pcur;
   return hipSuccess;
+}
+
+hipError_t launch_pcg_small(Ctx &c, double *x, int n_it) {
+  ProfScope ps(c, PROF_PCGSMALL);
+  if (ps.tok >= 0) c.pending[ps.tok].count = n_it;
+  double *p = c.pp[c.pcur];
+#define PS(DIM, VT)                                                                           \
+  EP_LAUNCH((k_pcg_small<DIM, VT>), dim3(1), dim3(PCGS_T), 0, c, n_it, c.n_n, c.bptr, c.bcol, \
+            (const VT *)c.Kt, c.freem, c.dinv, x, c.r, c.pz, p, c.pq, c.sc)
+  const bool f32 = c.opt.tangent_prec == EP_FP32;
+  if (c.dim == 2) {
+    if (f32) PS(2, float); else PS(2, double);
+  } else {
+    if (f32) PS(3, float); else PS(3, double);
+  }
+#undef PS
+  return hipGetLastError();
 }
 
 hipError_t launch_pcg_beta_init(Ctx &c, double rtol) {

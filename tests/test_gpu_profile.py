@@ -57,9 +57,14 @@ def test_profile_sections(name):
                     assert 0.0 < p[k][0] < wall_ms, (k, p[k], wall_ms)
                 assert sum(p[k][0] for k in ("constitutive", "compaction", "assembly",
                                               "force")) < wall_ms
-                # iterations run in chunks: at least the converged count
-                assert p["spmv"][1] >= its and p["pcg_vec"][1] == p["spmv"][1]
-                assert p["spmv"][0] > 0.0 and p["pcg_vec"][0] > 0.0
+                # iterations run in chunks: at least the converged count (small
+                # systems: one single-workgroup launch per chunk)
+                if mesh.n_dof <= 12288:
+                    assert p["pcg_small"][1] >= its and p["pcg_small"][0] > 0.0
+                    assert p["spmv"][1] == 0 and p["pcg_vec"][1] == 0
+                else:
+                    assert p["spmv"][1] >= its and p["pcg_vec"][1] == p["spmv"][1]
+                    assert p["spmv"][0] > 0.0 and p["pcg_vec"][0] > 0.0
                 assert p["split"][1] == 0 and p["elastic"][1] == 0
             else:
                 assert all(v == (0.0, 0) for v in prof_read.values())
