@@ -273,7 +273,7 @@ void free_ctx(Ctx *c) {
                   c->cmp_counts2, c->cmp_counts3, c->F, c->r, c->partials,
                   c->norms, c->pz, c->pp[0], c->pp[1], c->pq, c->px, c->dinv, c->sc,
                   c->iscratch, c->mlp_x, c->mlp_y, c->wu_pred, c->wu_warm, c->ky[0],
-                  c->ky[1], c->ut, c->rn};
+                  c->ky[1], c->ut, c->rn, c->partials2, c->sc2};
   if (c->pcg_graph) (void)hipGraphExecDestroy(c->pcg_graph);
   if (c->gstream) (void)hipStreamDestroy(c->gstream);
   for (void *p : ptrs)
@@ -492,13 +492,24 @@ double relative_residual(const double *norms_h) {
 // alternate two search-direction buffers, so an even chunk ends where it
 // started); otherwise the kernels are launched one by one.
 ep_status pcg_chunk(Ctx *c, double *x, int n) {
+  const bool assembled = c->opt.operator_form == EP_OPERATOR_ASSEMBLED;
   // small assembled systems: the chunk in one single-workgroup launch
-  if (c->opt.operator_form == EP_OPERATOR_ASSEMBLED && c->n_dof <= SMALL_PCG_DOFS) {
+  if (assembled && c->n_dof <= SMALL_PCG_DOFS) {
     HIPC(launch_pcg_small(*c, x, n));
     return EP_OK;
   }
+  // moderate sizes: two kernels per iteration, the last beta step after the
+  // chunk; otherwise five kernels per iteration
+  const bool two = assembled && c->n_dof <= MEDIUM_PCG_DOFS;
+  auto enqueue = [&](int m) -> hipError_t {
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < m && e == hipSuccess; ++k)
+      e = two ? launch_pcg_iteration2(*c, x) : launch_pcg_iteration(*c, x);
+    if (two && e == hipSuccess) e = launch_pcg_finish2(*c);
+    return e;
+  };
   if (c->prof_mask || n < 2 || n % 2 != 0) {
-    for (int k = 0; k < n; ++k) HIPC(launch_pcg_iteration(*c, x));
+    HIPC(enqueue(n));
     return EP_OK;
   }
   if (!c->pcg_graph || c->pcg_graph_x != x || c->pcg_graph_n != n ||
@@ -512,7 +523,7 @@ ep_status pcg_chunk(Ctx *c, double *x, int n) {
     const int pcur = c->pcur;
     c->stream = c->gstream;
     hipError_t e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
-    for (int k = 0; k < n && e == hipSuccess; ++k) e = launch_pcg_iteration(*c, x);
+    if (e == hipSuccess) e = enqueue(n);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(c->gstream, &g);
     c->stream = user;
@@ -876,6 +887,8 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   // block of up to 32 lanes per node
   c->partials_cap = std::max<int64_t>(2 * ((n_dof + 255) / 256), (n_n * 32 + 255) / 256) + 64;
   SETUP_HIP(dalloc(&c->partials, c->partials_cap));
+  SETUP_HIP(dalloc(&c->partials2, c->partials_cap));
+  SETUP_HIP(dalloc(&c->sc2, 16));
   SETUP_HIP(dalloc(&c->norms, 16));
   SETUP_HIP(hipHostMalloc((void **)&c->norms_h, 16 * sizeof(double), hipHostMallocDefault));
   SETUP_HIP(dalloc(&c->pz, n_dof));

@@ -43,9 +43,10 @@ constexpr int CMP_CHUNK = CMP_THREADS * CMP_ITEMS;
 constexpr int64_t SHORT_LIST_WORK = 65536;
 
 // PCG scalars on the device (sc[SC_N]); SC_BREAK = 1 when PCG stopped on
-// p.q <= 0 or a non-finite scalar.
+// p.q <= 0 or a non-finite scalar; SC_NEED = 1 when the two-kernel iteration
+// has left its beta step to the next kernel.
 enum { SC_RZ = 0, SC_PQ, SC_RR, SC_TOL, SC_DONE, SC_ITS, SC_ALPHA, SC_BETA, SC_RR0, SC_BREAK,
-       SC_N };
+       SC_NEED, SC_N };
 
 // Kernel ids for ep_profile.
 enum ProfId { PROF_CONST = 0, PROF_COMPACT, PROF_SPLIT, PROF_ASSEMBLE, PROF_FORCE, PROF_SPMV,
@@ -53,6 +54,9 @@ enum ProfId { PROF_CONST = 0, PROF_COMPACT, PROF_SPLIT, PROF_ASSEMBLE, PROF_FORC
 // PCG of systems of at most this many dofs runs in one workgroup (a launch
 // per chunk of iterations instead of five per iteration)
 constexpr int64_t SMALL_PCG_DOFS = 12288;
+// up to this many dofs (assembled operator) a PCG iteration is two kernels:
+// each repeats the single-block scalar step of the one before it
+constexpr int64_t MEDIUM_PCG_DOFS = 131072;
 
 struct Ctx;
 
@@ -103,6 +107,8 @@ hipError_t launch_emat(Ctx &c, bool elastic, int64_t listed);
 hipError_t launch_row_gather(Ctx &c, bool elastic, int64_t listed);
 hipError_t launch_row_fused(Ctx &c, int64_t listed);
 hipError_t launch_pcg_small(Ctx &c, double *x, int n_it);
+hipError_t launch_pcg_iteration2(Ctx &c, double *x);
+hipError_t launch_pcg_finish2(Ctx &c);
 size_t row_fused_lds(const Ctx &c);  // dynamic LDS of the fused row pass
 hipError_t launch_diag_inv(Ctx &c);
 hipError_t launch_spmv(Ctx &c, const double *x, double *y);
@@ -244,6 +250,7 @@ struct Ctx {
   double *Fp = nullptr;
   int32_t *slot_elem = nullptr;
   double *partials = nullptr;  // reduction scratch
+  double *partials2 = nullptr, *sc2 = nullptr;  // two-kernel PCG iteration
   int64_t partials_cap = 0;
   double *norms = nullptr;     // [8] device
   double *norms_h = nullptr;   // pinned host [8]

@@ -2303,6 +2303,7 @@ __global__ __launch_bounds__(256) void k_pcg_beta(const double *partials, int nb
       sc[SC_TOL] = rtol * rtol * sb[0];
       sc[SC_ITS] = 0.0;
       sc[SC_BETA] = 0.0;
+      sc[SC_NEED] = 0.0;
       sc[SC_BREAK] = finite ? 0.0 : 1.0;
       sc[SC_DONE] = (!finite || sb[0] <= sc[SC_TOL]) ? 1.0 : 0.0;
     } else if (!finite) {
@@ -2317,6 +2318,186 @@ __global__ __launch_bounds__(256) void k_pcg_beta(const double *partials, int nb
       if (sb[0] <= sc[SC_TOL]) sc[SC_DONE] = 1.0;
     }
   }
+}
+
+// PCG iteration in two kernels (systems of moderate size).  The scalar
+// steps of the single-block kernels (alpha, beta) are repeated by every block
+// of the kernel that follows them: each block sums the same partials in the
+// same order (strided_sum, then the same tree), so all blocks hold the values
+// the single-block kernel would have computed, and block 0 records them in
+// the other scalar buffer (sc_in is only read inside a kernel).
+//   k_pcg_spmv2: the beta step left by k_pcg_update2 (SC_NEED), then
+//     q = Q K p with p = z + beta p_old formed at each use (the rows of the
+//     block store their p) and the block's partial p.q;
+//   k_pcg_update2: alpha with the breakdown test, then x, r, z and the
+//     block's partials r.z, r.r (SC_NEED = 1);
+//   k_pcg_finish2 (one block, after a chunk of iterations): the pending beta
+//     step, so that the host sees the same scalars as after the five-kernel
+//     iteration.
+__device__ inline void pcg2_beta_step(double *st, double rz, double rr) {
+  const bool finite = fabs(rz) <= DBL_MAX && rr <= DBL_MAX;
+  if (!finite) {
+    st[SC_BREAK] = 1.0;
+    st[SC_DONE] = 1.0;
+  } else {
+    st[SC_BETA] = rz / st[SC_RZ];
+    st[SC_RZ] = rz;
+    st[SC_RR] = rr;
+    st[SC_ITS] += 1.0;
+    if (rr <= st[SC_TOL]) st[SC_DONE] = 1.0;
+  }
+  st[SC_NEED] = 0.0;
+}
+
+// the beta step's two sums over the update kernel's partials (every thread of
+// the block calls it; the tree is that of k_pcg_beta)
+__device__ inline void pcg2_sums(const double *pin, int nin, double *sa, double *sb) {
+  const int tid = threadIdx.x;
+  sa[tid] = strided_sum(pin, nin, 2, tid, 256);
+  sb[tid] = strided_sum(pin + 1, nin, 2, tid, 256);
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      sa[tid] += sa[tid + h];
+      sb[tid] += sb[tid + h];
+    }
+    __syncthreads();
+  }
+}
+
+template <int D, typename VT, int G>
+__global__ __launch_bounds__(256) void k_pcg_spmv2(int64_t n_n, const int32_t *bptr,
+                                                   const int32_t *bcol, const VT *val,
+                                                   const double *z, const double *pold,
+                                                   double *pnew, const uint8_t *freem, double *q,
+                                                   const double *pin, int nin,
+                                                   const double *sc_in, double *sc_out,
+                                                   double *pout) {
+  __shared__ double sa[256], sb[256];
+  __shared__ double s_st[SC_N];
+  const int tid = threadIdx.x;
+  if (tid < SC_N) s_st[tid] = sc_in[tid];
+  __syncthreads();
+  if (s_st[SC_NEED] != 0.0 && s_st[SC_DONE] == 0.0) {  // uniform
+    pcg2_sums(pin, nin, sa, sb);
+    if (tid == 0) pcg2_beta_step(s_st, sa[0], sb[0]);
+    __syncthreads();
+  }
+  if (blockIdx.x == 0 && tid < SC_N) sc_out[tid] = s_st[tid];
+  if (s_st[SC_DONE] != 0.0) return;  // uniform
+  const double beta = s_st[SC_BETA];
+  const int g = tid % G;
+  const int64_t m = ((int64_t)blockIdx.x * 256 + tid) / G;
+  double acc[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) acc[i] = 0.0;
+  if (m < n_n) {
+    const int b1 = bptr[m + 1];
+    for (int b = bptr[m] + g; b < b1; b += G) {
+      const int64_t cn = bcol[b];
+      double xv[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) xv[j] = z[D * cn + j] + beta * pold[D * cn + j];
+      const VT *v = val + (int64_t)b * D * D;
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) acc[i] += (double)v[i * D + j] * xv[j];
+    }
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int i = 0; i < D; ++i) acc[i] += __shfl_xor(acc[i], o, G);
+  double dot = 0.0;
+  if (m < n_n && g == 0) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const int64_t r = D * m + i;
+      const double pv = z[r] + beta * pold[r];
+      pnew[r] = pv;
+      const double yv = freem[r] ? acc[i] : 0.0;
+      q[r] = yv;
+      dot += pv * yv;
+    }
+  }
+  // block sum of the group leaders' dots, fixed order (as k_spmv)
+  __shared__ double s[256 / G];
+  if (g == 0) s[tid / G] = dot;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int k = 0; k < 256 / G; ++k) t += s[k];
+    pout[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pcg_update2(int64_t n, double *x, const double *p,
+                                                     double *r, const double *q, double *z,
+                                                     const double *dinv, const double *pin,
+                                                     int nin, const double *sc_in,
+                                                     double *sc_out, double *pout) {
+  __shared__ double sa[256], sb[256];
+  __shared__ double s_st[SC_N];
+  const int tid = threadIdx.x;
+  if (tid < SC_N) s_st[tid] = sc_in[tid];
+  __syncthreads();
+  if (s_st[SC_DONE] == 0.0) {  // uniform: alpha as k_pcg_alpha
+    sa[tid] = strided_sum(pin, nin, 1, tid, 256);
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (tid < h) sa[tid] += sa[tid + h];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const double pq = sa[0];
+      s_st[SC_PQ] = pq;
+      if (!(pq > 0.0 && pq <= DBL_MAX) || !(fabs(s_st[SC_RZ]) <= DBL_MAX)) {
+        s_st[SC_ALPHA] = 0.0;
+        s_st[SC_BREAK] = 1.0;
+        s_st[SC_DONE] = 1.0;
+      } else {
+        s_st[SC_ALPHA] = s_st[SC_RZ] / pq;
+        s_st[SC_NEED] = 1.0;
+      }
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0 && tid < SC_N) sc_out[tid] = s_st[tid];
+  if (s_st[SC_DONE] != 0.0) return;  // uniform
+  const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+  double rz = 0.0, rr = 0.0;
+  if (i < n) {
+    const double al = s_st[SC_ALPHA];
+    x[i] += al * p[i];
+    const double rv = r[i] - al * q[i];
+    r[i] = rv;
+    const double zv = dinv[i] * rv;
+    z[i] = zv;
+    rz = rv * zv;
+    rr = rv * rv;
+  }
+  sa[tid] = rz;
+  sb[tid] = rr;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      sa[tid] += sa[tid + h];
+      sb[tid] += sb[tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    pout[2 * blockIdx.x] = sa[0];
+    pout[2 * blockIdx.x + 1] = sb[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pcg_finish2(const double *pin, int nin, double *sc) {
+  __shared__ double sa[256], sb[256];
+  if (sc[SC_NEED] == 0.0 || sc[SC_DONE] != 0.0) return;
+  pcg2_sums(pin, nin, sa, sb);
+  if (threadIdx.x == 0) pcg2_beta_step(sc, sa[0], sb[0]);
 }
 
 // PCG iterations of a small system in one workgroup: the same steps and
@@ -3121,6 +3302,60 @@ hipError_t launch_pcg_small(Ctx &c, double *x, int n_it) {
     if (f32) PS(3, float); else PS(3, double);
   }
 #undef PS
+  return hipGetLastError();
+}
+
+// Two-kernel PCG iteration: scalars sc -> sc2 (k_pcg_spmv2) -> sc
+// (k_pcg_update2), partials partials2 -> partials -> partials2.
+template <int D, typename VT>
+static hipError_t pcg_spmv2_launch(Ctx &c, const double *pold, double *pnew, int nin,
+                                   int *nblk) {
+  const int G = spmv_lanes(c);
+  const int grid = ceil_div(c.n_n * G, 256);
+  *nblk = grid;
+#define SP2(GG)                                                                               \
+  EP_LAUNCH((k_pcg_spmv2<D, VT, GG>), dim3(grid), dim3(256), 0, c, c.n_n, c.bptr, c.bcol,   \
+            (const VT *)c.Kt, c.pz, pold, pnew, c.freem, c.pq, c.partials2, nin, c.sc, c.sc2, \
+            c.partials)
+  switch (G) {
+    case 4: SP2(4); break;
+    case 8: SP2(8); break;
+    case 16: SP2(16); break;
+    default: SP2(32); break;
+  }
+#undef SP2
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_iteration2(Ctx &c, double *x) {
+  const int grid = ceil_div(c.n_dof, 256);
+  double *pold = c.pp[c.pcur], *pnew = c.pp[1 - c.pcur];
+  int nblk = 0;
+  {
+    ProfScope ps(c, PROF_SPMV);
+    const bool f32 = c.opt.tangent_prec == EP_FP32;
+    hipError_t e;
+    if (c.dim == 2)
+      e = f32 ? pcg_spmv2_launch<2, float>(c, pold, pnew, grid, &nblk)
+              : pcg_spmv2_launch<2, double>(c, pold, pnew, grid, &nblk);
+    else
+      e = f32 ? pcg_spmv2_launch<3, float>(c, pold, pnew, grid, &nblk)
+              : pcg_spmv2_launch<3, double>(c, pold, pnew, grid, &nblk);
+    RT(e);
+  }
+  {
+    ProfScope ps(c, PROF_PCGVEC);
+    EP_LAUNCH(k_pcg_update2, dim3(grid), dim3(256), 0, c, c.n_dof, x, pnew, c.r, c.pq, c.pz,
+              c.dinv, c.partials, nblk, c.sc2, c.sc, c.partials2);
+    RT(hipGetLastError());
+  }
+  c.pcur = 1 - c.pcur;
+  return hipSuccess;
+}
+
+hipError_t launch_pcg_finish2(Ctx &c) {
+  const int grid = ceil_div(c.n_dof, 256);
+  EP_LAUNCH(k_pcg_finish2, dim3(1), dim3(256), 0, c, c.partials2, grid, c.sc);
   return hipGetLastError();
 }
 
