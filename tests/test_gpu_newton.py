@@ -159,8 +159,12 @@ def test_quadratic_convergence_with_forcing():
         ctx.close()
 
 
-def test_pcg_against_direct_solve():
-    wl = W.workload_q1_cube(5)
+@pytest.mark.parametrize("n", [5, 16])
+def test_pcg_against_direct_solve(n):
+    """The PCG solution equals a direct solve of the free block: n = 5 (648
+    dofs) runs the single-workgroup PCG, n = 16 (14 739 dofs) the two-kernel
+    iteration."""
+    wl = W.workload_q1_cube(n)
     ep, beta, kappa, _ = W.seeded_state(wl, 0.5, seed=1)
     ctx = _ep.Context(wl.mesh, wl.free, wl.material)
     try:
@@ -195,11 +199,14 @@ def test_pcg_iteration_limit_is_reported():
         ctx.close()
 
 
-def test_pcg_graph_replay_matches_eager():
+@pytest.mark.parametrize("n", [5, 16, 36])
+def test_pcg_graph_replay_matches_eager(n):
     """PCG chunks replayed as a HIP graph give bit-identical iterates to the
     same kernels launched one by one (profiling on), over several solves
-    with eager work in between and with the graph reused and recaptured."""
-    wl = W.workload_q1_cube(5)
+    with eager work in between and with the graph reused and recaptured; for
+    each PCG size class (single workgroup, two kernels, five kernels per
+    iteration: 648, 14 739 and 151 959 dofs)."""
+    wl = W.workload_q1_cube(n)
     ep, beta, kappa, _ = W.seeded_state(wl, 0.5, seed=2)
     ctx = _ep.Context(wl.mesh, wl.free, wl.material, options={"pcg_check_every": 10})
     try:
