@@ -503,8 +503,9 @@ static void rm_vm(double G, double K, double a, double Y,
    associated flow; a = 0 is the paper's perfect plasticity.  For a > 0 the
    cohesion hardens linearly with the accumulated multiplier kappa (the
    paper's framework with W = R and H(chi) = a*chi).  flag: 0 elastic,
-   1 return to the smooth cone, 2 return to the apex.  The smooth / apex
-   decision follows the paper's listing: smooth iff CRIT2 <= 0. */
+   1 return to the smooth cone, 2 return to the apex.  At the tie the smooth
+   branch is taken (smooth iff CRIT2 <= 0), as the paper's implementation of
+   Section 2.3 decides; the text's inequalities leave the tie open. */
 static void rm_dp(double G, double K, double a, double eta, double c,
                   const double *eps_v, const double *ep_v, double kappa,
                   double *sig_v, double *D, uint8_t *flag, double *ep_out, double *kappa_out,
