@@ -159,14 +159,16 @@ def test_quadratic_convergence_with_forcing():
         ctx.close()
 
 
+@pytest.mark.parametrize("values", ["fp64", "fp32"])
 @pytest.mark.parametrize("n", [5, 16])
-def test_pcg_against_direct_solve(n):
-    """The PCG solution equals a direct solve of the free block: n = 5 (648
-    dofs) runs the single-workgroup PCG, n = 16 (14 739 dofs) the two-kernel
-    iteration."""
+def test_pcg_against_direct_solve(n, values):
+    """The PCG solution equals a direct solve of the free block (of the same
+    matrix: FP32 values taken as they are stored): n = 5 (648 dofs) runs the
+    single-workgroup PCG, n = 16 (14 739 dofs) the two-kernel iteration."""
     wl = W.workload_q1_cube(n)
     ep, beta, kappa, _ = W.seeded_state(wl, 0.5, seed=1)
-    ctx = _ep.Context(wl.mesh, wl.free, wl.material)
+    ctx = _ep.Context(wl.mesh, wl.free, wl.material, options={
+        "tangent_prec": _ep.EP_FP32 if values == "fp32" else _ep.EP_FP64})
     try:
         ctx.set_state(ep, beta)
         ctx.constitutive(ctx.tensor(np.zeros(wl.mesh.n_dof)), sig=False, D=False, flag=False)
@@ -176,7 +178,7 @@ def test_pcg_against_direct_solve(n):
         assert st == _ep.EP_OK and rel <= 1e-12
         rp, ci, val = (_np(t) for t in ctx.csr(1))
         import scipy.sparse.linalg as spla
-        K = O.csr_to_scipy(rp, ci, val, wl.mesh.n_dof)
+        K = O.csr_to_scipy(rp, ci, val.astype(np.float64), wl.mesh.n_dof)
         q = wl.free.astype(bool)
         xo = np.zeros(wl.mesh.n_dof)
         xo[q] = spla.spsolve(K[q][:, q].tocsc(), wl.f(3)[q])
