@@ -937,13 +937,21 @@ struct MfmaCfg {
   static constexpr int NPAIR = T::NP * (T::NP + 1) / 2;
   static constexpr int NBT = (NPAIR + 255) / 256;
   static constexpr int TPW = (NT + 3) / 4;
+  // occupancy target (waves per SIMD): 3 (three workgroups per CU; the LDS
+  // of the 27-node products fits that since the tangent is kept in its
+  // vector form), except the P2 BF16 colour kernel, measured faster with
+  // the compiler's own register budget
+  static constexpr int wpe(bool emat) {
+    return (emat || !(ETID == ET_P2_3D && BF16)) ? 3 : 1;
+  }
 };
 
 template <bool BF16> struct MfmaElem { using type = float; };
 template <> struct MfmaElem<true> { using type = __bf16; };
 
 template <int ETID, typename VT, bool BF16, bool EMAT = false>
-__global__ __launch_bounds__(256) void k_assemble_mfma(KA a) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(MfmaCfg<ETID, BF16>::wpe(EMAT), 8))) void k_assemble_mfma(KA a) {
   using T = Et<ETID>;
   using C = MfmaCfg<ETID, BF16>;
   using ET = typename MfmaElem<BF16>::type;
@@ -965,7 +973,9 @@ __global__ __launch_bounds__(256) void k_assemble_mfma(KA a) {
   ET *const s_H = s_B + MP * LDK;
   float *const s_K = ALIAS ? s_BHK : s_BHK + NBH;
   __shared__ double s_x[NP * 3];
-  __shared__ double s_M[NQ * 36];
+  // per plastic point: n and c1..c4 of w (D_q - C) (vector form, as in the
+  // FP64 kernel)
+  __shared__ double s_pt[NQ * 10];
   __shared__ double s_Ji[NQ * 9];
   __shared__ int s_q[NQ];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1052,11 +1062,16 @@ __global__ __launch_bounds__(256) void k_assemble_mfma(KA a) {
         for (int i = 0; i < 3; ++i)
 #pragma unroll
           for (int jj = 0; jj < 3; ++jj) s_Ji[tid * 9 + i * 3 + jj] = Ji[i][jj];
-        double dsc[10];
         const int64_t ip = (int64_t)e * NQ + q;
+        double *pt = s_pt + tid * 10;
 #pragma unroll
-        for (int c = 0; c < 10; ++c) dsc[c] = a.desc[c * a.n_int + ip];
-        tangent_matrix<3>(dsc, false, a.G, a.K, w, s_M + tid * 36);
+        for (int c = 0; c < 6; ++c) pt[c] = a.desc[c * a.n_int + ip];
+        const double al = a.desc[6 * a.n_int + ip], be = a.desc[7 * a.n_int + ip];
+        const double ga = a.desc[8 * a.n_int + ip], de = a.desc[9 * a.n_int + ip];
+        pt[6] = w * (de - al / 3.0);
+        pt[7] = w * ga;
+        pt[8] = w * be;
+        pt[9] = 0.5 * w * al;
       }
       f32x4_t tacc[TPW];
 #pragma unroll
@@ -1087,16 +1102,24 @@ __global__ __launch_bounds__(256) void k_assemble_mfma(KA a) {
               bc[1][rr] = b1[rr];
               bc[2][rr] = b2[rr];
             }
-            const double *M = s_M + qi * 36;
+            // H = w (D_q - C) B_q column by column: for the column of
+            // (p, i), 2 c4 I_sym b + P_i 1 + Q_i n with a = N g,
+            // P = c1 g + c2 a, Q = c3 a + c2 g (I_sym halves the shears)
+            const double *pt = s_pt + qi * 10;
+            double nv[6];
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
+            for (int c = 0; c < 6; ++c) nv[c] = pt[c];
+            const double c1 = pt[6], c2 = pt[7], c3 = pt[8], c4 = pt[9];
+            const double av[3] = {nv[0] * g[0] + nv[3] * g[1] + nv[5] * g[2],
+                                  nv[3] * g[0] + nv[1] * g[1] + nv[4] * g[2],
+                                  nv[5] * g[0] + nv[4] * g[1] + nv[2] * g[2]};
 #pragma unroll
-              for (int rr = 0; rr < 6; ++rr) {
-                double h = 0.0;
+            for (int i = 0; i < 3; ++i) {
+              const double P = c1 * g[i] + c2 * av[i], Qv = c3 * av[i] + c2 * g[i];
 #pragma unroll
-                for (int l = 0; l < 6; ++l) h += M[rr * 6 + l] * bc[i][l];
-                hc[i][rr] = h;
-              }
+              for (int rr = 0; rr < 6; ++rr)
+                hc[i][rr] = (rr < 3 ? 2.0 * c4 : c4) * bc[i][rr] + (rr < 3 ? P : 0.0) + Qv * nv[rr];
+            }
           } else {
 #pragma unroll
             for (int i = 0; i < 3; ++i)
