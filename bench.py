@@ -356,8 +356,9 @@ def lshape_report(level, steps, assembly="colours"):
     """The paper's von Mises example (Section 8.2) on the L-shaped domain of
     20-node serendipity hexahedra: tangent-assembly time of every Newton
     iteration against its number of plastic points, a least-squares line
-    through them, and the K_elast assembly time for comparison; plus the
-    hysteresis data (load factor, work f_max^T u) of the load path."""
+    through them, the tangent assembly with every point plastic (seeded),
+    and the K_elast assembly time for comparison; plus the hysteresis data
+    (load factor, work f_max^T u) of the load path."""
     import numpy as np
     import torch
     from paper_1805_04155_amd import _ep
@@ -389,6 +390,19 @@ def lshape_report(level, steps, assembly="colours"):
         hyst.append((round(float(wl.load_factors[k] / 200.0), 4),
                      round(float(torch.dot(fmax, u).item()), 6)))
     t = time.perf_counter() - t0
+    # every point plastic (all elements seeded at u = 0): the tangent
+    # assembly measured, one untimed pass first (it also restores the path's
+    # last plastic set)
+    ep, beta, _, _ = W.seeded_state(wl, 1.0, seed=0)
+    ctx.set_state(ep, beta, None)
+    u.zero_()
+    for k in range(6):
+        _ep.ep_constitutive(ctx.h, u)
+        _ep.ep_assemble_tangent(ctx.h)
+        if k == 0:
+            _ep.ep_profile_read(ctx.h, "assembly")
+    all_ms = _ep.ep_profile_read(ctx.h, "assembly")[0] / 5
+    all_ip, _ = _ep.ep_get_plastic(ctx.h)
     _ep.ep_profile(ctx.h, 0)
     ctx.close()
     n = np.array([p[0] for p in pts], dtype=np.float64)
@@ -413,9 +427,13 @@ def lshape_report(level, steps, assembly="colours"):
            if small else None,
            "assemblies_without_plastic_points_skipped": int(sum(1 for a, _ in pts if a == 0)),
            "ratio_all_plastic_to_elastic": round(float(full / el_ms), 3) if el_ms > 0 else None,
+           "measured_all_plastic": {"plastic_points": int(all_ip), "tangent_assembly_ms":
+                                    round(all_ms, 4), "ratio_to_elastic":
+                                    round(all_ms / el_ms, 3) if el_ms > 0 else None},
            "hysteresis_zeta_work": hyst}
     log(f"lshape {assembly}: {len(pts)} assemblies, fit {out['fit_ms']}, elastic "
-        f"{el_ms:.4f} ms, extrapolated {full:.4f} ms")
+        f"{el_ms:.4f} ms, extrapolated {full:.4f} ms, measured all plastic {all_ms:.4f} ms "
+        f"({all_ip} points)")
     return out
 
 

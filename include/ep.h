@@ -96,10 +96,14 @@ typedef enum { EP_OPERATOR_ASSEMBLED = 0, EP_OPERATOR_SPLIT = 1 } ep_operator;
  *          one-byte stamp per block telling whether the block still holds
  *          the previous assembly's values (then it starts from K_elast).
  *          A work list whose length the host holds (inside ep_newton_step)
- *          with at most 65536 (element, node, point) triples, FP64 local
- *          products, takes the single launch of FUSED instead.
+ *          is routed by its length: at most 4096 (element, node, point)
+ *          triples (FP64 local products) take the single launch of FUSED;
+ *          at most 16 elements and 24576 element-matrix entries per compute
+ *          unit the two launches of ROWS, in a buffer of that many
+ *          element slots; longer lists the colour rounds.
  * ROWS:    two launches: the element matrices of the elements with plastic
- *          points go to a buffer (one slot per element), then every node
+ *          points go to a buffer (slot: the element's work-list position),
+ *          then every node
  *          row touched by an element plastic now or at the last assembly
  *          is rewritten once as its K_elast row plus those elements' rows
  *          (ascending element), accumulated in LDS.

@@ -267,7 +267,7 @@ hipError_t upload(T *d, const std::vector<T> &h, hipStream_t s) {
 void free_ctx(Ctx *c) {
   if (!c) return;
   void *ptrs[] = {c->coord, c->elem, c->freem, c->ref, c->bptr, c->bcol, c->bdiag, c->bpos,
-                  c->Ke, c->Ke32, c->Kt, c->epoch, c->bposs, c->n2e_ptr, c->n2e, c->emat, c->fslot, c->slot_elem, c->Fp, c->ecol_perm,
+                  c->Ke, c->Ke32, c->Kt, c->epoch, c->bposs, c->n2e_ptr, c->n2e, c->emat, c->eslot, c->fslot, c->slot_elem, c->Fp, c->ecol_perm,
                   c->d_colour_first_block, c->ep_s, c->beta_s, c->kappa_s, c->flag, c->desc,
                   c->Fe, c->em[0], c->em[1], c->plist, c->coff, c->ptotals, c->cmp_counts,
                   c->cmp_counts2, c->cmp_counts3, c->F, c->r, c->partials,
@@ -423,6 +423,26 @@ ep_status do_assemble(Ctx *c) {
       {
         ProfScope ps(*c, PROF_ASSEMBLE);
         HIPC(launch_row_fused(*c, listed));
+      }
+      c->em_asm = c->em_cur;
+      c->coff_known = false;
+      return EP_OK;
+    }
+  }
+  // a longer list that fits the element-matrix buffer (a few elements per
+  // compute unit): the colour rounds would hold about one element per
+  // compute unit each and last one element's latency chain apiece; the
+  // element matrices (one launch over the whole list) and the node-row
+  // gather fill the device instead.  The gather also leaves K_elast plus the
+  // present terms in every block of a listed element.
+  if (c->coff_known && c->emat_cap > 0) {
+    const int64_t listed = (int64_t)(c->coff_h[c->n_col] - c->coff_h[0]);
+    if (listed > 0 && listed <= c->emat_cap) {
+      {
+        ProfScope ps(*c, PROF_ASSEMBLE);
+        if (ps.tok >= 0) c->pending[ps.tok].count = 2;
+        HIPC(launch_emat(*c, false, listed));
+        HIPC(launch_row_gather(*c, false, listed));
       }
       c->em_asm = c->em_cur;
       c->coff_known = false;
@@ -816,7 +836,7 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
     c->max_deg = std::max(c->max_deg, gr.bptr[m + 1] - gr.bptr[m]);
     c->max_slots = std::max(c->max_slots, gr.n2e_ptr[m + 1] - gr.n2e_ptr[m]);
   }
-  if (sizeof(double) * (size_t)c->max_deg * dim * dim + sizeof(int) * (size_t)c->max_slots >
+  if (sizeof(double) * (size_t)c->max_deg * dim * dim + 2 * sizeof(int) * (size_t)c->max_slots >
       65536) {
     c->err = "ep_setup: a node row does not fit the 64 KB of LDS of the row gather";
     return bail(EP_EINVAL);
@@ -854,9 +874,21 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   SETUP_HIP(dalloc(&c->n2e_ptr, n_n + 1));
   SETUP_HIP(dalloc(&c->n2e, n_e * n_p));
   // element matrices of the row-gather assembly, FP64 size (matrix-core
-  // products store FP32 in it)
-  if (opt.assembly == EP_ASSEMBLY_ROWS)
-    SETUP_HIP(hipMalloc(&c->emat, sizeof(double) * std::max<int64_t>(1, n_e * n_p * n_p * dim * dim)));
+  // products store FP32 in it): every element in rows mode; in colour mode
+  // the work lists of at most ROW_ROUTE_PER_CU elements and
+  // ROW_ROUTE_ENTRIES_PER_CU element-matrix entries per compute unit (about
+  // 50 MB on 256 compute units)
+  if (opt.assembly == EP_ASSEMBLY_ROWS) {
+    c->emat_cap = n_e;
+  } else if (opt.assembly == EP_ASSEMBLY_COLOURS) {
+    const int64_t entries = (int64_t)n_p * n_p * dim * dim;
+    c->emat_cap = std::min<int64_t>({n_e, ROW_ROUTE_PER_CU * c->n_cu,
+                                     ROW_ROUTE_ENTRIES_PER_CU * c->n_cu / entries});
+  }
+  if (c->emat_cap > 0) {
+    SETUP_HIP(hipMalloc(&c->emat, sizeof(double) * c->emat_cap * n_p * n_p * dim * dim));
+    SETUP_HIP(dalloc(&c->eslot, n_e));
+  }
   SETUP_HIP(dalloc(&c->fslot, n_e * n_p));
   SETUP_HIP(dalloc(&c->slot_elem, n_e * n_p));
   SETUP_HIP(dalloc(&c->Fp, n_e * n_p * dim));

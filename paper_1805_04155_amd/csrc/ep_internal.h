@@ -40,7 +40,12 @@ constexpr int CMP_ITEMS = 8;
 constexpr int CMP_CHUNK = CMP_THREADS * CMP_ITEMS;
 // colour-round assembly: work lists of at most this many (element, node,
 // point) triples (listed elements x n_p x n_q) go through the fused row pass
-constexpr int64_t SHORT_LIST_WORK = 65536;
+constexpr int64_t SHORT_LIST_WORK = 4096;
+// colour-round assembly: longer work lists of at most this many elements,
+// and element-matrix entries, per compute unit go through the element
+// matrices and the node-row gather
+constexpr int64_t ROW_ROUTE_PER_CU = 16;
+constexpr int64_t ROW_ROUTE_ENTRIES_PER_CU = 24576;
 
 // PCG scalars on the device (sc[SC_N]); SC_BREAK = 1 when PCG stopped on
 // p.q <= 0 or a non-finite scalar; SC_NEED = 1 when the two-kernel iteration
@@ -202,9 +207,14 @@ struct Ctx {
   int32_t *n2e_ptr = nullptr;  // [n_n+1]
   int32_t *n2e = nullptr;      // [n_e*n_p] slot -> e * n_p + p
   bool fused_ok = false;       // the fused row pass fits (FP64 products, slots, LDS)
-  // element matrices [n_e][n_p][n_p][dim][dim] (double, or float for
-  // matrix-core local products) of the row-gather assembly
+  // element matrices [slot][n_p][n_p][dim][dim] (double, or float for
+  // matrix-core local products) of the row-gather assembly: emat_cap slots
+  // (rows mode: n_e; colour mode: the work lists it routes to the gather);
+  // a tangent assembly stores element e at its work-list position,
+  // eslot[e] (K_elast, rows mode only: at slot e)
   void *emat = nullptr;
+  int64_t emat_cap = 0;
+  int32_t *eslot = nullptr;    // [n_e]
   int max_deg = 0, max_slots = 0;  // largest node row (blocks) and node-to-element count
   int32_t *fslot = nullptr;    // [n_e*n_p]
 

@@ -461,6 +461,10 @@ struct KA {
   int colour_end;
   double *emat64;
   float *emat32;
+  // with eslot: an element's matrix goes to the slot of its work-list
+  // position (k - first position), recorded in eslot[e], so that the buffer
+  // needs only as many slots as the list has entries; without: slot e
+  int32_t *eslot;
 };
 
 template <int ETID>
@@ -829,7 +833,9 @@ __attribute__((amdgpu_waves_per_eu(AsmCfg<ETID>::WPE, 8))) void k_assemble(KA a)
     }
     if constexpr (EMAT) {
       // the element matrix, [p][p'][r][c], to its slot of the buffer
-      double *dst = a.emat64 + (int64_t)e * NB2 * D * D;
+      const int64_t slot = a.eslot ? k - k0 : (int64_t)e;
+      if (a.eslot && tid == 0) a.eslot[e] = (int32_t)slot;
+      double *dst = a.emat64 + slot * NB2 * D * D;
       if constexpr (SORTED) {
         for (int t = tid; t < NB2 * D * D; t += BS) dst[t] = s_K[t];
       } else {
@@ -1184,7 +1190,9 @@ __attribute__((amdgpu_waves_per_eu(MfmaCfg<ETID, BF16>::wpe(EMAT), 8))) void k_a
       __syncthreads();
       if constexpr (EMAT) {
         // the element matrix, [p][p'][r][c] (FP32 accumulators), to its slot
-        float *dst = a.emat32 + (int64_t)e * NB2 * 9;
+        const int64_t slot = a.eslot ? k - k0 : (int64_t)e;
+        if (a.eslot && tid == 0) a.eslot[e] = (int32_t)slot;
+        float *dst = a.emat32 + slot * NB2 * 9;
         for (int t = tid; t < NB2 * 9; t += 256) {
           const int pb = t / 9, rc = t - (t / 9) * 9;
           const int p = pb / NP, pq = pb - (pb / NP) * NP;
@@ -1264,6 +1272,9 @@ struct KR {
   // listed elements is computed twice, with the same values
   const int32_t *list, *elem;
   int64_t n_list;
+  // element e's matrix at slot eslot[e] of emat (element matrices stored by
+  // work-list position), or at slot e when null
+  const int32_t *eslot;
 };
 
 template <int ETID>
@@ -1296,6 +1307,7 @@ __global__ __launch_bounds__(RowCfg<ETID>::BS) void k_row_gather(KR a) {
     const int L = (int)(a.bptr[m + 1] - r0) * DD;
     double *s_acc = s_dyn;
     int *s_sv = (int *)(s_dyn + L);  // slot value e * n_p + p, or -1 (no term now)
+    int *s_ev = s_sv + a.max_slots;  // its element matrix's rows: slot * n_p + p
     // slots of the row: element terms present now, and whether the row is
     // touched by an element listed now or at the last assembly
     bool act = all || a.list != nullptr;
@@ -1305,6 +1317,7 @@ __global__ __launch_bounds__(RowCfg<ETID>::BS) void k_row_gather(KR a) {
       const uint32_t now = all ? 1u : a.em_cur[e];
       const uint32_t before = (all || !a.em_prev) ? 0u : a.em_prev[e];
       s_sv[k - k0] = now ? sv : -1;
+      if (now) s_ev[k - k0] = a.eslot ? a.eslot[e] * NP + (sv - e * NP) : sv;
       act = act || ((now | before) != 0u);
     }
     act = __syncthreads_or(act) != 0;
@@ -1327,7 +1340,7 @@ __global__ __launch_bounds__(RowCfg<ETID>::BS) void k_row_gather(KR a) {
           if (sv >= 0) {
             const int pp = t / DD, ij = t - (t / DD) * DD;
             dst[i] = (a.bpos[(int64_t)sv * NP + pp] - (int32_t)r0) * DD + ij;
-            val[i] = (double)emat[(int64_t)sv * NV + t];
+            val[i] = (double)emat[(int64_t)s_ev[kc + sj] * NV + t];
             sl[i] = sj;
           }
         }
@@ -2956,6 +2969,7 @@ static hipError_t emat_et(Ctx &c, bool elastic, int64_t listed) {
   a.elastic = elastic ? 1 : 0;
   a.emat64 = (double *)c.emat;
   a.emat32 = (float *)c.emat;
+  a.eslot = elastic ? nullptr : c.eslot;
   int64_t cnt;
   if (elastic) {
     a.list = c.ecol_perm;
@@ -3003,6 +3017,7 @@ static hipError_t row_gather_et(Ctx &c, bool elastic, int64_t listed) {
   a.n2e = c.n2e;
   a.bpos = c.bpos;
   a.emat = c.emat;
+  a.eslot = elastic ? nullptr : c.eslot;
   a.max_slots = c.max_slots;
   if (elastic) {
     a.em_cur = nullptr;
@@ -3017,7 +3032,7 @@ static hipError_t row_gather_et(Ctx &c, bool elastic, int64_t listed) {
   }
   if (c.n_n == 0) return hipSuccess;
   const int D = c.dim;
-  const size_t lds = sizeof(double) * (size_t)c.max_deg * D * D + sizeof(int) * c.max_slots;
+  const size_t lds = sizeof(double) * (size_t)c.max_deg * D * D + 2 * sizeof(int) * c.max_slots;
   int64_t work = c.n_n;
   if (!elastic && listed >= 0 && listed * c.n_p < c.n_n / 2) {
     // short list (its length known on the host): the listed elements' rows

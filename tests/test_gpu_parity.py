@@ -374,19 +374,28 @@ def test_row_gather_short_work_list():
 
 
 @pytest.mark.parametrize("values", ["fp64", "fp32"])
-def test_short_lists_alternate_with_colour_rounds(values):
-    """Colour mode inside Newton steps: a short work list (at most 65536
-    element x node x point triples) takes the fused row pass, a long one the
-    colour rounds.  Alternating the two (fused, colours over every element,
-    colours again, fused, colours with the stamps of the earlier rounds left
-    stale), K_tangent equals the oracle's at each step's displacement (FP32
-    values: to their roundings, one per touching element plus K_elast's)."""
+def test_work_list_routes_alternate(values):
+    """Colour mode inside Newton steps routes the work list by its length:
+    at most 4096 (element, node, point) triples take the fused row pass (one
+    launch), at most 16 elements and 24576 element-matrix entries per
+    compute unit the element matrices and the node-row gather (two
+    launches), longer lists the colour rounds (one launch per colour).  Alternating the three over plastic sets that grow
+    and shrink (the seeded state switched between steps, stamps of earlier
+    colour rounds left stale), K_tangent equals the oracle's at each step
+    (FP32 values: to their roundings, one per touching element plus
+    K_elast's), and the profile's launch count names the route taken."""
     import types
-    mesh = W.mesh_q1_3d(12, 12, 12, 1.0, 1.0, 1.0)   # 1728 elements > 65536 / 64
+    import torch
+    mesh = W.mesh_q1_3d(20, 20, 20, 1.0, 1.0, 1.0)   # 8000 elements
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    cap = min(mesh.n_elems, 16 * n_cu, 24576 * n_cu // 576)
+    n_mid = 1500   # 8 nodes x 8 points: above 4096 triples, at most the cap
+    assert 3 * 8 * 8 <= 4096 < n_mid * 8 * 8 and n_mid <= cap < mesh.n_elems
     mat = W.VM_MATERIAL
     free = W.free_mask(mesh, [(2, 0.0, [0, 1, 2])])
     wl = types.SimpleNamespace(mesh=mesh, material=mat)
-    ep2, beta2, _, _ = W.seeded_state(wl, 3.5 / mesh.n_elems, seed=4)
+    st_few = W.seeded_state(wl, 3.5 / mesh.n_elems, seed=4)[:2]
+    st_mid = W.seeded_state(wl, (n_mid + 0.5) / mesh.n_elems, seed=4)[:2]
     yld = mat.Y / mat.E
     u_big = W.random_displacement(mesh, 5, 300.0 * yld, free)
     u0 = np.zeros(mesh.n_dof)
@@ -400,12 +409,27 @@ def test_short_lists_alternate_with_colour_rounds(values):
     ctx = _ep.Context(mesh, free, mat, options={
         "tangent_prec": _ep.EP_FP32 if values == "fp32" else _ep.EP_FP64})
     tol = 16 * 2.0 ** -24 if values == "fp32" else None  # at most 9 roundings to FP32
+    # (state, displacement, plastic elements, launches: 1 fused, 2 rows, > 2
+    # colours).  The work list holds the elements plastic now or at the last
+    # assembly (their blocks are restored), so the step after an all-plastic
+    # one runs the colour rounds, and a shrinking set restores through the
+    # route of the longer list.
+    steps = [(st_few, u0, 3, 1), (st_mid, u0, n_mid, 2), (st_mid, u_big, mesh.n_elems, None),
+             (st_mid, u0, n_mid, None), (st_mid, u0, n_mid, 2), (st_few, u0, 3, 2),
+             (st_few, u0, 3, 1), (st_mid, u0, n_mid, 2), (st_few, u_big, mesh.n_elems, None),
+             (st_few, u0, 3, None), (st_few, u0, 3, 1)]
     try:
-        ctx.set_state(ep2, beta2)
-        for k, (uu, n_el) in enumerate([(u0, 3), (u_big, mesh.n_elems), (u0, 3), (u0, 3),
-                                        (u_big, mesh.n_elems)]):
+        _ep.ep_profile(ctx.h, True, ["assembly"])
+        for k, ((ep2, beta2), uu, n_el, launches) in enumerate(steps):
+            ctx.set_state(ep2, beta2)
+            _ep.ep_profile_read(ctx.h, "assembly")
             st, info = _ep.ep_newton_step(ctx.h, ctx.tensor(f), ctx.tensor(uu))
             assert info["n_plastic_elem"] == n_el, k
+            count = _ep.ep_profile_read(ctx.h, "assembly")[1]
+            if launches is None:
+                assert count > 2, (k, count)
+            else:
+                assert count == launches, (k, count)
             ref = O.constitutive(mat, O.strain(mesh, dphi, uu), O.state_to_ip6(ep2, 3),
                                  O.state_to_ip6(beta2, 3))
             _, _, Kt = O.assemble(mesh, dphi, w, ref["D"], rp, ci)
@@ -414,5 +438,6 @@ def test_short_lists_alternate_with_colour_rounds(values):
             else:
                 _row_scaled_close(_np(ctx.csr(1)[2]).astype(np.float64), Kt, rp,
                                   np.maximum(np.abs(Kt), np.abs(Ke)), tol=tol)
+        _ep.ep_profile(ctx.h, 0)
     finally:
         ctx.close()
