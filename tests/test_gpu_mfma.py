@@ -97,3 +97,46 @@ def test_fused_rows_refuse_reduced_local_precision():
     with pytest.raises(_ep.EpError):
         _ep.Context(mesh, np.ones(mesh.n_dof, np.uint8), W.VM_MATERIAL,
                     options={"local_prec": _ep.EP_FP32, "assembly": _ep.EP_ASSEMBLY_FUSED})
+
+
+@pytest.mark.parametrize("case", ["q2_3d_dph", "p2_3d_dph"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_matrix_core_products_through_the_row_route(case, prec):
+    """Colour mode inside Newton steps with matrix-core products: a work
+    list that fits the element-matrix buffer (every list of these small
+    meshes) goes through the matrix-core element matrices, stored at the
+    elements' work-list positions, and the node-row gather (two launches);
+    K_tangent equals the oracle's at each step's displacement to the
+    per-entry bound, over steps whose plastic sets differ."""
+    mesh, free, mat, u, (ep, beta, kappa) = make_case(case)
+    ctx = _ep.Context(mesh, free, mat, options={
+        "local_prec": _ep.EP_FP32 if prec == "fp32" else _ep.EP_BF16})
+    try:
+        ctx.set_state(ep, None, kappa)
+        _, _, Ke = ctx.csr(0)
+        Ke = _np(Ke)
+        dphi, w = O.geometry(mesh)
+        pat = O.pattern(mesh)
+        rows = np.repeat(np.arange(mesh.n_dof), np.diff(pat[0]))
+        f = np.zeros(mesh.n_dof)
+        f[-1] = 1e-9  # a nonzero load: the step is not converged
+        _ep.ep_profile(ctx.h, True, ["assembly"])
+        errs, listed = [], []
+        for s in (1.0, 0.1, 1.0, 0.02):
+            _ep.ep_profile_read(ctx.h, "assembly")
+            st, info = _ep.ep_newton_step(ctx.h, ctx.tensor(f), ctx.tensor(u * s))
+            assert _ep.ep_profile_read(ctx.h, "assembly")[1] == 2, s
+            listed.append(info["n_plastic_elem"])
+            _, _, val = ctx.csr(1)
+            ref = O.constitutive(mat, O.strain(mesh, dphi, u * s), O.state_to_ip6(ep, 3), None,
+                                 kappa)
+            _, _, Kt = O.assemble(mesh, dphi, w, ref["D"], *pat)
+            scale = np.zeros(mesh.n_dof)
+            np.maximum.at(scale, rows, np.maximum(np.abs(Kt), np.abs(Ke)))
+            errs.append((np.abs(_np(val) - Kt) / scale[rows]).max())
+        _ep.ep_profile(ctx.h, 0)
+        assert min(listed) > 0 and len(set(listed)) > 1, listed
+        assert max(errs) <= TOL[prec], errs
+        assert max(errs) > 0
+    finally:
+        ctx.close()
