@@ -785,7 +785,7 @@ ep_status ep_setup(const ep_mesh *mesh, const ep_quadrature *quad, const ep_mate
   MeshGraph gr;
   {
     const std::string why = build_mesh_graph(n_n, n_e, n_p, dim, mesh->elem, sorted_scatter,
-                                             CMP_CHUNK, 512, gr);
+                                             CMP_CHUNK, CMP_MAX_COLOURS, gr);
     if (!why.empty()) return fail("ep_setup: " + why, EP_EINVAL);
   }
 

@@ -38,6 +38,9 @@ struct MatC {
 constexpr int CMP_THREADS = 256;
 constexpr int CMP_ITEMS = 8;
 constexpr int CMP_CHUNK = CMP_THREADS * CMP_ITEMS;
+// most element colours a mesh may need (the compaction keeps a count per
+// colour in LDS)
+constexpr int CMP_MAX_COLOURS = 512;
 // colour-round assembly: work lists of at most this many (element, node,
 // point) triples (listed elements x n_p x n_q) go through the fused row pass
 constexpr int64_t SHORT_LIST_WORK = 4096;

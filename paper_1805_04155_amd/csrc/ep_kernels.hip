@@ -2050,6 +2050,7 @@ __global__ __launch_bounds__(CMP_THREADS) void k_compact_scatter(
     int32_t *out) {
   __shared__ int32_t s_w[CMP_THREADS / 64];
   __shared__ int32_t s_r[3][CMP_THREADS];
+  __shared__ int32_t s_cfb[CMP_MAX_COLOURS + 1], s_cc[CMP_MAX_COLOURS + 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t base = (int64_t)blockIdx.x * CMP_CHUNK;
   // this thread's items first (their loads overlap the offset reduction)
@@ -2088,17 +2089,32 @@ __global__ __launch_bounds__(CMP_THREADS) void k_compact_scatter(
       totals[1] = s_r[1][0];
       totals[2] = s_r[2][0];
     }
-    if (colour_off)
+    if (colour_off) {
+      // each block of the colour-major order lies in one colour (every
+      // colour is padded to whole blocks): the selected counts summed per
+      // colour (integer sums: exact in any order), then the offsets in
+      // colour order
       for (int c = tid; c <= n_col; c += CMP_THREADS) {
-        const int fb = colour_first_block[c];
-        int32_t off = 0;
-        if (fb >= nblk) {
-          off = total;
-        } else {
-          for (int j = 0; j < fb; ++j) off += counts[j];
+        s_cfb[c] = colour_first_block[c];
+        s_cc[c] = 0;
+      }
+      __syncthreads();
+      for (int j = tid; j < nblk; j += CMP_THREADS) {
+        int lo = 0, hi = n_col - 1;  // the last colour whose first block is <= j
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) / 2;
+          if (s_cfb[mid] <= j) lo = mid;
+          else hi = mid - 1;
         }
+        atomicAdd(&s_cc[lo], counts[j]);
+      }
+      __syncthreads();
+      for (int c = tid; c <= n_col; c += CMP_THREADS) {
+        int32_t off = 0;
+        for (int k = 0; k < c; ++k) off += s_cc[k];
         colour_off[c] = off;
       }
+    }
   }
 #pragma unroll
   for (int k = 0; k < CMP_ITEMS; ++k) {
