@@ -29,22 +29,50 @@ static inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b)
 
 // Per-thread part of a one-block reduction of n partial results:
 // sum over b = t, t + nt, t + 2 nt, ... < n of p[b * stride] in increasing
-// b.  The loads of 16 strides are issued together (the reduction kernels run
-// as a single block, so their time is load latency); the additions keep the
-// stride order.
+// b.  The loads of U strides are issued together, the last group masked
+// (a reduction kernel that runs as a single block takes as long as its
+// rounds of load latency; U = 16 where many blocks repeat the sum); the
+// additions keep the stride order, so U does not change the result.
+template <int U = 16>
 __device__ inline double strided_sum(const double *p, int n, int stride, int t, int nt) {
-  constexpr int U = 16;
   double v = 0.0;
-  int b = t;
-  for (; b + (U - 1) * nt < n; b += U * nt) {
+  for (int b = t; b < n; b += U * nt) {
     double x[U];
 #pragma unroll
-    for (int j = 0; j < U; ++j) x[j] = p[(int64_t)(b + j * nt) * stride];
+    for (int j = 0; j < U; ++j) {
+      const int bj = b + j * nt;
+      x[j] = bj < n ? p[(int64_t)bj * stride] : 0.0;
+    }
 #pragma unroll
-    for (int j = 0; j < U; ++j) v += x[j];
+    for (int j = 0; j < U; ++j)
+      if (b + j * nt < n) v += x[j];
   }
-  for (; b < n; b += nt) v += p[(int64_t)b * stride];
   return v;
+}
+
+// Both sums of interleaved pairs (p[2b], p[2b + 1]) in one pass, each as
+// strided_sum would form it.
+template <int U>
+__device__ inline void strided_sum_pairs(const double *p, int n, int t, int nt, double &sa,
+                                         double &sb) {
+  double va = 0.0, vb = 0.0;
+  for (int b = t; b < n; b += U * nt) {
+    double x[U], y[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int bj = b + j * nt;
+      x[j] = bj < n ? p[2 * (int64_t)bj] : 0.0;
+      y[j] = bj < n ? p[2 * (int64_t)bj + 1] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+      if (b + j * nt < n) {
+        va += x[j];
+        vb += y[j];
+      }
+  }
+  sa = va;
+  sb = vb;
 }
 
 // ----------------------------------------------------------------------------
@@ -1636,7 +1664,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double *partials, int nblk
   __shared__ double s[256];
   const int tid = threadIdx.x;
   for (int c = 0; c < width; ++c) {
-    s[tid] = strided_sum(partials + c, nblk, width, tid, 256);
+    s[tid] = strided_sum<32>(partials + c, nblk, width, tid, 256);
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
       if (tid < h) s[tid] += s[tid + h];
@@ -2263,7 +2291,7 @@ __global__ __launch_bounds__(256) void k_pcg_alpha(const double *partials, int n
   __shared__ double s[256];
   if (sc[SC_DONE] != 0.0) return;
   const int tid = threadIdx.x;
-  s[tid] = strided_sum(partials, nblk, 1, tid, 256);
+  s[tid] = strided_sum<32>(partials, nblk, 1, tid, 256);
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
     if (tid < h) s[tid] += s[tid + h];
@@ -2336,8 +2364,7 @@ __global__ __launch_bounds__(256) void k_pcg_beta(const double *partials, int nb
   __shared__ double sa[256], sb[256];
   if (!init && sc[SC_DONE] != 0.0) return;
   const int tid = threadIdx.x;
-  sa[tid] = strided_sum(partials, nblk, 2, tid, 256);
-  sb[tid] = strided_sum(partials + 1, nblk, 2, tid, 256);
+  strided_sum_pairs<32>(partials, nblk, tid, 256, sa[tid], sb[tid]);
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
     if (tid < h) {
