@@ -48,7 +48,7 @@ def _oracle(mesh, mat, u):
     dphi, w = O.geometry(mesh)
     n = mesh.n_int
     z = np.zeros((n, 6))
-    ref = O.constitutive(mat, O.strain(mesh, dphi, u), z, z, np.zeros(n))
+    ref = O.constitutive(mat, O.strain(mesh, dphi, u), z, z, np.zeros(n), crit=True)
     rp, ci = O.pattern(mesh)
     _, _, K = O.assemble(mesh, dphi, w, ref["D"], rp, ci)
     F = O.internal_force(mesh, dphi, w, ref["sig"])
@@ -80,6 +80,7 @@ def test_smallest_mesh(name, matname, amp, mode):
         "assembly": _ep.ASSEMBLY[mode]})
     try:
         sig, _, flag = ctx.constitutive(ctx.tensor(u), D=False)
+        assert not O.tie_band(mat, ref["crit"]).any()  # exact branch decisions are meaningful
         assert np.array_equal(_np(flag), ref["flag"])
         ip, el = ctx.plastic()
         pl = np.nonzero(ref["flag"])[0]

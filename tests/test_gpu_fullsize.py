@@ -53,7 +53,8 @@ def _oracle_points(f, elems):
     ips = (elems[:, None] * mesh.n_q + np.arange(mesh.n_q)).ravel()
     ep6 = O.state_to_ip6(f["ep"][:, ips], mesh.dim)
     beta6 = O.state_to_ip6(f["beta"][:, ips], mesh.dim)
-    return ips, O.constitutive(f["mat"], eps, ep6, beta6, f["kappa"][ips]), dphi, w, sub
+    return (ips, O.constitutive(f["mat"], eps, ep6, beta6, f["kappa"][ips], crit=True), dphi, w,
+            sub)
 
 
 def test_points_sampled(full):
@@ -61,7 +62,10 @@ def test_points_sampled(full):
     rng = np.random.default_rng(7)
     elems = np.sort(rng.choice(mesh.n_elems, size=min(3000, mesh.n_elems), replace=False))
     ips, ref, _, _, _ = _oracle_points(full, elems)
-    assert np.array_equal(full["flag"][ips], ref["flag"])
+    # exact outside the tie band of the yield tests, which is empty here
+    band = O.tie_band(full["mat"], ref["crit"])
+    assert np.array_equal(full["flag"][ips][~band], ref["flag"][~band])
+    assert not band.any(), f"{int(band.sum())} sampled points in the tie band"
     d = mesh.dim
     sig = full["sig"][:, ips].T
     rs = ref["sig"] if d == 3 else ref["sig"][:, :4]

@@ -45,7 +45,8 @@ class Case:
         eps = O.strain(self.mesh, self.dphi, u)
         return O.constitutive(self.mat, eps, O.state_to_ip6(self.ep, self.dim),
                               O.state_to_ip6(self.beta, self.dim),
-                              self.kappa if self.mat.model == "DP" else np.zeros(self.mesh.n_int))
+                              self.kappa if self.mat.model == "DP" else np.zeros(self.mesh.n_int),
+                              crit=True)
 
     def du(self):
         return self.ctx.tensor(self.u)
@@ -110,7 +111,12 @@ def test_strain(case):
 def test_return_map_and_tangent(case):
     sig, D, flag = case.ctx.constitutive(case.du())
     ref = case.oracle_const(case.u)
-    assert np.array_equal(_np(flag), ref["flag"])
+    # the branch decisions agree bit for bit outside the tie band of the
+    # yield tests (|CRIT| < 1e-12 Y or c), where two roundings may differ;
+    # on these seeded inputs the band is empty
+    band = O.tie_band(case.mat, ref["crit"])
+    assert np.array_equal(_np(flag)[~band], ref["flag"][~band])
+    assert not band.any(), f"{int(band.sum())} points in the tie band"
     close(_voigt_from_soa(_np(sig), case.dim), ref["sig"])
     n = case.mesh.n_int
     Dg = _np(D).T.reshape(n, case.ctx.sizes["n_str"], case.ctx.sizes["n_str"])
